@@ -1,0 +1,368 @@
+"""Pins for the CPU oracle: checks against what the paper and mathematics fix,
+never against the oracle itself.
+
+* published SplitMix64 outputs (the clique hash's key function);
+* the paper's worked example (Section II-A, Fig. 1(a));
+* brute-force subset enumeration from the definition of a maximal clique,
+  exhaustively on every graph with at most 5 vertices and on all 32,768
+  labelled graphs on 6 vertices, and on random graphs of up to 20 vertices;
+* Algorithm 1 (no pivot, no first-level split) on random graphs;
+* closed forms (complete, empty, Moon-Moser, multipartite, cocktail party,
+  cycle, path, star, triangle-free, disjoint unions, overlapping cliques, the
+  Moon-Moser upper bound);
+* networkx's independent ``find_cliques`` and ``core_number``;
+* invariants of the output (clique, maximal, no duplicates, every edge covered).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_01473_amd import inputs as I
+from conftest import read_golden_lines
+
+MASK64 = (1 << 64) - 1
+
+
+def _full(g):
+    return oracle.mce(g, collect=True)
+
+
+def _hist_dict(h):
+    return {k: int(v) for k, v in enumerate(h) if v}
+
+
+# ---------------------------------------------------------------- hash
+
+def test_key_matches_published_splitmix64_outputs():
+    expected = [int(x, 16) for x in read_golden_lines("splitmix64_seed0.txt")]
+    assert [oracle.key(v) for v in range(len(expected))] == expected
+
+
+def test_hash_is_additive_over_disjoint_unions():
+    a, b = I.moon_moser(3), I.cycle_graph(7)
+    ra, rb = oracle.mce(a), oracle.mce(b)
+    u = I.disjoint_union([a, b])
+    ru = _full(u)
+    assert ru.count == ra.count + rb.count
+    # the union relabels b's vertices, so recompute from the explicit cliques
+    cnt, hist, h = oracle.summarize(ru.cliques)
+    assert (cnt, h) == (ru.count, ru.hash)
+    assert ra.hash == oracle.summarize(_full(a).cliques)[2]
+
+
+def test_hash_distinguishes_duplicates_from_cancellation():
+    # a sum (not xor) of clique hashes: the same clique twice does not cancel
+    h = oracle.clique_hash((0, 1, 2))
+    assert (2 * h) & MASK64 != 0
+
+
+# ---------------------------------------------------------------- worked example
+
+def test_fig1a_example():
+    g = I.fig1a_example()
+    expected = sorted(tuple(int(x) for x in ln.split()) for ln in read_golden_lines("fig1a.txt"))
+    r = _full(g)
+    assert sorted(r.cliques) == expected
+    assert r.count == 2
+    assert _hist_dict(r.hist) == {3: 1, 4: 1}
+    assert int(g.degrees()[0]) == 5
+    # degeneracy of the example is 3 (ABCD is a 4-clique, E and F have degree 2)
+    assert r.degeneracy == 3
+
+
+# ---------------------------------------------------------------- brute force
+
+def _brute_masks_all_graphs(n):
+    """Maximal cliques of every labelled graph on n vertices at once, straight
+    from the definition; returns {graph_mask: sorted list of subset masks}."""
+    pairs = list(itertools.combinations(range(n), 2))
+    G = np.arange(1 << len(pairs), dtype=np.int64)
+    adj = np.zeros((G.size, n), dtype=np.int64)
+    for k, (i, j) in enumerate(pairs):
+        bit = (G >> k) & 1
+        adj[:, i] |= bit << j
+        adj[:, j] |= bit << i
+    S = np.arange(1, 1 << n, dtype=np.int64)
+    clique = np.ones((G.size, S.size), dtype=bool)
+    for i in range(n):
+        has_i = ((S >> i) & 1 == 1)[None, :]
+        others = (S & ~(1 << i))[None, :]
+        clique &= ~has_i | ((others & ~adj[:, i:i + 1]) == 0)
+    ext = np.zeros_like(clique)
+    for j in range(n):
+        not_in = ((S >> j) & 1 == 0)[None, :]
+        ext |= not_in & ((S[None, :] & ~adj[:, j:j + 1]) == 0)
+    maxi = clique & ~ext
+    return G, S, maxi, pairs
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_exhaustive_small_graphs_vs_brute_force(n):
+    G, S, maxi, pairs = _brute_masks_all_graphs(n)
+    iu = np.array([p[0] for p in pairs], dtype=np.int64)
+    ju = np.array([p[1] for p in pairs], dtype=np.int64)
+    for gi in range(G.size):
+        bits = ((G[gi] >> np.arange(len(pairs))) & 1).astype(bool)
+        g = I.from_edges(n, iu[bits], ju[bits])
+        r = oracle.mce(g, collect=True)
+        got = sorted(sum(1 << v for v in c) for c in r.cliques)
+        exp = sorted(int(s) for s in S[maxi[gi]])
+        assert got == exp, (n, gi)
+        assert r.count == len(exp)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_graphs_vs_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(7, 21))
+    p = float(rng.choice([0.1, 0.3, 0.5, 0.7, 0.9]))
+    g = I.erdos_renyi(n, p, 5000 + seed)
+    exp = sorted(oracle.brute_force(g))
+    r = _full(g)
+    assert sorted(r.cliques) == exp
+    cnt, hist, h = oracle.summarize(exp)
+    assert (r.count, r.hash) == (cnt, h)
+    assert _hist_dict(r.hist) == _hist_dict(hist)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_graphs_vs_algorithm1(seed):
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(10, 40))
+    p = float(rng.uniform(0.1, 0.6))
+    g = I.erdos_renyi(n, p, 7000 + seed)
+    exp = sorted(oracle.bk_no_pivot(g))
+    assert sorted(_full(g).cliques) == exp
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 40])
+def test_complete_graph(n):
+    r = oracle.mce(I.complete_graph(n))
+    assert r.count == 1 and _hist_dict(r.hist) == {n: 1}
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 17])
+def test_empty_graph(n):
+    r = oracle.mce(I.empty_graph(n))
+    assert r.count == n
+    if n:
+        assert _hist_dict(r.hist) == {1: n}
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8])
+def test_moon_moser(k):
+    r = oracle.mce(I.moon_moser(k))
+    assert r.count == 3 ** k and _hist_dict(r.hist) == {k: 3 ** k}
+
+
+@pytest.mark.parametrize("sizes", [[1, 2, 3], [2, 2, 5, 1], [4, 3], [7]])
+def test_complete_multipartite(sizes):
+    r = oracle.mce(I.complete_multipartite(sizes))
+    assert r.count == math.prod(sizes)
+    assert _hist_dict(r.hist) == {len(sizes): math.prod(sizes)}
+
+
+@pytest.mark.parametrize("k", [1, 3, 6, 9])
+def test_cocktail_party(k):
+    assert oracle.mce(I.cocktail_party(k)).count == 2 ** k
+
+
+@pytest.mark.parametrize("n", [4, 5, 10, 101])
+def test_cycle(n):
+    r = oracle.mce(I.cycle_graph(n))
+    assert r.count == n and _hist_dict(r.hist) == {2: n}
+
+
+def test_triangle():
+    assert _hist_dict(oracle.mce(I.cycle_graph(3)).hist) == {3: 1}
+
+
+@pytest.mark.parametrize("n", [2, 3, 9, 50])
+def test_path(n):
+    assert oracle.mce(I.path_graph(n)).count == n - 1
+
+
+@pytest.mark.parametrize("m", [1, 2, 30])
+def test_star(m):
+    assert oracle.mce(I.star_graph(m)).count == m
+
+
+def test_triangle_free_bipartite():
+    rng = np.random.default_rng(7)
+    a, b = 40, 60
+    s = rng.integers(0, a, 300)
+    t = rng.integers(a, a + b, 300)
+    g = I.from_edges(a + b, s, t)
+    iso = int((g.degrees() == 0).sum())
+    r = oracle.mce(g)
+    assert r.count == g.m + iso
+
+
+@pytest.mark.parametrize("s,t", [(5, 2), (8, 7), (4, 0), (10, 3)])
+def test_two_overlapping_cliques(s, t):
+    n = 2 * s - t
+    A = list(range(s))
+    B = list(range(s - t, n))
+    e = [(u, v) for S in (A, B) for u, v in itertools.combinations(S, 2)]
+    g = I.from_edges(n, [x for x, _ in e], [y for _, y in e])
+    r = oracle.mce(g)
+    assert r.count == 2 and _hist_dict(r.hist) == {s: 2}
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_moon_moser_upper_bound(seed):
+    n = 12 + seed
+    g = I.erdos_renyi(n, 0.6, 300 + seed)
+    bound = {0: 3 ** (n // 3), 1: 4 * 3 ** ((n - 4) // 3), 2: 2 * 3 ** ((n - 2) // 3)}[n % 3]
+    assert oracle.mce(g).count <= bound
+
+
+def test_disjoint_union_adds():
+    parts = [I.moon_moser(2), I.complete_graph(5), I.cycle_graph(6), I.empty_graph(3)]
+    r = oracle.mce(I.disjoint_union(parts))
+    assert r.count == 9 + 1 + 6 + 3
+
+
+# ---------------------------------------------------------------- networkx cross-check
+
+nx = pytest.importorskip("networkx")
+
+
+def _nx_graph(g):
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    G.add_edges_from(map(tuple, g.edges().tolist()))
+    return G
+
+
+def _nx_summary(G, keep=lambda c: True):
+    cnt, hist, h = 0, {}, 0
+    for c in nx.find_cliques(G):
+        if not keep(c):
+            continue
+        cnt += 1
+        hist[len(c)] = hist.get(len(c), 0) + 1
+        h = (h + oracle.clique_hash(c)) & MASK64
+    return cnt, hist, h
+
+
+def test_er1000_vs_networkx():
+    g = I.erdos_renyi(1000, 0.02, 1)
+    r = oracle.mce(g)
+    cnt, hist, h = _nx_summary(_nx_graph(g))
+    assert (r.count, _hist_dict(r.hist), r.hash) == (cnt, hist, h)
+
+
+@pytest.mark.parametrize("scale", [9, 11])
+def test_rmat_vs_networkx(scale):
+    g = I.rmat(scale, 16, 0.57, 0.19, 0.19, 0.05, 40 + scale)
+    r = oracle.mce(g)
+    cnt, hist, h = _nx_summary(_nx_graph(g))
+    assert (r.count, _hist_dict(r.hist), r.hash) == (cnt, hist, h)
+
+
+def test_core_numbers_vs_networkx():
+    g = I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 77)
+    G = _nx_graph(g)
+    cn = nx.core_number(G)
+    exp = np.array([cn[v] for v in range(g.n)], dtype=np.uint32)
+    order, core = oracle.degeneracy(g)
+    assert (core == exp).all()
+    core2, rnd, nr = oracle.sync_peel(g)
+    assert (core2 == exp).all()
+
+
+def _later_degree(g, order):
+    pos = np.empty(g.n, dtype=np.int64)
+    pos[order] = np.arange(g.n)
+    deg = g.degrees()
+    src = np.repeat(np.arange(g.n), deg)
+    later = pos[g.col_idx.astype(np.int64)] > pos[src]
+    return np.bincount(src[later], minlength=g.n)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_orders_are_degeneracy_orders(seed):
+    g = I.rmat(11, 12, 0.57, 0.19, 0.19, 0.05, 90 + seed)
+    order, core = oracle.degeneracy(g)
+    assert (np.diff(core[order].astype(np.int64)) >= 0).all()
+    assert (_later_degree(g, order) <= core).all()
+    sorder, rank = oracle.sync_order(g)
+    c2, _, _ = oracle.sync_peel(g)
+    assert (np.diff(c2[sorder].astype(np.int64)) >= 0).all()
+    assert (_later_degree(g, sorder) <= c2).all()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sync_peel_rounds_satisfy_definition(seed):
+    """Every round removes exactly the remaining vertices whose remaining
+    degree is at most the current level k (checked as a fixed-point property
+    of the returned arrays, not by re-running the peel)."""
+    g = I.rmat(10, 10, 0.57, 0.19, 0.19, 0.05, 200 + seed)
+    core, rnd, nr = oracle.sync_peel(g)
+    deg = g.degrees()
+    src = np.repeat(np.arange(g.n), deg)
+    dst = g.col_idx.astype(np.int64)
+    assert int(rnd.max()) + 1 == nr
+    for r in range(nr):
+        alive = rnd >= r
+        removed = rnd == r
+        k = int(core[removed][0])
+        assert (core[removed] == k).all()
+        d_alive = np.bincount(src[alive[src] & alive[dst]], minlength=g.n)
+        assert (d_alive[removed] <= k).all()
+        survivors = alive & ~removed
+        assert (d_alive[survivors] > k).all()
+
+
+# ---------------------------------------------------------------- core window
+
+@pytest.mark.parametrize("scale", [10, 12])
+def test_core_window_equals_filter_on_min_core(scale):
+    g = I.rmat(scale, 16, 0.57, 0.19, 0.19, 0.05, 300 + scale)
+    G = _nx_graph(g)
+    cn = nx.core_number(G)
+    d = max(cn.values())
+    for c in (0, 1, d // 2, d - 1, d):
+        r = oracle.mce(g, max_root_core=c)
+        cnt, hist, h = _nx_summary(G, keep=lambda C: min(cn[v] for v in C) <= c)
+        assert (r.count, _hist_dict(r.hist), r.hash) == (cnt, hist, h), c
+
+
+# ---------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("seed", range(4))
+def test_output_invariants(seed):
+    g = I.chung_lu_planted(n=600, wmax=80, n_cliques=6, cmin=5, cmax=9, pool=60, seed=seed)
+    r = _full(g)
+    nbr = [set(map(int, g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]])) for v in range(g.n)]
+    seen = set()
+    covered = set()
+    for c in r.cliques:
+        assert c not in seen
+        seen.add(c)
+        for u, v in itertools.combinations(c, 2):
+            assert v in nbr[u]
+            covered.add((u, v))
+        common = set.intersection(*(nbr[v] for v in c)) if c else set()
+        assert not (common - set(c))
+    assert len(covered) == g.m
+    assert sum(int(x) for x in r.hist) == r.count
+    # relabelling invariance of count and histogram
+    perm = np.random.default_rng(seed).permutation(g.n)
+    e = g.edges()
+    g2 = I.from_edges(g.n, perm[e[:, 0]], perm[e[:, 1]])
+    r2 = oracle.mce(g2)
+    assert r2.count == r.count and _hist_dict(r2.hist) == _hist_dict(r.hist)
+
+
+def test_threads_do_not_change_results():
+    g = I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 11)
+    a = oracle.mce(g, threads=1)
+    b = oracle.mce(g, threads=0)
+    assert (a.count, a.hash, _hist_dict(a.hist)) == (b.count, b.hash, _hist_dict(b.hist))
