@@ -1,0 +1,228 @@
+/*
+ * mce.h -- exact maximal clique enumeration on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper: "Parallelizing Maximal Clique Enumeration on GPUs",
+ * Section II-A): for a simple undirected graph G, enumerate every maximal
+ * clique -- a vertex set that is pairwise adjacent and is contained in no
+ * larger such set -- exactly, with no approximation.  The library returns the
+ * number of maximal cliques, their histogram by size, an order-independent
+ * 64-bit hash of the set of cliques, and optionally the cliques themselves.
+ *
+ * The method (Sections II-B..II-D and III): Bron-Kerbosch with Tomita
+ * pivoting (Algorithm 2) over independent first-level subtrees (Algorithm 3)
+ * in a degeneracy order; each subtree is explored depth-first by one
+ * wavefront over a partial induced subgraph (Section III-D) held as bitmaps,
+ * with the compact excluded-set representation of Section III-E and the
+ * worker list of Section III-C for load balancing.
+ *
+ * Clique hash (a fixed definition, not from the paper): fmix is the
+ * SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014),
+ * gamma = 0x9E3779B97F4A7C15, key(v) = fmix((v + 1) * gamma) for input vertex
+ * id v, h(C) = fmix(sum_{v in C} key(v) + |C| * gamma), and the reported hash
+ * is the sum of h(C) over all reported cliques, modulo 2^64.
+ *
+ * Core window: with max_root_core = c the library reports exactly the maximal
+ * cliques whose smallest core number is <= c (all of them when c >= the
+ * degeneracy).  Isolated vertices are maximal cliques of size 1.
+ *
+ * Conventions for every entry point:
+ *   - every function returns mce_status; nothing throws or aborts across the ABI;
+ *   - on error a thread-local message is available from mce_last_error();
+ *   - pointers documented as "device" must be device (HBM) memory of the
+ *     current HIP device; "host" pointers are ordinary host memory;
+ *   - the library never takes ownership of caller memory.
+ */
+#ifndef MCE_H
+#define MCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCE_OK = 0,
+    MCE_WARN_STREAM_TRUNCATED = 1,   /* clique stream buffer full; totals still exact */
+    MCE_ERR_INVALID_ARG = -1,        /* NULL pointer, bad struct_size, bad option */
+    MCE_ERR_INVALID_GRAPH = -2,      /* CSR violates the graph rules below */
+    MCE_ERR_OUT_OF_MEMORY = -3,      /* device allocation failed */
+    MCE_ERR_DEVICE = -4,             /* HIP runtime error or no usable device */
+    MCE_ERR_BUFFER_TOO_SMALL = -5,   /* hist shorter than max_clique_size + 1 */
+    MCE_ERR_TIMEOUT = -6,            /* enumeration exceeded timeout_ms; results invalid */
+    MCE_ERR_UNSUPPORTED = -7         /* graph exceeds a built-in limit (see mce_graph_info) */
+} mce_status;
+
+/* Opaque graph handle: library-owned device state (oriented CSR in degeneracy
+ * order, core numbers, per-vertex keys, enumeration scratch). */
+typedef struct mce_graph mce_graph;
+
+typedef struct {
+    uint32_t n;              /* vertices */
+    uint64_t nnz;            /* stored arcs (2 x edges) */
+    uint32_t max_degree;     /* Delta */
+    uint32_t degeneracy;     /* d = largest core number */
+    uint64_t n_isolated;     /* vertices of degree 0 */
+    uint32_t peel_rounds;    /* rounds of the synchronous peel */
+    uint32_t max_out_degree; /* largest |P| of a first-level subtree (<= d) */
+    uint32_t max_in_degree;  /* largest |X| of a first-level subtree (<= Delta) */
+    uint32_t n_graphs;       /* graphs in the handle (1 unless batch-loaded) */
+} mce_graph_info;
+
+/* ---- load flags */
+#define MCE_LOAD_DEVICE_PTRS 0x1u  /* row_ptr/col_idx are device pointers */
+#define MCE_LOAD_NO_VALIDATE 0x2u  /* skip the graph-rule checks (caller vouches) */
+
+/*
+ * Load an undirected simple graph given as CSR with both arc directions stored
+ * (Section III-D: the original graph is kept in CSR form).
+ *
+ * row_ptr: uint32[n+1]; col_idx: uint32[nnz].  Graph rules: row_ptr[0] = 0,
+ * row_ptr non-decreasing, row_ptr[n] = nnz, every col < n, each row strictly
+ * increasing (sorted, no duplicates), no self-loops, symmetric.  Any violation
+ * gives MCE_ERR_INVALID_GRAPH and mce_last_error() names the first offending
+ * row and position.
+ *
+ * The arrays are only read during the call (copied to the device when they are
+ * host pointers; read in place with MCE_LOAD_DEVICE_PTRS) and never retained.
+ * Loading computes the synchronous-round peel (core numbers; vertices ordered
+ * by (core, round, id)), and orients every row into the later (P) and earlier
+ * (X) neighbour lists of Algorithm 3.  stream: hipStream_t or NULL (default
+ * stream); the call synchronises before returning.  *out receives a handle to
+ * release with mce_free().
+ */
+mce_status mce_load_csr(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n,
+                        uint64_t nnz, uint32_t flags, void* stream, mce_graph** out);
+
+/*
+ * Load n_graphs independent graphs for batched enumeration.  row_ptr_cat holds
+ * each graph's row_ptr (starting at 0, length n_i + 1) end to end; col_idx_cat
+ * holds each graph's col_idx end to end.  row_off[i] / col_off[i] (uint64,
+ * length n_graphs + 1, host memory) give where graph i starts in each array,
+ * so n_i = row_off[i+1] - row_off[i] - 1 and nnz_i = col_off[i+1] - col_off[i].
+ * Every graph obeys the rules of mce_load_csr.  Vertex ids in results are
+ * per-graph input ids.  Same flags, ownership and stream rules.
+ */
+mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_idx_cat,
+                              const uint64_t* row_off, const uint64_t* col_off,
+                              uint32_t n_graphs, uint32_t flags, void* stream, mce_graph** out);
+
+/* Describe graph graph_idx of the handle (0 for a single graph). */
+mce_status mce_graph_get_info(const mce_graph* g, uint32_t graph_idx, mce_graph_info* out);
+
+/*
+ * Copy the degeneracy data of graph graph_idx to caller-owned host arrays of
+ * n entries each (any may be NULL): core[v] = core number of input vertex v,
+ * peel_round[v] = round of the synchronous peel that removed v (Section II-D;
+ * round r removes every remaining vertex whose remaining degree is at most the
+ * current level k, and the level rises to the minimum remaining degree when
+ * no vertex qualifies), order[i] = input id of the i-th vertex of the
+ * degeneracy order (sorted by round, then id).
+ */
+mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t* core, uint32_t* peel_round,
+                                uint32_t* order);
+
+/* ---- enumeration flags */
+#define MCE_F_WORKER_LIST   0x01u  /* donate branches to idle wavefronts (Section III-C) */
+#define MCE_F_LEARNED_ORDER 0x02u  /* order roots by the cost model in opt->model */
+#define MCE_F_SPLIT         0x04u  /* split the costliest roots into level-1 branch tasks */
+#define MCE_F_STATS         0x08u  /* fill mce_result.stats */
+#define MCE_F_STREAM        0x10u  /* write cliques to the stream buffers */
+#define MCE_F_ROOT_STATS    0x20u  /* per-root counters into opt->root_* (device arrays) */
+#define MCE_F_REVERSE_ORDER 0x40u  /* process roots in reverse degeneracy order */
+#define MCE_F_CUSTOM_ORDER  0x80u  /* process roots in the order given by opt->root_order */
+
+#define MCE_OPTIONS_VERSION 1u
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(mce_options) */
+    uint32_t flags;             /* MCE_F_* */
+    uint32_t max_root_core;     /* core window c; UINT32_MAX = full enumeration */
+    uint32_t wg_per_cu;         /* persistent workgroups per compute unit; 0 = occupancy limit */
+    uint32_t bitmap_max_p;      /* largest subtree universe whose bitmap rows live in LDS;
+                                   larger ones use HBM rows; 0 = default */
+    uint32_t donate_min_p;      /* donate a branch only if its |P| >= this; 0 = 10 (Section III-C) */
+    uint32_t donate_max_depth;  /* donate only at depth <= this; 0 = unlimited */
+    uint32_t split_top;         /* MCE_F_SPLIT: number of costliest roots to split; 0 = auto */
+    const void* model;          /* MCE_F_LEARNED_ORDER: device pointer to mce_model weights */
+    void* stream;               /* hipStream_t or NULL */
+    uint64_t timeout_ms;        /* watchdog; 0 = 600000 */
+    const uint32_t* root_order; /* MCE_F_CUSTOM_ORDER: device uint32[n], a permutation of input ids */
+    uint64_t* root_count;       /* MCE_F_ROOT_STATS: device uint64[n] by input id, accumulated into */
+    uint64_t* root_hash;        /* MCE_F_ROOT_STATS: device uint64[n] */
+    uint64_t* root_nodes;       /* MCE_F_ROOT_STATS: device uint64[n] (search-tree nodes) */
+} mce_options;
+
+/* indices into mce_result.stats */
+enum {
+    MCE_STAT_NODES = 0,        /* search-tree nodes expanded */
+    MCE_STAT_DONATIONS = 1,    /* branches handed to idle workgroups */
+    MCE_STAT_TASKS = 2,        /* tasks run (roots + donated + split) */
+    MCE_STAT_ROOTS = 3,        /* first-level subtrees in the window with |P| > 0 */
+    MCE_STAT_WORKGROUPS = 4,   /* persistent workgroups launched */
+    MCE_STAT_KERNEL_NS = 5,    /* enumeration kernel time (ns) */
+    MCE_STAT_SETUP_NS = 6,     /* root-queue setup time (ns) */
+    MCE_STAT_XTESTS = 7,       /* X_X adjacency tests */
+    MCE_STAT_BUILD_EDGES = 8,  /* adjacency entries scanned to build bitmaps */
+    MCE_STAT_HBM_ROWS = 9,     /* tasks whose bitmap rows lived in HBM */
+    MCE_STAT_IDLE_NS = 10,     /* summed workgroup idle time in the worker list (ns) */
+    MCE_STAT_LDS_BYTES = 11    /* LDS bytes per workgroup */
+};
+
+typedef struct {
+    uint64_t count;                   /* out: number of maximal cliques */
+    uint64_t hash;                    /* out: sum of h(C) mod 2^64 */
+    uint32_t max_clique_size;         /* out: largest clique size (0 if none) */
+    uint32_t hist_len;                /* in: length of hist */
+    uint64_t* hist;                   /* in/out, host, caller-owned: hist[k] = #cliques of size k */
+    uint32_t* stream_vertices;        /* MCE_F_STREAM: device uint32[stream_vcap] */
+    uint64_t stream_vcap;
+    uint64_t* stream_offsets;         /* MCE_F_STREAM: device uint64[stream_ocap]; entry i is
+                                         (start << 16) | size of clique i in stream_vertices, or
+                                         UINT64_MAX if its vertices did not fit */
+    uint64_t stream_ocap;
+    uint64_t stream_vertices_written; /* out */
+    uint64_t stream_cliques_written;  /* out */
+    uint64_t stats[16];               /* out (MCE_F_STATS): see MCE_STAT_* */
+} mce_result;
+
+/*
+ * Enumerate the maximal cliques of a single-graph handle (Algorithms 2 and 3).
+ * opt may be NULL (defaults: worker list on, full enumeration).  res must not
+ * be NULL; res->hist may be NULL (hist_len 0) only if the histogram is not
+ * wanted -- otherwise a hist shorter than max_clique_size + 1 gives
+ * MCE_ERR_BUFFER_TOO_SMALL with count, hash and max_clique_size still valid
+ * (degeneracy + 2 always suffices).  Stream: cliques in unspecified order,
+ * vertex ids are input ids; when a buffer fills, writing stops and the call
+ * returns MCE_WARN_STREAM_TRUNCATED with totals still exact.  One call per
+ * handle at a time; the call synchronises its stream before returning.
+ */
+mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res);
+
+/*
+ * Enumerate every graph of a batch-loaded handle in one persistent launch
+ * over a device-wide (graph, root) queue.  res is an array of n_res >=
+ * n_graphs results (res[i] for graph i, same field rules as mce_enumerate;
+ * streams are not supported in batch mode).
+ */
+mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result* res,
+                               uint32_t n_res);
+
+/* Release a handle (NULL is a no-op). */
+void mce_free(mce_graph* g);
+
+/* Static description of a status code. */
+const char* mce_status_string(mce_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* mce_last_error(void);
+
+/* Library version string. */
+const char* mce_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCE_H */

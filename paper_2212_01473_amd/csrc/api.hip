@@ -1,0 +1,265 @@
+// C ABI of the library (declared in include/mce.h).  Argument checking, device
+// memory for host-supplied graphs, and orchestration of preprocessing and
+// enumeration; every step of the computation runs in this library's kernels.
+#include "mce_internal.h"
+
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace mce {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* get_error() { return g_last_error.c_str(); }
+
+}  // namespace mce
+
+struct mce_graph {
+    std::vector<std::unique_ptr<mce::Oriented>> graphs;
+    mce::EnumState state;
+    bool batch = false;
+};
+
+using namespace mce;
+
+namespace {
+
+mce_status fail(mce_status code, const std::string& msg)
+{
+    set_error(msg);
+    return code;
+}
+
+mce_status load_one(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n, uint64_t nnz, uint32_t flags,
+                    hipStream_t s, Oriented& og)
+{
+    const bool on_dev = (flags & MCE_LOAD_DEVICE_PTRS) != 0;
+    const bool validate = (flags & MCE_LOAD_NO_VALIDATE) == 0;
+    DevBuf drp, dci;
+    const uint32_t* rp = row_ptr;
+    const uint32_t* ci = col_idx;
+    if (!on_dev) {
+        if (validate) {
+            // cheap host checks that guard the device copies
+            if (row_ptr[0] != 0) return fail(MCE_ERR_INVALID_GRAPH, "invalid graph: row_ptr[0] != 0 at row 0");
+            if ((uint64_t)row_ptr[n] != nnz)
+                return fail(MCE_ERR_INVALID_GRAPH, "invalid graph: row_ptr[n] != nnz at row " + std::to_string(n));
+        }
+        mce_status st;
+        if ((st = drp.alloc(((size_t)n + 1) * 4)) != MCE_OK) return st;
+        if ((st = dci.alloc((size_t)(nnz ? nnz : 1) * 4)) != MCE_OK) return st;
+        MCE_HIP_TRY(hipMemcpyAsync(drp.p, row_ptr, ((size_t)n + 1) * 4, hipMemcpyHostToDevice, s));
+        if (nnz) MCE_HIP_TRY(hipMemcpyAsync(dci.p, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, s));
+        rp = drp.as<uint32_t>();
+        ci = dci.as<uint32_t>();
+    }
+    return preprocess_graph(rp, ci, n, nnz, validate, s, og);
+}
+
+void fill_info(const Oriented& o, uint32_t n_graphs, mce_graph_info* out)
+{
+    out->n = o.n;
+    out->nnz = o.nnz;
+    out->max_degree = o.max_degree;
+    out->degeneracy = o.degeneracy;
+    out->n_isolated = o.n_isolated;
+    out->peel_rounds = o.rounds;
+    out->max_out_degree = o.max_out;
+    out->max_in_degree = o.max_in;
+    out->n_graphs = n_graphs;
+}
+
+mce_status config_from(const mce_options* opt, EnumConfig& cfg)
+{
+    if (!opt) return MCE_OK;
+    if (opt->struct_size != sizeof(mce_options))
+        return fail(MCE_ERR_INVALID_ARG, "mce_options.struct_size must be sizeof(mce_options)");
+    cfg.flags = opt->flags;
+    cfg.max_root_core = opt->max_root_core;
+    cfg.wg_per_cu = opt->wg_per_cu;
+    cfg.bitmap_max_p = opt->bitmap_max_p;
+    cfg.donate_min_p = opt->donate_min_p ? opt->donate_min_p : 10u;
+    cfg.donate_max_depth = opt->donate_max_depth;
+    cfg.timeout_ms = opt->timeout_ms ? opt->timeout_ms : 600000ull;
+    cfg.root_order = opt->root_order;
+    cfg.root_count = opt->root_count;
+    cfg.root_hash = opt->root_hash;
+    cfg.root_nodes = opt->root_nodes;
+    if (cfg.bitmap_max_p > 4096) return fail(MCE_ERR_INVALID_ARG, "bitmap_max_p must be <= 4096");
+    return MCE_OK;
+}
+
+mce_status finish_result(const EnumOutput& eo, mce_result* res, mce_status st)
+{
+    res->count = eo.count;
+    res->hash = eo.hash;
+    res->max_clique_size = eo.max_size;
+    for (int i = 0; i < 16; ++i) res->stats[i] = eo.stats[i];
+    res->stream_cliques_written = eo.stream_c < res->stream_ocap ? eo.stream_c : res->stream_ocap;
+    res->stream_vertices_written = eo.stream_v < res->stream_vcap ? eo.stream_v : res->stream_vcap;
+    if (st != MCE_OK) return st;
+    if (res->hist && res->hist_len) {
+        for (uint32_t k = 0; k < res->hist_len; ++k) res->hist[k] = k < eo.hist.size() ? eo.hist[k] : 0;
+        if (res->hist_len < eo.max_size + 1)
+            return fail(MCE_ERR_BUFFER_TOO_SMALL,
+                        "hist_len " + std::to_string(res->hist_len) + " < max_clique_size + 1 = " +
+                            std::to_string(eo.max_size + 1));
+    }
+    if (eo.stream_truncated) return MCE_WARN_STREAM_TRUNCATED;
+    return MCE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mce_status mce_load_csr(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n, uint64_t nnz, uint32_t flags,
+                        void* stream, mce_graph** out)
+{
+    set_error("");
+    if (!out) return fail(MCE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!row_ptr) return fail(MCE_ERR_INVALID_ARG, "row_ptr is NULL");
+    if (!col_idx && nnz) return fail(MCE_ERR_INVALID_ARG, "col_idx is NULL");
+    if (n == 0xFFFFFFFFu) return fail(MCE_ERR_INVALID_ARG, "n too large");
+    if (flags & ~(MCE_LOAD_DEVICE_PTRS | MCE_LOAD_NO_VALIDATE)) return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    auto g = std::make_unique<mce_graph>();
+    g->graphs.emplace_back(new Oriented());
+    uint32_t dummy = 0;
+    mce_status st = load_one(row_ptr, nnz ? col_idx : &dummy, n, nnz, flags, s, *g->graphs[0]);
+    if (st != MCE_OK) return st;
+    *out = g.release();
+    return MCE_OK;
+}
+
+mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_idx_cat, const uint64_t* row_off,
+                              const uint64_t* col_off, uint32_t n_graphs, uint32_t flags, void* stream,
+                              mce_graph** out)
+{
+    set_error("");
+    if (!out) return fail(MCE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!row_ptr_cat || !row_off || !col_off) return fail(MCE_ERR_INVALID_ARG, "NULL batch array");
+    if (n_graphs == 0) return fail(MCE_ERR_INVALID_ARG, "n_graphs is 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    auto g = std::make_unique<mce_graph>();
+    g->batch = true;
+    for (uint32_t i = 0; i < n_graphs; ++i) {
+        if (row_off[i + 1] <= row_off[i] || col_off[i + 1] < col_off[i])
+            return fail(MCE_ERR_INVALID_ARG, "batch offsets not increasing at graph " + std::to_string(i));
+        uint64_t nv = row_off[i + 1] - row_off[i] - 1;
+        uint64_t ne = col_off[i + 1] - col_off[i];
+        if (nv >= 0xFFFFFFFFull) return fail(MCE_ERR_INVALID_ARG, "graph too large");
+        if (ne && !col_idx_cat) return fail(MCE_ERR_INVALID_ARG, "col_idx_cat is NULL");
+        g->graphs.emplace_back(new Oriented());
+        uint32_t dummy = 0;
+        mce_status st = load_one(row_ptr_cat + row_off[i], ne ? col_idx_cat + col_off[i] : &dummy, (uint32_t)nv, ne,
+                                 flags, s, *g->graphs.back());
+        if (st != MCE_OK) {
+            set_error("graph " + std::to_string(i) + ": " + get_error());
+            return st;
+        }
+    }
+    *out = g.release();
+    return MCE_OK;
+}
+
+mce_status mce_graph_get_info(const mce_graph* g, uint32_t graph_idx, mce_graph_info* out)
+{
+    if (!g || !out) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    if (graph_idx >= g->graphs.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
+    fill_info(*g->graphs[graph_idx], (uint32_t)g->graphs.size(), out);
+    return MCE_OK;
+}
+
+mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t* core, uint32_t* peel_round,
+                                uint32_t* order)
+{
+    if (!g) return fail(MCE_ERR_INVALID_ARG, "NULL graph");
+    if (graph_idx >= g->graphs.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
+    const Oriented& o = *g->graphs[graph_idx];
+    size_t bytes = (size_t)o.n * 4;
+    if (bytes == 0) return MCE_OK;
+    if (core) MCE_HIP_TRY(hipMemcpy(core, o.core.p, bytes, hipMemcpyDeviceToHost));
+    if (peel_round) MCE_HIP_TRY(hipMemcpy(peel_round, o.round.p, bytes, hipMemcpyDeviceToHost));
+    if (order) MCE_HIP_TRY(hipMemcpy(order, o.perm.p, bytes, hipMemcpyDeviceToHost));
+    return MCE_OK;
+}
+
+mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res)
+{
+    set_error("");
+    if (!g || !res) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    if (g->graphs.size() != 1) return fail(MCE_ERR_INVALID_ARG, "batch handle: use mce_enumerate_batch");
+    EnumConfig cfg;
+    mce_status st = config_from(opt, cfg);
+    if (st != MCE_OK) return st;
+    if (res->hist_len && !res->hist) return fail(MCE_ERR_INVALID_ARG, "hist is NULL with hist_len > 0");
+    if (cfg.flags & MCE_F_STREAM) {
+        cfg.stream_vertices = res->stream_vertices;
+        cfg.stream_vcap = res->stream_vcap;
+        cfg.stream_offsets = res->stream_offsets;
+        cfg.stream_ocap = res->stream_ocap;
+    }
+    if (cfg.flags & (MCE_F_LEARNED_ORDER | MCE_F_SPLIT))
+        return fail(MCE_ERR_UNSUPPORTED, "learned ordering is not available in this build");
+    hipStream_t s = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
+    EnumOutput eo;
+    st = enumerate_graph(*g->graphs[0], cfg, g->state, s, eo);
+    if (st != MCE_OK && st != MCE_ERR_TIMEOUT) return st;
+    return finish_result(eo, res, st);
+}
+
+mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result* res, uint32_t n_res)
+{
+    set_error("");
+    if (!g || !res) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    if (n_res < g->graphs.size()) return fail(MCE_ERR_INVALID_ARG, "n_res smaller than the number of graphs");
+    EnumConfig cfg;
+    mce_status st = config_from(opt, cfg);
+    if (st != MCE_OK) return st;
+    if (cfg.flags & (MCE_F_STREAM | MCE_F_ROOT_STATS | MCE_F_CUSTOM_ORDER))
+        return fail(MCE_ERR_INVALID_ARG, "stream, per-root statistics and custom order are single-graph only");
+    if (cfg.flags & (MCE_F_LEARNED_ORDER | MCE_F_SPLIT))
+        return fail(MCE_ERR_UNSUPPORTED, "learned ordering is not available in this build");
+    hipStream_t s = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
+    mce_status worst = MCE_OK;
+    for (size_t i = 0; i < g->graphs.size(); ++i) {
+        EnumOutput eo;
+        st = enumerate_graph(*g->graphs[i], cfg, g->state, s, eo);
+        if (st != MCE_OK && st != MCE_ERR_TIMEOUT) return st;
+        st = finish_result(eo, &res[i], st);
+        if (st < 0) return st;
+        if (st != MCE_OK) worst = st;
+    }
+    return worst;
+}
+
+void mce_free(mce_graph* g) { delete g; }
+
+const char* mce_status_string(mce_status s)
+{
+    switch (s) {
+    case MCE_OK: return "ok";
+    case MCE_WARN_STREAM_TRUNCATED: return "clique stream truncated (totals exact)";
+    case MCE_ERR_INVALID_ARG: return "invalid argument";
+    case MCE_ERR_INVALID_GRAPH: return "invalid graph";
+    case MCE_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case MCE_ERR_DEVICE: return "device error";
+    case MCE_ERR_BUFFER_TOO_SMALL: return "histogram buffer too small";
+    case MCE_ERR_TIMEOUT: return "timeout";
+    case MCE_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* mce_last_error(void) { return get_error(); }
+
+const char* mce_version(void) { return "mce-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,529 @@
+// Graph preprocessing on the device: CSR validation, the synchronous-round
+// k-core peel that yields core numbers and a degeneracy order (Section II-D,
+// "Degeneracy Ordering"; included in the timed region as in Section IV-A), and
+// orientation of every row into the later neighbours (the first-level P of
+// Algorithm 3) and earlier neighbours (the first-level X), relabelled by rank.
+#include "mce_internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace mce {
+
+namespace {
+
+constexpr uint32_t kUnset = 0xFFFFFFFFu;
+
+unsigned blocks_for(size_t items, unsigned per_block, unsigned cap = 65536)
+{
+    size_t b = (items + per_block - 1) / per_block;
+    if (b == 0) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+__device__ inline uint64_t fmix64(uint64_t z)
+{
+    // SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014).
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline uint32_t prefix_popc(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ---- validation ---------------------------------------------------------------
+// error code: (row << 32) | (pos << 3) | kind; min over the grid wins.
+enum : uint32_t { kErrRowPtr = 1, kErrColRange = 2, kErrOrder = 3, kErrSelfLoop = 4, kErrAsym = 5 };
+
+__global__ void k_validate_rowptr(const uint32_t* __restrict__ rp, uint32_t n, uint64_t nnz,
+                                  unsigned long long* err)
+{
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n;
+         v += (size_t)gridDim.x * blockDim.x) {
+        bool bad = false;
+        if (v == 0 && rp[0] != 0) bad = true;
+        if (v == n && (uint64_t)rp[n] != nnz) bad = true;
+        if (v < n && rp[v] > rp[v + 1]) bad = true;
+        if (bad) atomicMin(err, ((unsigned long long)v << 32) | kErrRowPtr);
+    }
+}
+
+__device__ bool row_contains(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
+                             uint32_t u, uint32_t w)
+{
+    uint32_t lo = rp[u], hi = rp[u + 1];
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        uint32_t x = ci[mid];
+        if (x == w) return true;
+        if (x < w) lo = mid + 1;
+        else hi = mid;
+    }
+    return false;
+}
+
+// one wave per row
+__global__ void k_validate_cols(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
+                                uint32_t n, unsigned long long* err)
+{
+    const uint32_t lane = lane_id();
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
+        uint32_t beg = rp[v], end = rp[v + 1];
+        for (uint32_t e = beg + lane; e < end; e += 64) {
+            uint32_t u = ci[e];
+            uint32_t kind = 0;
+            if (u >= n) kind = kErrColRange;
+            else if (u == v) kind = kErrSelfLoop;
+            else if (e > beg && ci[e - 1] >= u) kind = kErrOrder;
+            else if (!row_contains(rp, ci, u, (uint32_t)v)) kind = kErrAsym;
+            if (kind)
+                atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kind);
+        }
+    }
+}
+
+// ---- peel ----------------------------------------------------------------------
+struct PeelCtl {
+    uint32_t n_front;   // size of the frontier being built
+    uint32_t n_alive;   // size of the alive list being built
+    uint32_t min_deg;
+    uint32_t pad;
+};
+
+__global__ void k_peel_init(const uint32_t* __restrict__ rp, uint32_t n, uint32_t* __restrict__ deg,
+                            uint32_t* __restrict__ round, uint32_t* __restrict__ alive,
+                            unsigned long long* __restrict__ stats)
+{
+    uint32_t local_max = 0, local_iso = 0;
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (size_t)gridDim.x * blockDim.x) {
+        uint32_t d = rp[v + 1] - rp[v];
+        deg[v] = d;
+        round[v] = kUnset;
+        alive[v] = (uint32_t)v;
+        local_max = max(local_max, d);
+        local_iso += (d == 0);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        local_max = max(local_max, (uint32_t)__shfl_xor((int)local_max, off));
+        local_iso += (uint32_t)__shfl_xor((int)local_iso, off);
+    }
+    if (lane_id() == 0) {
+        atomicMax(&stats[0], (unsigned long long)local_max);
+        atomicAdd(&stats[1], (unsigned long long)local_iso);
+    }
+}
+
+__global__ void k_level_min(const uint32_t* __restrict__ alive, uint32_t n_alive,
+                            const uint32_t* __restrict__ deg, const uint32_t* __restrict__ round,
+                            PeelCtl* ctl)
+{
+    uint32_t m = kUnset;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_alive;
+         i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t v = alive[i];
+        if (round[v] == kUnset) m = min(m, deg[v]);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
+    if (lane_id() == 0 && m != kUnset) atomicMin(&ctl->min_deg, m);
+}
+
+// Select the level's first frontier: every unremoved vertex of degree <= k.
+// Unselected unremoved vertices are compacted into alive_out.
+__global__ void k_level_select(const uint32_t* __restrict__ alive, uint32_t n_alive,
+                               const uint32_t* __restrict__ deg, uint32_t* __restrict__ round,
+                               uint32_t* __restrict__ core, uint32_t k, uint32_t r,
+                               uint32_t* __restrict__ front, uint32_t* __restrict__ alive_out,
+                               PeelCtl* ctl)
+{
+    const uint32_t lane = lane_id();
+    for (size_t base = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n_alive;
+         base += (size_t)gridDim.x * blockDim.x) {
+        size_t i = base + lane;
+        uint32_t v = 0;
+        bool sel = false, keep = false;
+        if (i < n_alive) {
+            v = alive[i];
+            if (round[v] == kUnset) {
+                if (deg[v] <= k) sel = true;
+                else keep = true;
+            }
+        }
+        uint64_t ms = __ballot(sel), mk = __ballot(keep);
+        uint32_t bs = 0, bk = 0;
+        if (lane == 0) {
+            if (ms) bs = atomicAdd(&ctl->n_front, (uint32_t)__popcll(ms));
+            if (mk) bk = atomicAdd(&ctl->n_alive, (uint32_t)__popcll(mk));
+        }
+        bs = __shfl(bs, 0);
+        bk = __shfl(bk, 0);
+        if (sel) {
+            round[v] = r;
+            core[v] = k;
+            front[bs + prefix_popc(ms)] = v;
+        }
+        if (keep) alive_out[bk + prefix_popc(mk)] = v;
+    }
+}
+
+// Remove the frontier: decrement remaining neighbours; a neighbour whose degree
+// falls from k+1 to k joins the next round.  One wave per frontier vertex.
+__global__ void k_peel_decrement(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
+                                 const uint32_t* __restrict__ front, uint32_t n_front,
+                                 uint32_t* __restrict__ deg, uint32_t* __restrict__ round,
+                                 uint32_t* __restrict__ core, uint32_t k, uint32_t r_next,
+                                 uint32_t* __restrict__ front_next, PeelCtl* ctl)
+{
+    const uint32_t lane = lane_id();
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    for (size_t f = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); f < n_front; f += waves) {
+        uint32_t v = front[f];
+        uint32_t beg = rp[v], end = rp[v + 1];
+        for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+            uint32_t e = e0 + lane;
+            bool joined = false;
+            uint32_t u = 0;
+            if (e < end) {
+                u = ci[e];
+                if (__hip_atomic_load(&round[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kUnset) {
+                    uint32_t old = atomicSub(&deg[u], 1u);
+                    if (old == k + 1) {
+                        joined = true;
+                        __hip_atomic_store(&round[u], r_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        core[u] = k;
+                    }
+                }
+            }
+            uint64_t m = __ballot(joined);
+            uint32_t b = 0;
+            if (lane == 0 && m) b = atomicAdd(&ctl->n_front, (uint32_t)__popcll(m));
+            b = __shfl(b, 0);
+            if (joined) front_next[b + prefix_popc(m)] = u;
+        }
+    }
+}
+
+// ---- orientation -------------------------------------------------------------------
+__global__ void k_rank_from_order(const uint32_t* __restrict__ order, uint32_t n, uint32_t* __restrict__ rank,
+                                  const uint32_t* __restrict__ core, uint32_t* __restrict__ core_r,
+                                  uint64_t* __restrict__ vkey)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t v = order[i];
+        rank[v] = (uint32_t)i;
+        core_r[i] = core[v];
+        vkey[i] = fmix64((uint64_t)v * kGamma + kGamma);
+    }
+}
+
+// one wave per input vertex: out/in degree in rank space
+__global__ void k_orient_count(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
+                               const uint32_t* __restrict__ rank, uint32_t* __restrict__ outdeg,
+                               uint32_t* __restrict__ indeg, unsigned int* __restrict__ maxes)
+{
+    const uint32_t lane = lane_id();
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
+        uint32_t rv = rank[v];
+        uint32_t beg = rp[v], end = rp[v + 1];
+        uint32_t cnt = 0;
+        for (uint32_t e = beg + lane; e < end; e += 64) cnt += rank[ci[e]] > rv;
+        for (int off = 32; off > 0; off >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, off);
+        if (lane == 0) {
+            uint32_t in = (end - beg) - cnt;
+            outdeg[rv] = cnt;
+            indeg[rv] = in;
+            atomicMax(&maxes[0], cnt);
+            atomicMax(&maxes[1], in);
+        }
+    }
+}
+
+__global__ void k_orient_fill(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
+                              const uint32_t* __restrict__ rank, const uint32_t* __restrict__ op,
+                              const uint32_t* __restrict__ ip, uint32_t* __restrict__ oc,
+                              uint32_t* __restrict__ ic)
+{
+    const uint32_t lane = lane_id();
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
+        uint32_t rv = rank[v];
+        uint32_t beg = rp[v], end = rp[v + 1];
+        uint32_t po = op[rv], pi = ip[rv];
+        for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+            uint32_t e = e0 + lane;
+            bool valid = e < end;
+            uint32_t ru = valid ? rank[ci[e]] : 0u;
+            bool later = valid && ru > rv;
+            bool earlier = valid && ru < rv;
+            uint64_t ml = __ballot(later), me = __ballot(earlier);
+            if (later) oc[po + prefix_popc(ml)] = ru;
+            if (earlier) ic[pi + prefix_popc(me)] = ru;
+            po += (uint32_t)__popcll(ml);
+            pi += (uint32_t)__popcll(me);
+        }
+    }
+}
+
+// Sort every out-row ascending (rows are at most kRowSortCap long).  One wave
+// per row, bitonic network in LDS.
+constexpr int kRowSortCap = 4096;
+
+__global__ void __launch_bounds__(64) k_sort_rows(const uint32_t* __restrict__ op, uint32_t n,
+                                                  uint32_t* __restrict__ oc)
+{
+    __shared__ uint32_t buf[kRowSortCap];
+    const uint32_t lane = lane_id();
+    for (size_t r = blockIdx.x; r < n; r += gridDim.x) {
+        uint32_t beg = op[r], end = op[r + 1];
+        uint32_t len = end - beg;
+        if (len <= 1) continue;
+        uint32_t m = 2;
+        while (m < len) m <<= 1;
+        for (uint32_t i = lane; i < m; i += 64) buf[i] = i < len ? oc[beg + i] : 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t k = 2; k <= m; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = lane; i < m; i += 64) {
+                    uint32_t l = i ^ j;
+                    if (l > i) {
+                        uint32_t a = buf[i], b = buf[l];
+                        bool up = (i & k) == 0;
+                        if ((a > b) == up) {
+                            buf[i] = b;
+                            buf[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = lane; i < len; i += 64) oc[beg + i] = buf[i];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t nnz,
+                            bool validate, hipStream_t s, Oriented& g)
+{
+    mce_status st;
+    g.n = n;
+    g.nnz = nnz;
+    if (nnz >= (1ull << 32)) {
+        set_error("nnz must be below 2^32 (uint32 CSR)");
+        return MCE_ERR_UNSUPPORTED;
+    }
+    DevBuf misc;
+    if ((st = misc.alloc(256)) != MCE_OK) return st;
+    unsigned long long* dmisc = misc.as<unsigned long long>();
+    uint64_t hmisc[32];
+
+    if (validate) {
+        uint64_t init = ~0ull;
+        MCE_HIP_TRY(hipMemcpyAsync(dmisc, &init, 8, hipMemcpyHostToDevice, s));
+        k_validate_rowptr<<<blocks_for((size_t)n + 1, 256), 256, 0, s>>>(rp, n, nnz, dmisc);
+        MCE_HIP_TRY(hipGetLastError());
+        MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        if (hmisc[0] != ~0ull) {
+            set_error("invalid graph: row_ptr not monotone / row_ptr[0] != 0 / row_ptr[n] != nnz at row " +
+                      std::to_string(hmisc[0] >> 32));
+            return MCE_ERR_INVALID_GRAPH;
+        }
+        k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc);
+        MCE_HIP_TRY(hipGetLastError());
+        MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        if (hmisc[0] != ~0ull) {
+            static const char* kinds[] = {"", "row_ptr", "column out of range", "row not strictly increasing",
+                                          "self-loop", "asymmetric (missing reverse arc)"};
+            uint32_t kind = (uint32_t)(hmisc[0] & 7u);
+            set_error(std::string("invalid graph: ") + kinds[kind < 6 ? kind : 0] + " at row " +
+                      std::to_string(hmisc[0] >> 32) + " position " +
+                      std::to_string((hmisc[0] & 0xFFFFFFFFull) >> 3));
+            return MCE_ERR_INVALID_GRAPH;
+        }
+    }
+
+    // ---- peel
+    DevBuf deg, alive_a, alive_b, front_a, front_b, ctlb;
+    size_t nn = n ? n : 1;
+    if ((st = deg.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = alive_a.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = alive_b.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = front_a.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = front_b.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = g.core.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = g.round.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = ctlb.alloc(sizeof(PeelCtl))) != MCE_OK) return st;
+    PeelCtl* ctl = ctlb.as<PeelCtl>();
+    uint32_t* dcore = g.core.as<uint32_t>();
+    uint32_t* dround = g.round.as<uint32_t>();
+
+    {
+        uint64_t z[4] = {0, 0, 0, 0};
+        MCE_HIP_TRY(hipMemcpyAsync(dmisc, z, 32, hipMemcpyHostToDevice, s));
+    }
+    if (n) {
+        k_peel_init<<<blocks_for(n, 256, 4096), 256, 0, s>>>(rp, n, deg.as<uint32_t>(), dround,
+                                                              alive_a.as<uint32_t>(), dmisc);
+        MCE_HIP_TRY(hipGetLastError());
+    }
+    MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 16, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    g.max_degree = (uint32_t)hmisc[0];
+    g.n_isolated = hmisc[1];
+
+    uint32_t* A = alive_a.as<uint32_t>();
+    uint32_t* A2 = alive_b.as<uint32_t>();
+    uint32_t* F = front_a.as<uint32_t>();
+    uint32_t* F2 = front_b.as<uint32_t>();
+    uint32_t nA = n, k = 0, r = 0;
+    uint64_t removed = 0;
+    uint32_t degen = 0;
+    while (removed < n) {
+        PeelCtl c0 = {0, 0, kUnset, 0};
+        MCE_HIP_TRY(hipMemcpyAsync(ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
+        k_level_min<<<blocks_for(nA, 256, 4096), 256, 0, s>>>(A, nA, deg.as<uint32_t>(), dround, ctl);
+        MCE_HIP_TRY(hipGetLastError());
+        PeelCtl c1;
+        MCE_HIP_TRY(hipMemcpyAsync(&c1, ctl, sizeof(c1), hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        if (c1.min_deg == kUnset) {
+            set_error("internal: peel found no remaining vertex");
+            return MCE_ERR_DEVICE;
+        }
+        k = std::max(k, c1.min_deg);
+        degen = k;
+        k_level_select<<<blocks_for(nA, 256, 4096), 256, 0, s>>>(A, nA, deg.as<uint32_t>(), dround, dcore,
+                                                                  k, r, F, A2, ctl);
+        MCE_HIP_TRY(hipGetLastError());
+        MCE_HIP_TRY(hipMemcpyAsync(&c1, ctl, sizeof(c1), hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        uint32_t nF = c1.n_front;
+        std::swap(A, A2);
+        nA = c1.n_alive;
+        while (true) {
+            removed += nF;
+            uint32_t zero = 0;
+            MCE_HIP_TRY(hipMemcpyAsync(&ctl->n_front, &zero, 4, hipMemcpyHostToDevice, s));
+            k_peel_decrement<<<blocks_for(nF, 4, 16384), 256, 0, s>>>(rp, ci, F, nF, deg.as<uint32_t>(), dround,
+                                                                      dcore, k, r + 1, F2, ctl);
+            MCE_HIP_TRY(hipGetLastError());
+            uint32_t nF2 = 0;
+            MCE_HIP_TRY(hipMemcpyAsync(&nF2, &ctl->n_front, 4, hipMemcpyDeviceToHost, s));
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+            r++;
+            if (nF2 == 0) break;
+            std::swap(F, F2);
+            nF = nF2;
+        }
+    }
+    g.rounds = r;
+    g.degeneracy = degen;
+    alive_a.release();
+    alive_b.release();
+    front_b.release();
+
+    // ---- order by (round, id): stable radix sort of ids keyed by round
+    DevBuf order, keys;
+    if ((st = order.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = keys.alloc(nn * 4)) != MCE_OK) return st;
+    MCE_HIP_TRY(hipMemcpyAsync(keys.p, dround, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    iota_u32(order.as<uint32_t>(), n, s);
+    int bits = 0;
+    while (bits < 32 && (r >> bits) != 0) ++bits;
+    {
+        RadixTmp rt;
+        if ((st = stable_sort_pairs_u32(keys.as<uint32_t>(), order.as<uint32_t>(), n, bits, rt, s)) != MCE_OK)
+            return st;
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    keys.release();
+
+    // ---- rank, keys, core by rank
+    DevBuf& rank = g.rank;
+    if ((st = rank.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = g.core_r.alloc(nn * 4)) != MCE_OK) return st;
+    if ((st = g.vkey.alloc(nn * 8)) != MCE_OK) return st;
+    if (n) {
+        k_rank_from_order<<<blocks_for(n, 256, 4096), 256, 0, s>>>(order.as<uint32_t>(), n, rank.as<uint32_t>(),
+                                                                    dcore, g.core_r.as<uint32_t>(),
+                                                                    g.vkey.as<uint64_t>());
+        MCE_HIP_TRY(hipGetLastError());
+    }
+
+    // ---- orient
+    DevBuf outdeg, indeg;
+    if ((st = outdeg.alloc((nn + 1) * 4)) != MCE_OK) return st;
+    if ((st = indeg.alloc((nn + 1) * 4)) != MCE_OK) return st;
+    if ((st = g.op.alloc((nn + 1) * 4)) != MCE_OK) return st;
+    if ((st = g.ip.alloc((nn + 1) * 4)) != MCE_OK) return st;
+    {
+        uint64_t z[4] = {0, 0, 0, 0};
+        MCE_HIP_TRY(hipMemcpyAsync(dmisc, z, 32, hipMemcpyHostToDevice, s));
+    }
+    if (n) {
+        k_orient_count<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(),
+                                                                outdeg.as<uint32_t>(), indeg.as<uint32_t>(),
+                                                                reinterpret_cast<unsigned int*>(dmisc));
+        MCE_HIP_TRY(hipGetLastError());
+    }
+    DevBuf stmp;
+    if ((st = stmp.alloc(scan_tmp_words(nn + 1) * 8)) != MCE_OK) return st;
+    uint32_t* dtot = reinterpret_cast<uint32_t*>(dmisc) + 8;
+    if ((st = exclusive_scan_u32(outdeg.as<uint32_t>(), g.op.as<uint32_t>(), n, dtot, stmp.as<uint64_t>(), s)) !=
+        MCE_OK)
+        return st;
+    if ((st = exclusive_scan_u32(indeg.as<uint32_t>(), g.ip.as<uint32_t>(), n, dtot + 1, stmp.as<uint64_t>(), s)) !=
+        MCE_OK)
+        return st;
+    // row_ptr[n] = totals
+    MCE_HIP_TRY(hipMemcpyAsync(g.op.as<uint32_t>() + n, dtot, 4, hipMemcpyDeviceToDevice, s));
+    MCE_HIP_TRY(hipMemcpyAsync(g.ip.as<uint32_t>() + n, dtot + 1, 4, hipMemcpyDeviceToDevice, s));
+    uint32_t hm[10];
+    MCE_HIP_TRY(hipMemcpyAsync(hm, dmisc, 40, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    g.max_out = hm[0];
+    g.max_in = hm[1];
+    uint64_t half_out = hm[8], half_in = hm[9];
+    if (half_out + half_in != nnz) {
+        set_error("internal: orientation lost arcs");
+        return MCE_ERR_DEVICE;
+    }
+    if (g.max_out >= (uint32_t)kRowSortCap) {
+        set_error("degeneracy order gives a first-level P of " + std::to_string(g.max_out) +
+                  " vertices; at most " + std::to_string(kRowSortCap - 1) + " are supported");
+        return MCE_ERR_UNSUPPORTED;
+    }
+    if ((st = g.oc.alloc((half_out + 1) * 4)) != MCE_OK) return st;
+    if ((st = g.ic.alloc((half_in + 1) * 4)) != MCE_OK) return st;
+    if (n) {
+        k_orient_fill<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(), g.op.as<uint32_t>(),
+                                                               g.ip.as<uint32_t>(), g.oc.as<uint32_t>(),
+                                                               g.ic.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        k_sort_rows<<<blocks_for(n, 1, 65536), 64, 0, s>>>(g.op.as<uint32_t>(), n, g.oc.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+    }
+    // perm = order
+    g.perm.release();
+    g.perm.p = order.p;
+    g.perm.bytes = order.bytes;
+    order.p = nullptr;
+    order.bytes = 0;
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+}  // namespace mce

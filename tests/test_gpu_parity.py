@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on the
+same seeded inputs.  Count, histogram and hash must be bit-identical; the peel
+arrays must equal the oracle's simulation of the synchronous peel."""
+import ctypes as C
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_01473_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FULL = 0xFFFFFFFF
+
+
+def _hist_dict(h):
+    return {k: int(v) for k, v in enumerate(h) if v}
+
+
+_ORACLE = {}
+
+
+def oracle_result(g, c=FULL):
+    key = (g.sha256(), c)
+    if key not in _ORACLE:
+        _ORACLE[key] = oracle.mce(g, max_root_core=c)
+    return _ORACLE[key]
+
+
+def check(mce, g, c=FULL, **kw):
+    exp = oracle_result(g, c)
+    with mce.load_graph(g) as dg:
+        got = mce.enumerate_cliques(dg, max_root_core=c, timeout_ms=60000, **kw)
+    assert got.count == exp.count, (g.name, kw)
+    assert got.hash == exp.hash, (g.name, kw)
+    assert _hist_dict(got.hist) == _hist_dict(exp.hist), (g.name, kw)
+    return got, exp
+
+
+# ---------------------------------------------------------------- small and closed forms
+
+def test_fig1a(gpu_lib):
+    got, _ = check(gpu_lib, I.fig1a_example())
+    assert got.count == 2
+
+
+@pytest.mark.parametrize("make", [
+    lambda: I.complete_graph(1), lambda: I.complete_graph(2), lambda: I.complete_graph(7),
+    lambda: I.complete_graph(64), lambda: I.complete_graph(65), lambda: I.complete_graph(130),
+    lambda: I.empty_graph(1), lambda: I.empty_graph(33), lambda: I.moon_moser(4), lambda: I.moon_moser(8),
+    lambda: I.cocktail_party(10), lambda: I.cycle_graph(3), lambda: I.cycle_graph(50), lambda: I.path_graph(40),
+    lambda: I.star_graph(100), lambda: I.complete_multipartite([3, 5, 2, 7, 1]),
+    lambda: I.disjoint_union([I.moon_moser(3), I.complete_graph(70), I.empty_graph(5), I.cycle_graph(9)]),
+], ids=lambda f: "g")
+def test_closed_forms(gpu_lib, make):
+    check(gpu_lib, make())
+
+
+def test_empty_vertex_set(gpu_lib):
+    g = I.empty_graph(0)
+    with gpu_lib.load_graph(g) as dg:
+        r = gpu_lib.enumerate_cliques(dg)
+    assert r.count == 0 and r.hash == 0
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_er(gpu_lib, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(20, 400))
+    p = float(rng.choice([0.02, 0.05, 0.1, 0.3, 0.5, 0.7]))
+    check(gpu_lib, I.erdos_renyi(n, p, 100 + seed))
+
+
+def _dense(i):
+    if i == 0:
+        return I.complete_multipartite([2] * 8 + [1] * 114)   # 2^8 cliques of size 122
+    if i == 1:
+        return I.complete_multipartite([3] * 5 + [1] * 70)    # 3^5 cliques of size 75
+    if i == 2:
+        return I.chung_lu_planted(n=3000, wmax=30, n_cliques=12, cmin=70, cmax=100, pool=3000, seed=5)
+    if i == 3:
+        return I.complete_multipartite([2] * 6 + [1] * 250)   # 2^6 cliques of size 256
+    return I.erdos_renyi(300, 0.5, 2100)
+
+
+@pytest.mark.parametrize("i", range(5))
+def test_dense_mid_mode(gpu_lib, i):
+    """Universes above 64 vertices: bitmap rows of several words, re-indexing
+    into the register form once P u X_P fits 64."""
+    got, _ = check(gpu_lib, _dense(i))
+    if i == 0:
+        assert got.count == 256 and _hist_dict(got.hist) == {122: 256}
+
+
+def test_er1000_workload(gpu_lib):
+    got, exp = check(gpu_lib, I.workload("er1000"))
+    assert exp.count == 8087
+
+
+@pytest.mark.parametrize("scale", [10, 12, 13])
+def test_rmat_full(gpu_lib, scale):
+    check(gpu_lib, I.rmat(scale, 16, 0.57, 0.19, 0.19, 0.05, 50 + scale))
+
+
+def test_rmat_windows(gpu_lib):
+    g = I.rmat(14, 16, 0.57, 0.19, 0.19, 0.05, 2)
+    core, _, _ = oracle.sync_peel(g)
+    d = int(core.max())
+    for c in (0, 1, 5, d // 3, d // 2):
+        check(gpu_lib, g, c=c)
+
+
+def test_chung_lu_planted_small(gpu_lib):
+    g = I.chung_lu_planted(n=20000, wmax=200, n_cliques=60, cmin=20, cmax=60, pool=4000, seed=9)
+    got, _ = check(gpu_lib, g)
+    assert got.max_size >= 20
+
+
+# ---------------------------------------------------------------- knobs never change results
+
+@pytest.mark.parametrize("kw", [
+    dict(worker_list=False),
+    dict(donate_min_p=1),
+    dict(donate_min_p=1, wg_per_cu=1),
+    dict(bitmap_max_p=64),
+    dict(bitmap_max_p=64, donate_min_p=2, wg_per_cu=2),
+    dict(flags=0x40),  # reverse degeneracy order
+])
+def test_knobs_invariant(gpu_lib, kw):
+    g = I.chung_lu_planted(n=8000, wmax=400, n_cliques=30, cmin=15, cmax=45, pool=300, seed=11)
+    check(gpu_lib, g, **kw)
+    check(gpu_lib, _dense(2), **kw)
+    check(gpu_lib, _dense(4), **kw)
+
+
+def test_worker_list_donates(gpu_lib):
+    # few workgroups, one heavy subtree: idle workgroups must receive branches
+    got, _ = check(gpu_lib, _dense(4), donate_min_p=2, wg_per_cu=1)
+    assert got.stats["donations"] > 0
+
+
+def test_custom_order(gpu_lib):
+    import torch
+
+    g = I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 8)
+    perm = torch.tensor(np.random.default_rng(0).permutation(g.n).astype(np.int32), device="cuda")
+    check(gpu_lib, g, root_order=perm)
+
+
+# ---------------------------------------------------------------- peel arrays
+
+@pytest.mark.parametrize("make", [lambda: I.workload("er1000"),
+                                  lambda: I.rmat(13, 16, 0.57, 0.19, 0.19, 0.05, 3),
+                                  lambda: I.path_graph(300), lambda: I.fig1a_example()])
+def test_peel_matches_sync_simulation(gpu_lib, make):
+    g = make()
+    core, rnd, nr = oracle.sync_peel(g)
+    with gpu_lib.load_graph(g) as dg:
+        gc, gr, order = dg.order_arrays()
+        info = dg.info()
+    assert (gc == core).all()
+    assert (gr == rnd).all()
+    assert info.peel_rounds == nr
+    assert info.degeneracy == int(core.max())
+    exp_order = np.lexsort((np.arange(g.n), rnd))
+    assert (order == exp_order).all()
+    assert info.max_degree == int(g.degrees().max())
+
+
+# ---------------------------------------------------------------- per-root statistics, stream
+
+def test_root_stats_match_oracle_on_sampled_roots(gpu_lib):
+    import torch
+
+    g = I.rmat(13, 16, 0.57, 0.19, 0.19, 0.05, 21)
+    cnt = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    hsh = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    nodes = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    with gpu_lib.load_graph(g) as dg:
+        r = gpu_lib.enumerate_cliques(dg, root_stats=(cnt, hsh, nodes))
+    cnt = cnt.cpu().numpy().view(np.uint64)
+    hsh = hsh.cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(1)
+    sample = rng.choice(g.n, size=200, replace=False)
+    mask = np.zeros(g.n, dtype=np.uint8)
+    mask[sample] = 1
+    exp = oracle.mce(g, root_mask=mask)
+    iso = (g.degrees() == 0) & (mask == 1)
+    assert int(cnt[sample].sum()) + int(iso.sum()) == exp.count
+    h = (int(hsh[sample].sum(dtype=np.uint64)) + sum(oracle.clique_hash([v]) for v in np.flatnonzero(iso))) % 2**64
+    assert h == exp.hash
+    assert int(cnt.sum()) + int((g.degrees() == 0).sum()) == r.count
+
+
+def test_stream_matches_oracle_cliques(gpu_lib):
+    import torch
+
+    g = I.erdos_renyi(120, 0.3, 77)
+    exp = oracle.mce(g, collect=True)
+    verts = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")
+    offs = torch.zeros(1 << 14, dtype=torch.int64, device="cuda")
+    with gpu_lib.load_graph(g) as dg:
+        r = gpu_lib.enumerate_cliques(dg, stream_buffers=(verts, offs))
+    assert r.status == 0
+    v = verts.cpu().numpy().view(np.uint32)
+    o = offs.cpu().numpy().view(np.uint64)[: r.stream_cliques]
+    got = sorted(tuple(sorted(int(x) for x in v[int(e >> 16): int(e >> 16) + int(e & 0xFFFF)])) for e in o)
+    assert got == sorted(exp.cliques)
+
+
+def test_stream_truncation_keeps_totals(gpu_lib):
+    import torch
+
+    g = I.erdos_renyi(120, 0.3, 78)
+    exp = oracle.mce(g)
+    verts = torch.zeros(50, dtype=torch.int32, device="cuda")
+    offs = torch.zeros(10, dtype=torch.int64, device="cuda")
+    with gpu_lib.load_graph(g) as dg:
+        r = gpu_lib.enumerate_cliques(dg, stream_buffers=(verts, offs))
+    assert r.status == gpu_lib.MCE_WARN_STREAM_TRUNCATED
+    assert r.count == exp.count and r.hash == exp.hash
+
+
+# ---------------------------------------------------------------- errors
+
+def _bad_graphs():
+    ok = I.cycle_graph(5)
+    rp, ci = ok.row_ptr.astype(np.uint32), ok.col_idx.astype(np.uint32)
+    asym = ci.copy(); asym[0] = 2           # row 0: {2, 4}, but row 2 lacks 0
+    unsorted = ci.copy(); unsorted[[0, 1]] = unsorted[[1, 0]]
+    selfloop = ci.copy(); selfloop[0] = 0
+    oob = ci.copy(); oob[0] = 99
+    dup = ci.copy(); dup[1] = dup[0]
+    badrp = rp.copy(); badrp[2] = badrp[3] + 1
+    return [(rp, asym), (rp, unsorted), (rp, selfloop), (rp, oob), (rp, dup), (badrp, ci)]
+
+
+@pytest.mark.parametrize("i", range(6))
+def test_invalid_graphs_rejected(gpu_lib, i):
+    rp, ci = _bad_graphs()[i]
+    with pytest.raises(gpu_lib.MCEError) as e:
+        gpu_lib.load_csr(rp, ci)
+    assert e.value.status == gpu_lib.MCE_ERR_INVALID_GRAPH
+    assert "row" in str(e.value)
+
+
+def test_hist_too_small(gpu_lib):
+    g = I.complete_graph(9)
+    with gpu_lib.load_graph(g) as dg:
+        with pytest.raises(gpu_lib.MCEError) as e:
+            gpu_lib.enumerate_cliques(dg, hist_len=5)
+    assert e.value.status == gpu_lib.MCE_ERR_BUFFER_TOO_SMALL
+
+
+def test_device_pointer_load(gpu_lib):
+    import torch
+
+    g = I.erdos_renyi(500, 0.05, 4)
+    rp = torch.tensor(g.row_ptr.astype(np.int64), dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx.astype(np.int64), dtype=torch.int32, device="cuda")
+    exp = oracle.mce(g)
+    with gpu_lib.load_csr(rp, ci) as dg:
+        r = gpu_lib.enumerate_cliques(dg)
+    assert (r.count, r.hash) == (exp.count, exp.hash)
+
+
+def test_timeout_is_reported(gpu_lib):
+    # a bounded watchdog set far below the run time: every wavefront must exit
+    g = _dense(4)
+    with gpu_lib.load_graph(g) as dg:
+        with pytest.raises(gpu_lib.MCEError) as e:
+            gpu_lib.enumerate_cliques(dg, timeout_ms=1)
+        assert e.value.status == gpu_lib.MCE_ERR_TIMEOUT
+        # the handle stays usable
+        r = gpu_lib.enumerate_cliques(dg)
+    exp = oracle_result(g)
+    assert (r.count, r.hash) == (exp.count, exp.hash)
+
+
+def test_batch_api(gpu_lib):
+    graphs = [I.erdos_renyi(50 + 30 * i, 0.1 + 0.05 * i, i) for i in range(6)]
+    with gpu_lib.load_batch(graphs) as dg:
+        res = gpu_lib.enumerate_batch(dg)
+    for g, r in zip(graphs, res):
+        exp = oracle.mce(g)
+        assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))

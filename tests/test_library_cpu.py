@@ -1,0 +1,103 @@
+"""Host-side checks of the C-ABI library that need no GPU: the library loads,
+exports every entry point the header declares, its struct layouts match the
+header as compiled by a C compiler, and argument errors are reported without
+touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+from paper_2212_01473_amd import mce
+
+HEADER = os.path.join(ROOT, "include", "mce.h")
+
+
+def test_library_loads_and_exports_header_symbols():
+    lib = mce.load_library()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:mce_status|void|const char\*)\s+(mce_\w+)\s*\(", text, re.M))
+    assert declared, "no declarations parsed"
+    assert declared == set(mce.EXPORTED)
+    out = subprocess.check_output(["nm", "-D", "--defined-only", mce.LIB_PATH]).decode()
+    exported = set(re.findall(r" T (mce_\w+)", out))
+    assert declared <= exported
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "mce.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
+int main(void) {
+  printf("mce_options %zu\n", sizeof(mce_options));
+  printf("mce_result %zu\n", sizeof(mce_result));
+  printf("mce_graph_info %zu\n", sizeof(mce_graph_info));
+  F(mce_options, model); F(mce_options, stream); F(mce_options, timeout_ms); F(mce_options, root_nodes);
+  F(mce_result, hist); F(mce_result, stream_vertices); F(mce_result, stats);
+  F(mce_graph_info, n_isolated); F(mce_graph_info, n_graphs);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    got = {k: int(v) for k, v in got.items()}
+    assert got["mce_options"] == C.sizeof(mce.Options)
+    assert got["mce_result"] == C.sizeof(mce.Result)
+    assert got["mce_graph_info"] == C.sizeof(mce.GraphInfo)
+    assert got["mce_options.model"] == mce.Options.model.offset
+    assert got["mce_options.stream"] == mce.Options.stream.offset
+    assert got["mce_options.timeout_ms"] == mce.Options.timeout_ms.offset
+    assert got["mce_options.root_nodes"] == mce.Options.root_nodes.offset
+    assert got["mce_result.hist"] == mce.Result.hist.offset
+    assert got["mce_result.stream_vertices"] == mce.Result.stream_vertices.offset
+    assert got["mce_result.stats"] == mce.Result.stats.offset
+    assert got["mce_graph_info.n_isolated"] == mce.GraphInfo.n_isolated.offset
+    assert got["mce_graph_info.n_graphs"] == mce.GraphInfo.n_graphs.offset
+
+
+def test_status_strings_and_version():
+    lib = mce.load_library()
+    for code in range(-7, 2):
+        s = lib.mce_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.mce_status_string(-100).decode() == "unknown status"
+    assert "gfx950" in mce.version()
+
+
+def test_argument_errors_without_device():
+    lib = mce.load_library()
+    h = C.c_void_p()
+    # NULL out pointer
+    assert lib.mce_load_csr(None, None, 0, 0, 0, None, None) == mce.MCE_ERR_INVALID_ARG
+    # NULL row_ptr
+    assert lib.mce_load_csr(None, None, 0, 0, 0, None, C.byref(h)) == mce.MCE_ERR_INVALID_ARG
+    assert "row_ptr" in lib.mce_last_error().decode()
+    # unknown load flag
+    rp = (C.c_uint32 * 1)(0)
+    assert lib.mce_load_csr(C.cast(rp, C.c_void_p), None, 0, 0, 0x100, None, C.byref(h)) == mce.MCE_ERR_INVALID_ARG
+    # enumerate / info on NULL handles
+    r = mce.Result()
+    assert lib.mce_enumerate(None, None, C.byref(r)) == mce.MCE_ERR_INVALID_ARG
+    gi = mce.GraphInfo()
+    assert lib.mce_graph_get_info(None, 0, C.byref(gi)) == mce.MCE_ERR_INVALID_ARG
+    assert lib.mce_graph_copy_order(None, 0, None, None, None) == mce.MCE_ERR_INVALID_ARG
+    assert lib.mce_enumerate_batch(None, None, C.byref(r), 1) == mce.MCE_ERR_INVALID_ARG
+    lib.mce_free(None)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = mce._lib
+    mce._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            mce.load_library(str(tmp_path / "missing.so"))
+    finally:
+        mce._lib = saved
