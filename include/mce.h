@@ -167,7 +167,9 @@ enum {
     MCE_STAT_BUILD_EDGES = 8,  /* adjacency entries scanned to build bitmaps */
     MCE_STAT_HBM_ROWS = 9,     /* tasks whose bitmap rows lived in HBM */
     MCE_STAT_IDLE_NS = 10,     /* summed workgroup idle time in the worker list (ns) */
-    MCE_STAT_LDS_BYTES = 11    /* LDS bytes per workgroup */
+    MCE_STAT_LDS_BYTES = 11,   /* LDS bytes per workgroup */
+    MCE_STAT_PROBES = 12,      /* adjacency-list entries read by X_X binary searches */
+    MCE_STAT_ROOT_WORDS = 13   /* P and X ids staged from the oriented CSR for roots */
 };
 
 typedef struct {

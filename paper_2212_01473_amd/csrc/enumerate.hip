@@ -182,7 +182,8 @@ struct Wg {
     uint32_t* uarr;   // ucap
     uint64_t* lrows;  // lds_cap * ws_lds
     // accumulators (wave-uniform)
-    uint64_t count, hash, nodes, donations, tasks, xtests, edges, hbm_tasks, idle_ticks;
+    uint64_t count, hash, nodes, donations, tasks, xtests, edges, hbm_tasks, idle_ticks, root_list_words;
+    uint32_t probes;  // per lane
     uint32_t hmax;
     uint32_t wl_tick;
     uint32_t poll;
@@ -192,12 +193,14 @@ struct Wg {
 };
 
 // Is b among the later neighbours of x?  (x precedes b in the order.)
-__device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b)
+// probes counts the list entries read.
+__device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b, uint32_t& probes)
 {
     uint32_t lo = p.op[x], hi = p.op[x + 1];
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
         uint32_t w = p.oc[mid];
+        ++probes;
         if (w == b) return true;
         if (w < b) lo = mid + 1;
         else hi = mid;
@@ -211,7 +214,7 @@ __device__ bool xx_any(const Params& p, Wg& w, uint32_t L, uint32_t b)
     const uint32_t lane = lane_id();
     for (uint32_t base = 0; base < L; base += 64) {
         uint32_t i = base + lane;
-        bool hit = i < L && has_later(p, w.xx[i], b);
+        bool hit = i < L && has_later(p, w.xx[i], b, w.probes);
         w.xtests += min(64u, L - base);
         if (__ballot(hit)) return true;
     }
@@ -228,7 +231,7 @@ __device__ uint32_t xx_partition(const Params& p, Wg& w, uint32_t L, uint32_t b)
     uint32_t K = 0;
     for (uint32_t base = 0; base < L; base += 64) {
         uint32_t i = base + lane;
-        bool keep = i < L && has_later(p, w.xx[i], b);
+        bool keep = i < L && has_later(p, w.xx[i], b, w.probes);
         uint64_t m = __ballot(keep);
         if (lane == 0) w.xflag[base >> 6] = m;
         K += (uint32_t)__popcll(m);
@@ -776,6 +779,7 @@ __device__ void run_root(const Params& p, Wg& w, uint32_t v)
     uint32_t ib = p.ip[v], L = p.ip[v + 1] - ib;
     for (uint32_t i = lane; i < nu; i += 64) w.uarr[i] = p.oc[beg + i];
     for (uint32_t i = lane; i < L; i += 64) w.xx[i] = p.ic[ib + i];
+    w.root_list_words += nu + L;
     if (lane == 0) w.R[0] = v;
     const uint32_t W = (nu + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
@@ -863,6 +867,8 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     for (uint32_t k = lane; k < (uint32_t)kHistLds; k += 64) w.hist[k] = 0;
     __syncthreads();
     w.count = w.hash = w.nodes = w.donations = w.tasks = w.xtests = w.edges = w.hbm_tasks = w.idle_ticks = 0;
+    w.root_list_words = 0;
+    w.probes = 0;
     w.hmax = 0;
     w.wl_tick = 0;
     w.poll = 0;
@@ -931,7 +937,15 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         run_received(p, w);
     }
     flush_hist(p, w);
+    uint64_t probes = 0;
+    {
+        uint32_t pl = w.probes;
+        for (int off = 32; off > 0; off >>= 1) pl += (uint32_t)__shfl_xor((int)pl, off, 64);
+        probes = pl;
+    }
     if (lane == 0) {
+        atomicAdd(&p.acc[2 + MCE_STAT_PROBES], (unsigned long long)probes);
+        atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)w.root_list_words);
         atomicAdd(&p.acc[0], (unsigned long long)w.count);
         atomicAdd(&p.acc[1], (unsigned long long)w.hash);
         atomicAdd(&p.acc[2 + MCE_STAT_NODES], (unsigned long long)w.nodes);

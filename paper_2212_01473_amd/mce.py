@@ -40,7 +40,7 @@ F_REVERSE_ORDER = 0x40
 F_CUSTOM_ORDER = 0x80
 
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
-              "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes"]
+              "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words"]
 
 FULL = 0xFFFFFFFF
 

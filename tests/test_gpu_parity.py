@@ -68,8 +68,12 @@ def test_empty_vertex_set(gpu_lib):
 @pytest.mark.parametrize("seed", range(16))
 def test_random_er(gpu_lib, seed):
     rng = np.random.default_rng(seed)
-    n = int(rng.integers(20, 400))
-    p = float(rng.choice([0.02, 0.05, 0.1, 0.3, 0.5, 0.7]))
+    if seed % 2:
+        n = int(rng.integers(20, 70))
+        p = float(rng.choice([0.3, 0.5, 0.7]))
+    else:
+        n = int(rng.integers(60, 2000))
+        p = float(rng.choice([0.005, 0.02, 0.05, 0.1]))
     check(gpu_lib, I.erdos_renyi(n, p, 100 + seed))
 
 
