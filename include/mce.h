@@ -169,7 +169,9 @@ enum {
     MCE_STAT_IDLE_NS = 10,     /* summed workgroup idle time in the worker list (ns) */
     MCE_STAT_LDS_BYTES = 11,   /* LDS bytes per workgroup */
     MCE_STAT_PROBES = 12,      /* adjacency-list entries read by X_X binary searches */
-    MCE_STAT_ROOT_WORDS = 13   /* P and X ids staged from the oriented CSR for roots */
+    MCE_STAT_ROOT_WORDS = 13,  /* P and X ids staged from the oriented CSR for roots */
+    MCE_STAT_BUSY_NS = 14,     /* summed task time over workgroups (ns) */
+    MCE_STAT_MAX_TASK_NS = 15  /* longest single task (ns) */
 };
 
 typedef struct {

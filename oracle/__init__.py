@@ -70,7 +70,7 @@ def _load():
         lib.oracle_mce.restype = C.c_int
         lib.oracle_mce.argtypes = [C.c_uint32, u32p, u32p, C.c_uint32, C.c_int,
                                    u64p, C.c_uint32, u32p, C.c_uint64, u64p, C.c_uint64,
-                                   C.POINTER(C.c_uint8), C.POINTER(_Result)]
+                                   C.POINTER(C.c_uint8), C.POINTER(C.c_uint32), C.POINTER(_Result)]
         lib.oracle_max_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -103,8 +103,10 @@ class MCEResult:
 
 
 def mce(g, max_root_core: int = 0xFFFFFFFF, threads: int = 0, collect: bool = False,
-        root_mask: np.ndarray | None = None) -> MCEResult:
-    """Exact maximal cliques of ``g`` (a CSR graph) with min core <= max_root_core."""
+        root_mask: np.ndarray | None = None, order: np.ndarray | None = None) -> MCEResult:
+    """Exact maximal cliques of ``g`` (a CSR graph) with min core <= max_root_core.
+    ``order`` (a core-sorted permutation) replaces the bucket degeneracy order;
+    it changes which root reports a clique, never the set of cliques."""
     lib = _load()
     rp, rpp = _u32(g.row_ptr)
     ci, cip = _u32(g.col_idx)
@@ -126,9 +128,14 @@ def mce(g, max_root_core: int = 0xFFFFFFFF, threads: int = 0, collect: bool = Fa
     if root_mask is not None:
         mask = np.ascontiguousarray(root_mask, dtype=np.uint8)
         mask_p = mask.ctypes.data_as(C.POINTER(C.c_uint8))
+    order_p = None
+    if order is not None:
+        order_a = np.ascontiguousarray(order, dtype=np.uint32)
+        assert order_a.shape[0] == n
+        order_p = order_a.ctypes.data_as(C.POINTER(C.c_uint32))
     st = lib.oracle_mce(n, rpp, cip, int(max_root_core) & 0xFFFFFFFF, int(threads),
                         hist.ctypes.data_as(C.POINTER(C.c_uint64)), hist_len,
-                        vp, vcap, op, ocap, mask_p, C.byref(res))
+                        vp, vcap, op, ocap, mask_p, order_p, C.byref(res))
     if st < 0:
         raise MemoryError("oracle ran out of memory")
     if st == 1:

@@ -315,9 +315,10 @@ typedef struct {
 } oracle_result;
 
 /*
- * Algorithm 3 over a degeneracy order, restricted to roots with
- * core <= max_root_core (and, when root_mask is given, to roots with a
- * non-zero mask byte: used only to time a bounded sample).  hist[k] counts
+ * Algorithm 3 over a degeneracy order (the bucket order above, or given_order
+ * when non-NULL), restricted to roots with core <= max_root_core (and, when
+ * root_mask is given, to roots with a non-zero mask byte: used to time a
+ * bounded sample and to compare per-root results).  hist[k] counts
  * cliques of size k for k < hist_len.  When clique_offsets is non-NULL the
  * cliques are also written out (input vertex ids; offsets are end positions)
  * and the run is single-threaded.
@@ -327,7 +328,7 @@ int oracle_mce(uint32_t n, const uint32_t* rp, const uint32_t* ci,
                uint64_t* hist, uint32_t hist_len,
                uint32_t* clique_verts, uint64_t vert_cap,
                uint64_t* clique_offsets, uint64_t off_cap,
-               const uint8_t* root_mask, oracle_result* out)
+               const uint8_t* root_mask, const uint32_t* given_order, oracle_result* out)
 {
     memset(out, 0, sizeof(*out));
     if (hist) memset(hist, 0, sizeof(uint64_t) * hist_len);
@@ -336,6 +337,8 @@ int oracle_mce(uint32_t n, const uint32_t* rp, const uint32_t* ci,
     uint32_t* core = malloc(sizeof(uint32_t) * n);
     uint32_t* pos = malloc(sizeof(uint32_t) * n);
     oracle_degeneracy(n, rp, ci, order, core);
+    /* a caller-given order (any core-sorted order gives the same window) */
+    if (given_order) memcpy(order, given_order, sizeof(uint32_t) * n);
     for (uint32_t i = 0; i < n; ++i) pos[order[i]] = i;
     uint32_t dmax = 0;
     for (uint32_t v = 0; v < n; ++v) if (core[v] > dmax) dmax = core[v];

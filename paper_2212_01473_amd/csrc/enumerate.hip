@@ -183,6 +183,7 @@ struct Wg {
     uint64_t* lrows;  // lds_cap * ws_lds
     // accumulators (wave-uniform)
     uint64_t count, hash, nodes, donations, tasks, xtests, edges, hbm_tasks, idle_ticks, root_list_words;
+    uint64_t busy_ticks, max_task_ticks, task_t0;
     uint32_t probes;  // per lane
     uint32_t hmax;
     uint32_t wl_tick;
@@ -762,6 +763,9 @@ __device__ void finish_task(const Params& p, Wg& w, uint32_t root, uint64_t c0, 
 {
     flush_hist(p, w);
     w.tasks += 1;
+    uint64_t dt = uni64(now_ticks()) - w.task_t0;
+    w.busy_ticks += dt;
+    w.max_task_ticks = max(w.max_task_ticks, dt);
     if ((p.flags & MCE_F_ROOT_STATS) && lane_id() == 0) {
         uint32_t id = p.perm[root];
         atomicAdd(&p.root_count[id], (unsigned long long)(w.count - c0));
@@ -775,6 +779,7 @@ __device__ void run_root(const Params& p, Wg& w, uint32_t v)
 {
     const uint32_t lane = lane_id();
     uint64_t c0 = w.count, h0 = w.hash, n0 = w.nodes;
+    w.task_t0 = uni64(now_ticks());
     uint32_t beg = p.op[v], nu = p.op[v + 1] - beg;
     uint32_t ib = p.ip[v], L = p.ip[v + 1] - ib;
     for (uint32_t i = lane; i < nu; i += 64) w.uarr[i] = p.oc[beg + i];
@@ -797,6 +802,7 @@ __device__ void run_received(const Params& p, Wg& w)
 {
     const uint32_t lane = lane_id();
     uint64_t c0 = w.count, h0 = w.hash, n0 = w.nodes;
+    w.task_t0 = uni64(now_ticks());
     MboxHdr h = *w.mbox;
     uint32_t np = uni(h.np), nxp = uni(h.nxp), L = uni(h.nxx), rs = uni(h.rsize), root = uni(h.root);
     uint64_t ks = uni64(h.keysum);
@@ -869,6 +875,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.count = w.hash = w.nodes = w.donations = w.tasks = w.xtests = w.edges = w.hbm_tasks = w.idle_ticks = 0;
     w.root_list_words = 0;
     w.probes = 0;
+    w.busy_ticks = w.max_task_ticks = w.task_t0 = 0;
     w.hmax = 0;
     w.wl_tick = 0;
     w.poll = 0;
@@ -945,6 +952,8 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     }
     if (lane == 0) {
         atomicAdd(&p.acc[2 + MCE_STAT_PROBES], (unsigned long long)probes);
+        atomicAdd(&p.acc[2 + MCE_STAT_BUSY_NS], (unsigned long long)w.busy_ticks);
+        atomicMax(&p.acc[2 + MCE_STAT_MAX_TASK_NS], (unsigned long long)w.max_task_ticks);
         atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)w.root_list_words);
         atomicAdd(&p.acc[0], (unsigned long long)w.count);
         atomicAdd(&p.acc[1], (unsigned long long)w.hash);
@@ -1223,6 +1232,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     out.stats[MCE_STAT_KERNEL_NS] = (uint64_t)(ms_kernel * 1e6);
     out.stats[MCE_STAT_SETUP_NS] = (uint64_t)(ms_setup * 1e6);
     out.stats[MCE_STAT_IDLE_NS] = acc[2 + MCE_STAT_IDLE_NS] * 10;  // 100 MHz ticks -> ns
+    out.stats[MCE_STAT_BUSY_NS] = acc[2 + MCE_STAT_BUSY_NS] * 10;
+    out.stats[MCE_STAT_MAX_TASK_NS] = acc[2 + MCE_STAT_MAX_TASK_NS] * 10;
     out.stats[MCE_STAT_LDS_BYTES] = lds_bytes;
     out.max_size = 0;
     for (uint32_t k = 0; k < hist_len; ++k)

@@ -40,7 +40,8 @@ F_REVERSE_ORDER = 0x40
 F_CUSTOM_ORDER = 0x80
 
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
-              "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words"]
+              "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words",
+              "busy_ns", "max_task_ns"]
 
 FULL = 0xFFFFFFFF
 

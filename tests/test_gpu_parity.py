@@ -190,7 +190,9 @@ def test_root_stats_match_oracle_on_sampled_roots(gpu_lib):
     sample = rng.choice(g.n, size=200, replace=False)
     mask = np.zeros(g.n, dtype=np.uint8)
     mask[sample] = 1
-    exp = oracle.mce(g, root_mask=mask)
+    # a clique is reported by its earliest vertex, so attribute with the GPU's order
+    sorder, _ = oracle.sync_order(g)
+    exp = oracle.mce(g, root_mask=mask, order=sorder)
     iso = (g.degrees() == 0) & (mask == 1)
     assert int(cnt[sample].sum()) + int(iso.sum()) == exp.count
     h = (int(hsh[sample].sum(dtype=np.uint64)) + sum(oracle.clique_hash([v]) for v in np.flatnonzero(iso))) % 2**64

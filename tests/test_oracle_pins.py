@@ -366,3 +366,18 @@ def test_threads_do_not_change_results():
     a = oracle.mce(g, threads=1)
     b = oracle.mce(g, threads=0)
     assert (a.count, a.hash, _hist_dict(a.hist)) == (b.count, b.hash, _hist_dict(b.hist))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_given_order_changes_attribution_not_results(seed):
+    g = I.rmat(11, 16, 0.57, 0.19, 0.19, 0.05, 600 + seed)
+    a = oracle.mce(g)
+    sorder, _ = oracle.sync_order(g)
+    b = oracle.mce(g, order=sorder)
+    assert (a.count, a.hash, _hist_dict(a.hist)) == (b.count, b.hash, _hist_dict(b.hist))
+    # per-root sums under the given order partition the total
+    rng = np.random.default_rng(seed)
+    mask = (rng.random(g.n) < 0.5).astype(np.uint8)
+    x = oracle.mce(g, order=sorder, root_mask=mask)
+    y = oracle.mce(g, order=sorder, root_mask=1 - mask)
+    assert x.count + y.count == b.count and (x.hash + y.hash) % 2**64 == b.hash
