@@ -49,7 +49,8 @@ struct Ctrl {
     unsigned int root_cursor;
     unsigned int err;              // 1 = timeout, 2 = internal limit
     unsigned int stream_trunc;
-    unsigned int pad[5];
+    unsigned int waiting;          // workgroups currently in the worker list
+    unsigned int pad[4];
 };
 
 struct MboxHdr {
@@ -119,15 +120,31 @@ __device__ inline uint32_t prefix_popc(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
+// Row rotation through DPP (row_ror:N, N = 1..15, rows of 16 lanes).
+template <int N>
+__device__ inline uint32_t row_ror(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + N, 0xF, 0xF, false);
+}
+// Wave-wide sum / max: reduce each 16-lane row with DPP rotations, then
+// combine the four rows through readlane (no LDS round trips).
 __device__ inline uint32_t wave_sum(uint32_t v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
-    return uni(v);
+    v += row_ror<1>(v);
+    v += row_ror<2>(v);
+    v += row_ror<4>(v);
+    v += row_ror<8>(v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 __device__ inline uint32_t wave_max(uint32_t v)
 {
-    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return uni(v);
+    v = max(v, row_ror<1>(v));
+    v = max(v, row_ror<2>(v));
+    v = max(v, row_ror<4>(v));
+    v = max(v, row_ror<8>(v));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 __device__ inline uint32_t wave_excl_scan(uint32_t v)
 {
@@ -180,6 +197,7 @@ struct Wg {
     uint32_t* sL;
     uint32_t* sA;
     uint32_t* uarr;   // ucap
+    uint64_t* ukey;   // ucap: key of each universe vertex
     uint64_t* lrows;  // lds_cap * ws_lds
     // accumulators (wave-uniform)
     uint64_t count, hash, nodes, donations, tasks, xtests, edges, hbm_tasks, idle_ticks, root_list_words;
@@ -187,6 +205,7 @@ struct Wg {
     uint32_t probes;  // per lane
     uint32_t hmax;
     uint32_t wl_tick;
+    uint32_t wl_seen;
     uint32_t poll;
     uint64_t deadline;
     uint32_t me;
@@ -329,19 +348,24 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
 {
     uint32_t r = kEmptySlot;
     if (lane_id() == 0) {
+        // The ring carries only workgroup ids, so every access here is relaxed;
+        // the task itself is published with release/acquire on the receiver's flag.
         unsigned long long h = __hip_atomic_load(&p.ctrl->ring_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long t = __hip_atomic_load(&p.ctrl->ring_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (h < t) {
-            if (__hip_atomic_compare_exchange_strong(&p.ctrl->ring_head, &h, h + 1, __ATOMIC_ACQ_REL,
+            if (__hip_atomic_compare_exchange_strong(&p.ctrl->ring_head, &h, h + 1, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 uint32_t* slot = &p.ring[h & p.ring_mask];
                 uint32_t v;
                 // the pusher has claimed this slot and stores its id imminently
-                while ((v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == kEmptySlot) {
+                while ((v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmptySlot) {
                     if (now_ticks() > w.deadline) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
-                if (v != kEmptySlot) __hip_atomic_store(slot, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v != kEmptySlot) {
+                    __hip_atomic_store(slot, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&p.ctrl->waiting, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
                 r = v;
             }
         }
@@ -349,15 +373,13 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
     return uni(r);
 }
 
-__device__ inline bool wl_has_waiting(const Params& p)
+// Number of waiting workgroups as read at the previous check: the load issued
+// now is consumed at the next check, so its latency overlaps the search.
+__device__ inline bool wl_has_waiting(const Params& p, Wg& w)
 {
-    uint32_t r = 0;
-    if (lane_id() == 0) {
-        unsigned long long h = __hip_atomic_load(&p.ctrl->ring_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long t = __hip_atomic_load(&p.ctrl->ring_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        r = h < t;
-    }
-    return uni(r) != 0;
+    uint32_t prev = w.wl_seen;
+    w.wl_seen = __hip_atomic_load(&p.ctrl->waiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return uni(prev) != 0;
 }
 
 __device__ inline Wg wg_view(const Params& p, uint32_t g)
@@ -379,8 +401,8 @@ __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child
     if (!(p.flags & MCE_F_WORKER_LIST)) return false;
     if (np_child < p.donate_min_p || !more_here || !anc) return false;
     if (p.donate_max_depth && depth > p.donate_max_depth) return false;
-    if ((++w.wl_tick & 7u) != 0) return false;
-    return wl_has_waiting(p);
+    if ((++w.wl_tick & 3u) != 0) return false;
+    return wl_has_waiting(p, w);
 }
 
 // Write a task into receiver r's mailbox.  P / X_P given as (id list writer)
@@ -407,8 +429,9 @@ __device__ void send_task(const Params& p, Wg& w, uint32_t r, uint32_t root, uin
         h.anc = 0;
         *d.mbox = h;
     }
+    // publish the mailbox: one release fence, then the flag
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(&p.wflags[r], kFlagTask, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) __hip_atomic_store(&p.wflags[r], kFlagTask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     w.donations += 1;
 }
 
@@ -420,15 +443,15 @@ __device__ bool try_donate(const Params& p, Wg& w, uint32_t root, uint32_t rsize
     uint32_t r = wl_try_pop(p, w);
     if (r == kEmptySlot) return false;
     // the receiver stops counting as idle before it is handed work
-    if (lane_id() == 0) __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane_id() == 0) __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     send_task(p, w, r, root, rsize, ks, np, nxp, nxx, vb);
     return true;
 }
 
 // ---------------------------------------------------------------- small mode
 // Universe of m <= 64 vertices; lane k holds its rank su and its row.
-__device__ void run_small(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t row,
-                          uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs, bool anc0)
+__device__ void run_small(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
+                          uint64_t row, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs, bool anc0)
 {
     const uint32_t lane = lane_id();
     const bool valid = lane < m;
@@ -467,7 +490,7 @@ enter : {
         P &= ~(1ull << bb);
         XP |= 1ull << bb;
         uint32_t vb = rl32(su, bb);
-        uint64_t ksc = ks + p.vkey[vb];
+        uint64_t ksc = ks + rl64(skey, bb);
         if (Pc == 0) {
             w.nodes += 1;
             if (XPc == 0 && !xx_any(p, w, L, vb)) {
@@ -596,6 +619,7 @@ __device__ void compact_and_run_small(const Params& p, Wg& w, uint32_t root, con
     bool valid = lane < m;
     uint32_t o = valid ? w.sidx[lane] : 0u;
     uint32_t su = valid ? U[o] : 0u;
+    uint64_t skey = valid ? w.ukey[o] : 0ull;
     uint64_t row = 0;
     for (uint32_t k2 = 0; k2 < m; ++k2) {
         uint32_t o2 = w.sidx[k2];
@@ -606,7 +630,7 @@ __device__ void compact_and_run_small(const Params& p, Wg& w, uint32_t root, con
     uint64_t Ps = __ballot(valid && ((pword >> (o & 63)) & 1ull));
     uint64_t XPs = __ballot(valid && ((xword >> (o & 63)) & 1ull));
     __syncthreads();
-    run_small(p, w, root, m, su, row, Ps, XPs, L, ks, rs, anc);
+    run_small(p, w, root, m, su, skey, row, Ps, XPs, L, ks, rs, anc);
 }
 
 // ---------------------------------------------------------------- mid mode
@@ -670,7 +694,7 @@ enter : {
             XP |= 1ull << bit;
         }
         uint32_t vb = U[bb];
-        uint64_t ksc = ks + p.vkey[vb];
+        uint64_t ksc = ks + w.ukey[bb];
         uint32_t npc = wave_sum((uint32_t)__popcll(Pc));
         uint32_t nxc = wave_sum((uint32_t)__popcll(XPc));
         bool more_here = __ballot(B != 0) != 0;
@@ -739,9 +763,11 @@ __device__ void run_universe(const Params& p, Wg& w, uint32_t root, uint32_t nu,
         uint64_t row = build_small_rows(p, w, w.uarr, nu);
         uint64_t P = w.pw[0], XP = w.xw[0];
         uint32_t su = lane < nu ? w.uarr[lane] : 0u;
-        run_small(p, w, root, nu, su, row, P, XP, L, ks, rs, false);
+        uint64_t skey = lane < nu ? p.vkey[su] : 0ull;
+        run_small(p, w, root, nu, su, skey, row, P, XP, L, ks, rs, false);
         return;
     }
+    for (uint32_t i = lane; i < nu; i += 64) w.ukey[i] = p.vkey[w.uarr[i]];
     const uint32_t W = (nu + 63) >> 6;
     uint64_t* rows;
     uint32_t ws;
@@ -869,6 +895,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.hist = reinterpret_cast<uint32_t*>(l); l += kHistLds * 4;
     w.sidx = reinterpret_cast<uint32_t*>(l); l += 64 * 4;
     w.uarr = reinterpret_cast<uint32_t*>(l); l += ((p.ucap + 1) & ~1u) * 4;
+    w.ukey = reinterpret_cast<uint64_t*>(l); l += (size_t)p.ucap * 8;
     w.lrows = reinterpret_cast<uint64_t*>(l);
     for (uint32_t k = lane; k < (uint32_t)kHistLds; k += 64) w.hist[k] = 0;
     __syncthreads();
@@ -878,6 +905,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.busy_ticks = w.max_task_ticks = w.task_t0 = 0;
     w.hmax = 0;
     w.wl_tick = 0;
+    w.wl_seen = 0;
     w.poll = 0;
     w.me = me;
     w.abort = false;
@@ -885,7 +913,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
 
     const bool use_wl = (p.flags & MCE_F_WORKER_LIST) != 0;
     if (use_wl && lane == 0)
-        __hip_atomic_fetch_add(&p.ctrl->packed, 1ull << 32, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&p.ctrl->packed, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     // phase 1: first-level subtrees from the shared counter
     while (!w.abort) {
@@ -907,26 +935,29 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
             terminate = idle == started;
             if (!terminate) {
                 unsigned long long t =
-                    __hip_atomic_fetch_add(&p.ctrl->ring_tail, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&p.ctrl->ring_tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 uint32_t* slot = &p.ring[t & p.ring_mask];
-                while (__hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != kEmptySlot) {
+                while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kEmptySlot) {
                     if (now_ticks() > w.deadline) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
-                __hip_atomic_store(slot, me, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&p.ctrl->waiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(slot, me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         terminate = uni(terminate);
         if (terminate) {
             for (uint32_t g = lane; g < p.nwg; g += 64)
-                __hip_atomic_store(&p.wflags[g], kFlagTerm, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&p.wflags[g], kFlagTerm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
         uint32_t f = kFlagIdle;
         uint64_t t0 = now_ticks();
         if (lane == 0) {
             uint32_t sleep = 1;
-            while ((f = __hip_atomic_load(&p.wflags[me], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == kFlagIdle) {
+            // poll with relaxed loads (an acquire load would invalidate caches on
+            // every iteration); acquire once below when a task has arrived
+            while ((f = __hip_atomic_load(&p.wflags[me], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kFlagIdle) {
                 if (now_ticks() > w.deadline) break;
                 if (sleep < 32) sleep <<= 1;
                 for (uint32_t s = 0; s < sleep; ++s) __builtin_amdgcn_s_sleep(2);
@@ -1049,7 +1080,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     if (lds_cap < 64) lds_cap = 64;
     const uint32_t ws_l = ((lds_cap + 63) / 64) | 1u;
     size_t lds_bytes = 64 * 8 * 2 + kSmallDepth * (8 * 4 + 4 * 2) + kHistLds * 4 + 64 * 4 +
-                       (size_t)((ucap + 1) & ~1u) * 4 + (size_t)lds_cap * ws_l * 8;
+                       (size_t)((ucap + 1) & ~1u) * 4 + (size_t)ucap * 8 + (size_t)lds_cap * ws_l * 8;
     lds_bytes = align_up(lds_bytes, 16);
     if (lds_bytes > 160 * 1024) {
         set_error("LDS budget exceeded; lower bitmap_max_p");
