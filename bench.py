@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--donate-min-p", type=int, default=0)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-sample-mod", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="launch one elementwise kernel that reads and writes 1 GiB each, as the "
+                         "reference for scaling hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,6 +103,13 @@ def main():
     rp = torch.from_numpy(g.row_ptr.astype(np.int64)).to(torch.int32).cuda()
     ci = torch.from_numpy(g.col_idx.astype(np.int64)).to(torch.int32).cuda()
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration kernel: 1 GiB read + 1 GiB written")
 
     flags = 0
     if args.reverse:
