@@ -49,6 +49,22 @@ def algorithmic_bytes(stats) -> int:
             + 4 * stats["probes"])
 
 
+def measured_traffic(workload: str, c: int):
+    """HBM bytes per launch of k_enumerate from the committed rocprofv3 counter
+    summary, used only when it was taken on the current kernel source and on
+    this workload; otherwise None."""
+    import glob
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2212_01473_amd", "csrc", "enumerate.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "k_enumerate_*_traffic.json")):
+        d = json.load(open(path))
+        if d.get("source_sha256_prefix") == sha and d.get("workload") == f"{workload} c={c}":
+            return d["fetch_bytes"] + d["write_bytes"]
+    return None
+
+
 def cpu_baseline(g, c, frac_mod: int, budget_s: float):
     """The oracle as it stands, on a deterministic sample of roots (input ids
     v with v % frac_mod == 0), all host threads it is given."""
@@ -168,7 +184,8 @@ def main():
                    "workgroups": r.stats["workgroups"], "tree_nodes": r.stats["nodes"],
                    "donations": r.stats["donations"]},
         "roofline": {"bound": "hbm", "kernel": "k_enumerate", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "GB/s", "frac": round(achieved / peak, 5), "traffic": None,
+                     "peak": peak, "unit": "GB/s", "frac": round(achieved / peak, 5),
+                     "traffic": measured_traffic(args.workload, c),
                      "algorithmic_bytes": alg, "avg_kernel_ms": round(kern_ms, 3)},
     }
     if args.cpu_baseline == "on":
