@@ -152,6 +152,10 @@ typedef struct {
     uint64_t* root_count;       /* MCE_F_ROOT_STATS: device uint64[n] by input id, accumulated into */
     uint64_t* root_hash;        /* MCE_F_ROOT_STATS: device uint64[n] */
     uint64_t* root_nodes;       /* MCE_F_ROOT_STATS: device uint64[n] (search-tree nodes) */
+    uint32_t xrow_ratio;        /* build X bitmap rows for a task when |X| <= ratio * max(|P u X_P|, 64);
+                                   0 = default 8; larger X uses lookups in the original graph */
+    uint32_t reserved;
+    uint64_t xrow_budget_words; /* X bitmap rows per workgroup, 64-bit words; 0 = default 2^18 */
 } mce_options;
 
 /* indices into mce_result.stats */
@@ -205,10 +209,14 @@ typedef struct {
 mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res);
 
 /*
- * Enumerate every graph of a batch-loaded handle in one persistent launch
- * over a device-wide (graph, root) queue.  res is an array of n_res >=
- * n_graphs results (res[i] for graph i, same field rules as mce_enumerate;
- * streams are not supported in batch mode).
+ * Enumerate every graph of a batch-loaded handle in one persistent launch.
+ * The batch is held as one disjoint union (its maximal cliques are exactly
+ * those of the member graphs), peeled and oriented once; the work queue holds
+ * (root) entries of all graphs and every result is attributed to the graph of
+ * its root.  res is an array of n_res >= n_graphs results (res[i] for graph i,
+ * same field rules as mce_enumerate).  Streams, per-root statistics and custom
+ * orders are single-graph only.  For a batch handle, peel_round and order of
+ * mce_graph_copy_order refer to the union's peel restricted to the graph.
  */
 mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result* res,
                                uint32_t n_res);

@@ -60,22 +60,27 @@ mce_status load_one(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n
     return preprocess_graph(rp, ci, n, nnz, validate, s, og);
 }
 
-void fill_info(const Oriented& o, uint32_t n_graphs, mce_graph_info* out)
+void fill_info(const Oriented& o, uint32_t idx, mce_graph_info* out)
 {
-    out->n = o.n;
-    out->nnz = o.nnz;
-    out->max_degree = o.max_degree;
-    out->degeneracy = o.degeneracy;
-    out->n_isolated = o.n_isolated;
+    const GraphMeta& m = o.meta[idx];
+    out->n = m.n;
+    out->nnz = m.nnz;
+    out->max_degree = m.max_degree;
+    out->degeneracy = m.degeneracy;
+    out->n_isolated = m.n_isolated;
     out->peel_rounds = o.rounds;
-    out->max_out_degree = o.max_out;
-    out->max_in_degree = o.max_in;
-    out->n_graphs = n_graphs;
+    out->max_out_degree = m.max_out;
+    out->max_in_degree = m.max_in;
+    out->n_graphs = o.ngraphs;
 }
 
 mce_status config_from(const mce_options* opt, EnumConfig& cfg)
 {
     if (!opt) return MCE_OK;
+    if (opt->struct_size == sizeof(mce_options)) {
+        if (opt->xrow_ratio) cfg.xrow_ratio = opt->xrow_ratio;
+        if (opt->xrow_budget_words) cfg.xrow_budget_words = opt->xrow_budget_words;
+    }
     if (opt->struct_size != sizeof(mce_options))
         return fail(MCE_ERR_INVALID_ARG, "mce_options.struct_size must be sizeof(mce_options)");
     cfg.flags = opt->flags;
@@ -93,21 +98,22 @@ mce_status config_from(const mce_options* opt, EnumConfig& cfg)
     return MCE_OK;
 }
 
-mce_status finish_result(const EnumOutput& eo, mce_result* res, mce_status st)
+mce_status finish_result(const EnumOutput& eo, size_t gi, mce_result* res, mce_status st)
 {
-    res->count = eo.count;
-    res->hash = eo.hash;
-    res->max_clique_size = eo.max_size;
+    const EnumOutput::PerGraph& pg = eo.graphs[gi];
+    res->count = pg.count;
+    res->hash = pg.hash;
+    res->max_clique_size = pg.max_size;
     for (int i = 0; i < 16; ++i) res->stats[i] = eo.stats[i];
     res->stream_cliques_written = eo.stream_c < res->stream_ocap ? eo.stream_c : res->stream_ocap;
     res->stream_vertices_written = eo.stream_v < res->stream_vcap ? eo.stream_v : res->stream_vcap;
     if (st != MCE_OK) return st;
     if (res->hist && res->hist_len) {
-        for (uint32_t k = 0; k < res->hist_len; ++k) res->hist[k] = k < eo.hist.size() ? eo.hist[k] : 0;
-        if (res->hist_len < eo.max_size + 1)
+        for (uint32_t k = 0; k < res->hist_len; ++k) res->hist[k] = k < pg.hist.size() ? pg.hist[k] : 0;
+        if (res->hist_len < pg.max_size + 1)
             return fail(MCE_ERR_BUFFER_TOO_SMALL,
                         "hist_len " + std::to_string(res->hist_len) + " < max_clique_size + 1 = " +
-                            std::to_string(eo.max_size + 1));
+                            std::to_string(pg.max_size + 1));
     }
     if (eo.stream_truncated) return MCE_WARN_STREAM_TRUNCATED;
     return MCE_OK;
@@ -146,25 +152,20 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
     *out = nullptr;
     if (!row_ptr_cat || !row_off || !col_off) return fail(MCE_ERR_INVALID_ARG, "NULL batch array");
     if (n_graphs == 0) return fail(MCE_ERR_INVALID_ARG, "n_graphs is 0");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    auto g = std::make_unique<mce_graph>();
-    g->batch = true;
+    if (flags & MCE_LOAD_DEVICE_PTRS) return fail(MCE_ERR_INVALID_ARG, "batch loading takes host arrays");
+    if (flags & ~(MCE_LOAD_NO_VALIDATE)) return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
     for (uint32_t i = 0; i < n_graphs; ++i) {
         if (row_off[i + 1] <= row_off[i] || col_off[i + 1] < col_off[i])
             return fail(MCE_ERR_INVALID_ARG, "batch offsets not increasing at graph " + std::to_string(i));
-        uint64_t nv = row_off[i + 1] - row_off[i] - 1;
-        uint64_t ne = col_off[i + 1] - col_off[i];
-        if (nv >= 0xFFFFFFFFull) return fail(MCE_ERR_INVALID_ARG, "graph too large");
-        if (ne && !col_idx_cat) return fail(MCE_ERR_INVALID_ARG, "col_idx_cat is NULL");
-        g->graphs.emplace_back(new Oriented());
-        uint32_t dummy = 0;
-        mce_status st = load_one(row_ptr_cat + row_off[i], ne ? col_idx_cat + col_off[i] : &dummy, (uint32_t)nv, ne,
-                                 flags, s, *g->graphs.back());
-        if (st != MCE_OK) {
-            set_error("graph " + std::to_string(i) + ": " + get_error());
-            return st;
-        }
     }
+    if (col_off[n_graphs] > col_off[0] && !col_idx_cat) return fail(MCE_ERR_INVALID_ARG, "col_idx_cat is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    auto g = std::make_unique<mce_graph>();
+    g->batch = true;
+    g->graphs.emplace_back(new Oriented());
+    mce_status st = preprocess_batch(row_ptr_cat, col_idx_cat, row_off, col_off, n_graphs,
+                                     (flags & MCE_LOAD_NO_VALIDATE) == 0, s, *g->graphs[0]);
+    if (st != MCE_OK) return st;
     *out = g.release();
     return MCE_OK;
 }
@@ -172,8 +173,9 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
 mce_status mce_graph_get_info(const mce_graph* g, uint32_t graph_idx, mce_graph_info* out)
 {
     if (!g || !out) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
-    if (graph_idx >= g->graphs.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
-    fill_info(*g->graphs[graph_idx], (uint32_t)g->graphs.size(), out);
+    const Oriented& o = *g->graphs[0];
+    if (graph_idx >= o.meta.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
+    fill_info(o, graph_idx, out);
     return MCE_OK;
 }
 
@@ -181,13 +183,25 @@ mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t
                                 uint32_t* order)
 {
     if (!g) return fail(MCE_ERR_INVALID_ARG, "NULL graph");
-    if (graph_idx >= g->graphs.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
-    const Oriented& o = *g->graphs[graph_idx];
-    size_t bytes = (size_t)o.n * 4;
+    const Oriented& o = *g->graphs[0];
+    if (graph_idx >= o.meta.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
+    const GraphMeta& m = o.meta[graph_idx];
+    size_t bytes = (size_t)m.n * 4;
     if (bytes == 0) return MCE_OK;
-    if (core) MCE_HIP_TRY(hipMemcpy(core, o.core.p, bytes, hipMemcpyDeviceToHost));
-    if (peel_round) MCE_HIP_TRY(hipMemcpy(peel_round, o.round.p, bytes, hipMemcpyDeviceToHost));
-    if (order) MCE_HIP_TRY(hipMemcpy(order, o.perm.p, bytes, hipMemcpyDeviceToHost));
+    if (core) MCE_HIP_TRY(hipMemcpy(core, o.core.as<uint32_t>() + m.voff, bytes, hipMemcpyDeviceToHost));
+    if (peel_round) MCE_HIP_TRY(hipMemcpy(peel_round, o.round.as<uint32_t>() + m.voff, bytes, hipMemcpyDeviceToHost));
+    if (order) {
+        if (o.ngraphs == 1) {
+            MCE_HIP_TRY(hipMemcpy(order, o.perm.p, bytes, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<uint32_t> perm(o.n), gid(o.n);
+            MCE_HIP_TRY(hipMemcpy(perm.data(), o.perm.p, (size_t)o.n * 4, hipMemcpyDeviceToHost));
+            MCE_HIP_TRY(hipMemcpy(gid.data(), o.gid.p, (size_t)o.n * 4, hipMemcpyDeviceToHost));
+            size_t k = 0;
+            for (uint32_t r = 0; r < o.n; ++r)
+                if (gid[r] == graph_idx) order[k++] = perm[r] - m.voff;
+        }
+    }
     return MCE_OK;
 }
 
@@ -195,7 +209,7 @@ mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res)
 {
     set_error("");
     if (!g || !res) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
-    if (g->graphs.size() != 1) return fail(MCE_ERR_INVALID_ARG, "batch handle: use mce_enumerate_batch");
+    if (g->batch) return fail(MCE_ERR_INVALID_ARG, "batch handle: use mce_enumerate_batch");
     EnumConfig cfg;
     mce_status st = config_from(opt, cfg);
     if (st != MCE_OK) return st;
@@ -212,14 +226,15 @@ mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res)
     EnumOutput eo;
     st = enumerate_graph(*g->graphs[0], cfg, g->state, s, eo);
     if (st != MCE_OK && st != MCE_ERR_TIMEOUT) return st;
-    return finish_result(eo, res, st);
+    return finish_result(eo, 0, res, st);
 }
 
 mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result* res, uint32_t n_res)
 {
     set_error("");
     if (!g || !res) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
-    if (n_res < g->graphs.size()) return fail(MCE_ERR_INVALID_ARG, "n_res smaller than the number of graphs");
+    const Oriented& o = *g->graphs[0];
+    if (n_res < o.ngraphs) return fail(MCE_ERR_INVALID_ARG, "n_res smaller than the number of graphs");
     EnumConfig cfg;
     mce_status st = config_from(opt, cfg);
     if (st != MCE_OK) return st;
@@ -227,15 +242,17 @@ mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result*
         return fail(MCE_ERR_INVALID_ARG, "stream, per-root statistics and custom order are single-graph only");
     if (cfg.flags & (MCE_F_LEARNED_ORDER | MCE_F_SPLIT))
         return fail(MCE_ERR_UNSUPPORTED, "learned ordering is not available in this build");
+    for (uint32_t i = 0; i < o.ngraphs; ++i)
+        if (res[i].hist_len && !res[i].hist) return fail(MCE_ERR_INVALID_ARG, "hist is NULL with hist_len > 0");
     hipStream_t s = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
+    EnumOutput eo;
+    st = enumerate_graph(o, cfg, g->state, s, eo);
+    if (st != MCE_OK && st != MCE_ERR_TIMEOUT) return st;
     mce_status worst = MCE_OK;
-    for (size_t i = 0; i < g->graphs.size(); ++i) {
-        EnumOutput eo;
-        st = enumerate_graph(*g->graphs[i], cfg, g->state, s, eo);
-        if (st != MCE_OK && st != MCE_ERR_TIMEOUT) return st;
-        st = finish_result(eo, &res[i], st);
-        if (st < 0) return st;
-        if (st != MCE_OK) worst = st;
+    for (uint32_t i = 0; i < o.ngraphs; ++i) {
+        mce_status si = finish_result(eo, i, &res[i], st);
+        if (si < 0 && worst >= 0) worst = si;
+        else if (si > 0 && worst == MCE_OK) worst = si;
     }
     return worst;
 }

@@ -3,32 +3,36 @@
 // One wavefront (64 lanes) owns one task at a time and explores it depth-first
 // (Section III-A): Bron-Kerbosch with pivoting (Algorithm 2) below a
 // first-level subtree of Algorithm 3.  A task is (R, P, X_P, X_X):
-//   * U = P u X_P, the vertices whose adjacency is kept as bitmap rows over U --
-//     the partial induced subgraph of Section III-D (edges among P; for a
-//     root task U = P = the later neighbours of the root);
-//   * X_X, the part of X that came from the root's earlier neighbours, kept as
-//     one array shrunk in place across levels with per-level end pointers
-//     (Section III-E, Fig. 2); adjacency of an X_X vertex x to a branch vertex
-//     b is looked up in the original graph (x precedes b, so b is searched in
-//     the sorted later-neighbour list of x);
-//   * the pivot maximises |P n N(u)| over u in P u X_P (Section III-E, last
-//     paragraph: X_X vertices are not pivot candidates under partial induced
-//     subgraphs).
-// Work distribution (Section III-C): phase 1 pops roots from a shared counter;
-// in phase 2 idle wavefronts enter a worker list (MPMC ring of workgroup ids)
-// and busy ones donate branches to them.
+//   * U = P u X_P, the vertices whose mutual adjacency is kept as bitmap rows
+//     over U -- the partial induced subgraph of Section III-D (for a root task
+//     U = P = the later neighbours of the root);
+//   * X_X, the part of X that came from the task's initial X (for a root: its
+//     earlier neighbours).  It only shrinks with depth, so it is one index list
+//     partitioned in place with per-level end pointers (Section III-E, Fig. 2).
+//     Its adjacency to U is either looked up in the original graph (binary
+//     search in the sorted later-neighbour list of the X vertex) or, when the
+//     task is small enough, read from per-task bitmap rows "X rows" built once
+//     at task start (the full induced subgraph of Section III-D, restricted to
+//     X x U);
+//   * pivots maximise |P n N(u)| (Tomita); candidates are P u X_P, plus the
+//     X_X vertices once they are folded into registers (below).
 //
-// Two representations of the bitmap state:
-//   * mid mode (|U| > 64): W = ceil(|U|/64) words per set, lane w holds word w
-//     of P, X_P and the remaining-branch set B; rows live in LDS when |U| fits
-//     the launch's LDS budget, otherwise in per-workgroup HBM scratch; the
-//     per-level stack lives in HBM scratch;
-//   * small mode (|U'| <= 64, reached by re-indexing P u X_P of a node): lane k
-//     holds the 64-bit row of local vertex k in registers and P, X_P, B are
-//     single wave-uniform words; the stack is in LDS.
+// Three executors share the search:
+//   mid    |P u X_P| > 64: W = ceil(|U|/64) words per set, lane w holds word w
+//          of P, X_P and of the remaining-branch set; bitmap rows in LDS (or
+//          per-workgroup HBM scratch above the LDS budget); stack in HBM.
+//   list   |P u X_P| <= 64 with a long X_X: lane k holds the 64-bit row of
+//          local vertex k; P, X_P, branches are wave-uniform words; X_X stays
+//          an index list; stack in LDS.
+//   folded |P u X_P| <= 64 and |X_X| <= 64 with X rows available: the X_X
+//          vertices get register rows too, so the search touches no memory
+//          except its LDS stack, and X_X vertices are pivot candidates.
+//
+// Work distribution (Section III-C): phase 1 pops (root, split) entries from
+// a shared counter; phase 2 is the worker list: idle workgroups wait in an
+// MPMC ring, busy ones hand branches to them.  Results accumulate per graph
+// (several graphs are enumerated as one disjoint union in batched mode).
 #include "mce_internal.h"
-
-#include <chrono>
 
 namespace mce {
 
@@ -37,8 +41,8 @@ namespace {
 constexpr uint32_t kFlagIdle = 0u, kFlagTask = 1u, kFlagTerm = 2u;
 constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
 constexpr int kHistLds = 256;
-constexpr int kSmallDepth = 66;
-constexpr uint32_t kMaxUniverse = 4096;  // W <= 64 words per bitmap row
+constexpr int kDepth = 66;                 // register-mode stack levels (universe <= 64)
+constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
 struct Ctrl {
     unsigned long long packed;     // started << 32 | idle
@@ -47,17 +51,17 @@ struct Ctrl {
     unsigned long long stream_v;
     unsigned long long stream_c;
     unsigned int root_cursor;
-    unsigned int err;              // 1 = timeout, 2 = internal limit
+    unsigned int err;              // 1 = timeout
     unsigned int stream_trunc;
     unsigned int waiting;          // workgroups currently in the worker list
     unsigned int pad[4];
 };
 
 struct MboxHdr {
-    uint32_t root;     // root rank (per-root statistics)
+    uint32_t root;     // root rank (graph and per-root attribution)
     uint32_t rsize;    // |R|
     uint64_t keysum;   // sum of keys of R (mod 2^64)
-    uint32_t np, nxp, nxx, anc;
+    uint32_t np, nxp, nxx, pad;
 };
 
 struct Params {
@@ -67,15 +71,21 @@ struct Params {
     const uint32_t* ic;
     const uint64_t* vkey;
     const uint32_t* perm;
+    const uint32_t* gid;       // graph of each rank, or null (one graph)
     const uint32_t* roots;
+    const uint32_t* splits;    // (C << 16) | c per queue entry, or null
     uint32_t nroots;
     Ctrl* ctrl;
-    unsigned long long* acc;
-    unsigned long long* hist;
+    unsigned long long* acc;   // kernel-wide statistics
+    unsigned long long* gacc;  // per graph: count, hash
+    unsigned long long* ghist; // per graph: histogram of hist_len entries
     uint32_t hist_len;
     uint8_t* scratch;
     uint64_t stride;
-    uint64_t off_P, off_XP, off_R, off_xx, off_flag, off_hpos, off_spos, off_rows, off_stack, off_meta;
+    uint64_t off_P, off_XP, off_R, off_xr, off_xx, off_flag, off_hpos, off_spos, off_rows, off_xrows, off_stack,
+        off_meta;
+    uint64_t xrow_budget;      // words of X rows per workgroup
+    uint32_t xrow_ratio;       // build X rows when |X| <= ratio * max(|U|, 64)
     uint32_t* ring;
     uint32_t ring_mask;
     uint32_t* wflags;
@@ -95,7 +105,6 @@ struct Params {
 
 // ---------------------------------------------------------------- wave helpers
 __device__ inline uint32_t lane_id() { return __lane_id(); }
-
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline uint64_t uni64(uint64_t v)
 {
@@ -120,14 +129,14 @@ __device__ inline uint32_t prefix_popc(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
-// Row rotation through DPP (row_ror:N, N = 1..15, rows of 16 lanes).
+// Row rotation through DPP (row_ror:N within rows of 16 lanes).
 template <int N>
 __device__ inline uint32_t row_ror(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + N, 0xF, 0xF, false);
 }
-// Wave-wide sum / max: reduce each 16-lane row with DPP rotations, then
-// combine the four rows through readlane (no LDS round trips).
+// Wave-wide sum / max: DPP rotations inside each 16-lane row, then readlane
+// across the four rows (no LDS round trips).
 __device__ inline uint32_t wave_sum(uint32_t v)
 {
     v += row_ror<1>(v);
@@ -155,7 +164,7 @@ __device__ inline uint32_t wave_excl_scan(uint32_t v)
     }
     return x - v;
 }
-// Cross-lane visibility of global/LDS stores within the (single-wave) workgroup.
+// Cross-lane visibility of global/LDS stores within the single-wave workgroup.
 __device__ inline void wave_mem_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -171,92 +180,116 @@ __device__ inline uint64_t fmix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// ---------------------------------------------------------------- per-workgroup context
+__device__ inline uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
+
+// ---------------------------------------------------------------- per-workgroup state
+// Statistics counters kept in LDS (updated by lane 0) to spare scalar registers.
+enum : int {
+    S_NODES = 0, S_DONATIONS, S_TASKS, S_XTESTS, S_EDGES, S_HBM, S_IDLE, S_ROOTW, S_XROW, S_BUSY, S_MAXTASK,
+    S_CTASK, S_HTASK, S_PENDING, S_COUNT
+};
+
+// Fixed-size LDS of a workgroup (static offsets: no pointer registers).
+struct LdsFixed {
+    uint64_t pw[64], xw[64];
+    uint64_t lP[kDepth], lXP[kDepth], lB[kDepth], lK[kDepth];  // list-mode stack
+    uint64_t fP[kDepth], fXP[kDepth], fXX[kDepth], fB[kDepth], fK[kDepth];  // folded-mode stack
+    uint64_t stat[S_COUNT + 2];
+    uint32_t lL[kDepth], lA[kDepth], fA[kDepth];
+    uint32_t hist[kHistLds];
+    uint32_t sidx[64], soff[64], sbeg[64];
+};
+__shared__ LdsFixed S;
+
+__device__ inline void stat_add(int k, uint64_t v)
+{
+    if (__lane_id() == 0) S.stat[k] += v;
+}
+
 struct Wg {
-    // global scratch
+    // HBM scratch
     MboxHdr* mbox;
-    uint32_t* mP;
-    uint32_t* mXP;
-    uint32_t* R;
-    uint32_t* xx;
+    uint32_t* mP;      // mailbox P ranks
+    uint32_t* mXP;     // mailbox X_P ranks
+    uint32_t* R;       // ranks of R
+    uint32_t* xr;      // the task's initial X_X ranks (mailbox target)
+    uint32_t* xx;      // X_X as indices into xr, partitioned in place
     uint64_t* xflag;
     uint32_t* hpos;
     uint32_t* spos;
     uint64_t* grows;
+    uint64_t* xrows;
     uint64_t* gstack;
     uint64_t* gmeta;
-    // LDS
-    uint32_t* hist;   // kHistLds
-    uint32_t* sidx;   // 64
-    uint64_t* pw;     // 64
-    uint64_t* xw;     // 64
-    uint64_t* sP;     // kSmallDepth
-    uint64_t* sXP;
-    uint64_t* sB;
-    uint64_t* sK;
-    uint32_t* sL;
-    uint32_t* sA;
-    uint32_t* uarr;   // ucap
-    uint64_t* ukey;   // ucap: key of each universe vertex
-    uint64_t* lrows;  // lds_cap * ws_lds
+    // LDS sized per launch
+    uint32_t* uarr;
+    uint64_t* ukey;
+    uint64_t* lrows;
+    // current task
+    uint32_t W;         // words of the task's universe
+    bool have_xrows;
     // accumulators (wave-uniform)
-    uint64_t count, hash, nodes, donations, tasks, xtests, edges, hbm_tasks, idle_ticks, root_list_words;
-    uint64_t busy_ticks, max_task_ticks, task_t0;
-    uint32_t probes;  // per lane
+    uint64_t count, hash;   // since the last per-graph flush
+    uint32_t cur_gid;
     uint32_t hmax;
-    uint32_t wl_tick;
-    uint32_t wl_seen;
-    uint32_t poll;
+    uint64_t task_t0;
+    uint32_t probes;  // per lane
+    uint32_t wl_tick, wl_seen, poll;
     uint64_t deadline;
     uint32_t me;
     bool abort;
 };
 
 // Is b among the later neighbours of x?  (x precedes b in the order.)
-// probes counts the list entries read.
 __device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b, uint32_t& probes)
 {
     uint32_t lo = p.op[x], hi = p.op[x + 1];
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
-        uint32_t w = p.oc[mid];
+        uint32_t v = p.oc[mid];
         ++probes;
-        if (w == b) return true;
-        if (w < b) lo = mid + 1;
+        if (v == b) return true;
+        if (v < b) lo = mid + 1;
         else hi = mid;
     }
     return false;
 }
 
-// Any X_X vertex in xx[0, L) adjacent to b?
-__device__ bool xx_any(const Params& p, Wg& w, uint32_t L, uint32_t b)
+// Adjacency of X_X entry j (index into xr) to the universe vertex with index
+// bidx and rank brank.
+__device__ inline bool xtest(const Params& p, Wg& w, uint32_t j, uint32_t bidx, uint32_t brank)
+{
+    if (w.have_xrows) return (w.xrows[(uint64_t)j * w.W + (bidx >> 6)] >> (bidx & 63)) & 1ull;
+    return has_later(p, w.xr[j], brank, w.probes);
+}
+
+__device__ __forceinline__ bool xx_any(const Params& p, Wg& w, uint32_t L, uint32_t bidx, uint32_t brank)
 {
     const uint32_t lane = lane_id();
     for (uint32_t base = 0; base < L; base += 64) {
         uint32_t i = base + lane;
-        bool hit = i < L && has_later(p, w.xx[i], b, w.probes);
-        w.xtests += min(64u, L - base);
+        bool hit = i < L && xtest(p, w, w.xx[i], bidx, brank);
+        stat_add(S_XTESTS, min(64u, L - base));
         if (__ballot(hit)) return true;
     }
     return false;
 }
 
-// Partition xx[0, L): vertices adjacent to b move to [0, K), the rest to
-// [K, L) (Section III-E: the array keeps every level's X_X as a prefix).
-// Returns K.  Only the misplaced elements move (holes in [0,K) are swapped
-// with kept elements in [K,L)).
-__device__ uint32_t xx_partition(const Params& p, Wg& w, uint32_t L, uint32_t b)
+// Partition xx[0, L): entries adjacent to b move to [0, K), the rest to
+// [K, L), so every level's X_X stays a prefix (Section III-E).  Only
+// misplaced entries move: holes in [0, K) swap with kept entries in [K, L).
+__device__ __forceinline__ uint32_t xx_partition(const Params& p, Wg& w, uint32_t L, uint32_t bidx, uint32_t brank)
 {
     const uint32_t lane = lane_id();
     uint32_t K = 0;
     for (uint32_t base = 0; base < L; base += 64) {
         uint32_t i = base + lane;
-        bool keep = i < L && has_later(p, w.xx[i], b, w.probes);
+        bool keep = i < L && xtest(p, w, w.xx[i], bidx, brank);
         uint64_t m = __ballot(keep);
         if (lane == 0) w.xflag[base >> 6] = m;
         K += (uint32_t)__popcll(m);
     }
-    w.xtests += L;
+    stat_add(S_XTESTS, L);
     if (K == 0 || K == L) return K;
     wave_mem_sync();
     uint32_t nh = 0;
@@ -288,15 +321,43 @@ __device__ uint32_t xx_partition(const Params& p, Wg& w, uint32_t L, uint32_t b)
     return K;
 }
 
+// ---------------------------------------------------------------- results
+__device__ void flush_graph(const Params& p, Wg& w)
+{
+    const uint32_t lane = lane_id();
+    if (lane == 0 && (w.count | w.hash)) {
+        atomicAdd(&p.gacc[2 * w.cur_gid], (unsigned long long)w.count);
+        atomicAdd(&p.gacc[2 * w.cur_gid + 1], (unsigned long long)w.hash);
+    }
+    uint32_t top = min(w.hmax + 1, (uint32_t)kHistLds);
+    wave_mem_sync();
+    unsigned long long* gh = p.ghist + (uint64_t)w.cur_gid * p.hist_len;
+    for (uint32_t k = lane; k < top; k += 64) {
+        uint32_t c = S.hist[k];
+        if (c) {
+            atomicAdd(&gh[k], (unsigned long long)c);
+            S.hist[k] = 0;
+        }
+    }
+    wave_mem_sync();
+    w.count = w.hash = 0;
+    w.hmax = 0;
+}
+
 __device__ void report(const Params& p, Wg& w, uint32_t rsize, uint64_t ks)
 {
+    uint64_t h = fmix64(ks + (uint64_t)rsize * kGamma);
     w.count += 1;
-    w.hash += fmix64(ks + (uint64_t)rsize * kGamma);
+    w.hash += h;
+    if (p.flags & MCE_F_ROOT_STATS) {
+        stat_add(S_CTASK, 1);
+        stat_add(S_HTASK, h);
+    }
     w.hmax = max(w.hmax, rsize);
     const uint32_t lane = lane_id();
     if (lane == 0) {
-        if (rsize < (uint32_t)kHistLds) w.hist[rsize] += 1;
-        else atomicAdd(&p.hist[rsize < p.hist_len ? rsize : p.hist_len - 1], 1ull);
+        if (rsize < (uint32_t)kHistLds) S.hist[rsize] += 1;
+        else atomicAdd(&p.ghist[(uint64_t)w.cur_gid * p.hist_len + min(rsize, p.hist_len - 1)], 1ull);
     }
     if (p.flags & MCE_F_STREAM) {
         unsigned long long c = 0, v = 0;
@@ -307,29 +368,13 @@ __device__ void report(const Params& p, Wg& w, uint32_t rsize, uint64_t ks)
         c = uni64(c);
         v = uni64(v);
         bool fits = v + rsize <= p.s_vcap;
-        if (fits) {
+        if (fits)
             for (uint32_t j = lane; j < rsize; j += 64) p.s_verts[v + j] = p.perm[w.R[j]];
-        }
         if (lane == 0) {
             if (c < p.s_ocap) p.s_offs[c] = fits ? ((v << 16) | rsize) : ~0ull;
             if (!fits || c >= p.s_ocap) p.ctrl->stream_trunc = 1;
         }
     }
-}
-
-__device__ inline void flush_hist(const Params& p, Wg& w)
-{
-    uint32_t top = min(w.hmax + 1, (uint32_t)kHistLds);
-    __syncthreads();
-    for (uint32_t k = lane_id(); k < top; k += 64) {
-        uint32_t c = w.hist[k];
-        if (c) {
-            atomicAdd(&p.hist[k], (unsigned long long)c);
-            w.hist[k] = 0;
-        }
-    }
-    __syncthreads();
-    w.hmax = 0;
 }
 
 __device__ inline bool check_deadline(const Params& p, Wg& w)
@@ -343,45 +388,6 @@ __device__ inline bool check_deadline(const Params& p, Wg& w)
 }
 
 // ---------------------------------------------------------------- worker list
-// Pop an idle workgroup id (or kEmptySlot).  Lane 0 acts; result broadcast.
-__device__ uint32_t wl_try_pop(const Params& p, Wg& w)
-{
-    uint32_t r = kEmptySlot;
-    if (lane_id() == 0) {
-        // The ring carries only workgroup ids, so every access here is relaxed;
-        // the task itself is published with release/acquire on the receiver's flag.
-        unsigned long long h = __hip_atomic_load(&p.ctrl->ring_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long t = __hip_atomic_load(&p.ctrl->ring_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (h < t) {
-            if (__hip_atomic_compare_exchange_strong(&p.ctrl->ring_head, &h, h + 1, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                uint32_t* slot = &p.ring[h & p.ring_mask];
-                uint32_t v;
-                // the pusher has claimed this slot and stores its id imminently
-                while ((v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmptySlot) {
-                    if (now_ticks() > w.deadline) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (v != kEmptySlot) {
-                    __hip_atomic_store(slot, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(&p.ctrl->waiting, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                r = v;
-            }
-        }
-    }
-    return uni(r);
-}
-
-// Number of waiting workgroups as read at the previous check: the load issued
-// now is consumed at the next check, so its latency overlaps the search.
-__device__ inline bool wl_has_waiting(const Params& p, Wg& w)
-{
-    uint32_t prev = w.wl_seen;
-    w.wl_seen = __hip_atomic_load(&p.ctrl->waiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return uni(prev) != 0;
-}
-
 __device__ inline Wg wg_view(const Params& p, uint32_t g)
 {
     Wg w;
@@ -390,11 +396,44 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
     w.mP = reinterpret_cast<uint32_t*>(base + p.off_P);
     w.mXP = reinterpret_cast<uint32_t*>(base + p.off_XP);
     w.R = reinterpret_cast<uint32_t*>(base + p.off_R);
-    w.xx = reinterpret_cast<uint32_t*>(base + p.off_xx);
+    w.xr = reinterpret_cast<uint32_t*>(base + p.off_xr);
     return w;
 }
 
-// Should this branch be handed to an idle workgroup (Section III-C)?
+// Pop an idle workgroup id (or kEmptySlot).  The ring only carries ids, so all
+// accesses are relaxed; the task is published with release/acquire on the
+// receiver's flag.
+__device__ uint32_t wl_try_pop(const Params& p, Wg& w)
+{
+    uint32_t r = kEmptySlot;
+    if (lane_id() == 0) {
+        unsigned long long h = __hip_atomic_load(&p.ctrl->ring_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long t = __hip_atomic_load(&p.ctrl->ring_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < t && __hip_atomic_compare_exchange_strong(&p.ctrl->ring_head, &h, h + 1, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            uint32_t* slot = &p.ring[h & p.ring_mask];
+            uint32_t v;
+            // the pusher has claimed this slot and stores its id imminently
+            while ((v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmptySlot) {
+                if (now_ticks() > w.deadline) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (v != kEmptySlot) {
+                __hip_atomic_store(slot, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&p.ctrl->waiting, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the receiver stops counting as idle before it is handed work
+                __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            r = v;
+        }
+    }
+    return uni(r);
+}
+
+// Should this branch be offered to an idle workgroup (Section III-C)?  Only
+// branches with |P| >= donate_min_p, with unexplored siblings at this level and
+// unexplored branches at an earlier level.  The waiting count read here was
+// loaded at the previous check, so its latency overlaps the search.
 __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child, bool more_here, bool anc,
                                        uint32_t depth)
 {
@@ -402,98 +441,86 @@ __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child
     if (np_child < p.donate_min_p || !more_here || !anc) return false;
     if (p.donate_max_depth && depth > p.donate_max_depth) return false;
     if ((++w.wl_tick & 3u) != 0) return false;
-    return wl_has_waiting(p, w);
+    uint32_t prev = w.wl_seen;
+    w.wl_seen = __hip_atomic_load(&p.ctrl->waiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return uni(prev) != 0;
 }
 
-// Write a task into receiver r's mailbox.  P / X_P given as (id list writer)
-// callbacks are replaced by explicit arrays filled by the caller before.
-__device__ void send_task(const Params& p, Wg& w, uint32_t r, uint32_t root, uint32_t rsize, uint64_t ks,
-                          uint32_t np, uint32_t nxp, uint32_t nxx, uint32_t vb)
+// Finish a donation to r: R (this workgroup's R[0, rs) plus vb), header, one
+// release fence, then the flag.  P, X_P and X_X were written by the caller.
+__device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
+                             uint64_t ks, uint32_t np, uint32_t nxp, uint32_t nxx)
 {
     const uint32_t lane = lane_id();
     Wg d = wg_view(p, r);
-    // P and X_P ids were staged in this workgroup's own mailbox arrays (free while busy)
-    for (uint32_t i = lane; i < np; i += 64) d.mP[i] = w.mP[i];
-    for (uint32_t i = lane; i < nxp; i += 64) d.mXP[i] = w.mXP[i];
-    for (uint32_t i = lane; i < nxx; i += 64) d.xx[i] = w.xx[i];
-    for (uint32_t i = lane; i + 1 < rsize; i += 64) d.R[i] = w.R[i];
+    for (uint32_t i = lane; i < rs; i += 64) d.R[i] = w.R[i];
     if (lane == 0) {
-        d.R[rsize - 1] = vb;
+        d.R[rs] = vb;
         MboxHdr h;
         h.root = root;
-        h.rsize = rsize;
+        h.rsize = rs + 1;
         h.keysum = ks;
         h.np = np;
         h.nxp = nxp;
         h.nxx = nxx;
-        h.anc = 0;
+        h.pad = 0;
         *d.mbox = h;
     }
-    // publish the mailbox: one release fence, then the flag
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) __hip_atomic_store(&p.wflags[r], kFlagTask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    w.donations += 1;
+    stat_add(S_DONATIONS, 1);
 }
 
-// Try to donate; returns true when the branch was handed over.  The caller has
-// already partitioned X_X for the child (its first nxx entries of xx).
-__device__ bool try_donate(const Params& p, Wg& w, uint32_t root, uint32_t rsize, uint64_t ks, uint32_t np,
-                           uint32_t nxp, uint32_t nxx, uint32_t vb)
-{
-    uint32_t r = wl_try_pop(p, w);
-    if (r == kEmptySlot) return false;
-    // the receiver stops counting as idle before it is handed work
-    if (lane_id() == 0) __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    send_task(p, w, r, root, rsize, ks, np, nxp, nxx, vb);
-    return true;
-}
-
-// ---------------------------------------------------------------- small mode
-// Universe of m <= 64 vertices; lane k holds its rank su and its row.
-__device__ void run_small(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
-                          uint64_t row, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs, bool anc0)
+// ---------------------------------------------------------------- folded executor
+// P-universe of m <= 64 vertices (lane k: rank su, key skey, rowP over the
+// P-universe, rowX over the folded X set); folded X set of up to 64 vertices
+// (lane j: rank xrank, xrowP = its adjacency over the P-universe).
+__device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
+                           uint64_t rowP, uint64_t rowX, uint64_t xrowP, uint32_t xrank, uint64_t P, uint64_t XP,
+                           uint64_t XX, uint64_t ks, uint32_t rs, bool anc)
 {
     const uint32_t lane = lane_id();
     const bool valid = lane < m;
     uint32_t depth = 0;
     uint64_t B;
-    bool anc = anc0;
-    // enter node (P != 0)
 enter : {
-    w.nodes += 1;
-    uint64_t cand = P | XP;
+    stat_add(S_NODES, 1);
+    uint64_t cp = P | XP;
     uint32_t key = 0;
-    if (valid && ((cand >> lane) & 1ull)) key = ((uint32_t)__popcll(P & row) << 8) | (255u - lane);
+    if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
+    if ((XX >> lane) & 1ull) key = max(key, ((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane));
     uint32_t best = wave_max(key);
-    uint32_t piv = 255u - (best & 255u);
-    B = P & ~rl64(row, piv);
+    uint32_t idx = 255u - (best & 255u);
+    uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
+    B = P & ~rowpiv;
 }
     while (true) {
         if (B == 0) {
             if (depth == 0) return;
             --depth;
-            P = w.sP[depth];
-            XP = w.sXP[depth];
-            B = w.sB[depth];
-            ks = w.sK[depth];
-            L = w.sL[depth];
-            anc = w.sA[depth] != 0;
+            P = S.fP[depth];
+            XP = S.fXP[depth];
+            XX = S.fXX[depth];
+            B = S.fB[depth];
+            ks = S.fK[depth];
+            anc = S.fA[depth] != 0;
             --rs;
             continue;
         }
-        if ((++w.poll & 1023u) == 0 && check_deadline(p, w)) return;
+        if ((++w.poll & 4095u) == 0 && check_deadline(p, w)) return;
         uint32_t bb = (uint32_t)__builtin_ctzll(B);
         B &= B - 1;
-        uint64_t rowb = rl64(row, bb);
-        uint64_t Pc = P & rowb;
-        uint64_t XPc = XP & rowb;
+        uint64_t rp = rl64(rowP, bb);
+        uint64_t Pc = P & rp;
+        uint64_t XPc = XP & rp;
+        uint64_t XXc = XX & rl64(rowX, bb);
         P &= ~(1ull << bb);
         XP |= 1ull << bb;
         uint32_t vb = rl32(su, bb);
         uint64_t ksc = ks + rl64(skey, bb);
         if (Pc == 0) {
-            w.nodes += 1;
-            if (XPc == 0 && !xx_any(p, w, L, vb)) {
+            stat_add(S_NODES, 1);
+            if ((XPc | XXc) == 0) {
                 if (p.flags & MCE_F_STREAM) {
                     if (lane == 0) w.R[rs] = vb;
                     wave_mem_sync();
@@ -502,25 +529,155 @@ enter : {
             }
             continue;
         }
-        uint32_t Lc = xx_partition(p, w, L, vb);
         uint32_t npc = (uint32_t)__popcll(Pc);
         if (donation_wanted(p, w, npc, B != 0, anc || depth > 0, depth)) {
-            // stage ids of P' and X_P' in the own mailbox arrays
-            uint32_t nxc = (uint32_t)__popcll(XPc);
-            if (valid && ((Pc >> lane) & 1ull)) w.mP[prefix_popc(Pc)] = su;
-            if (valid && ((XPc >> lane) & 1ull)) w.mXP[prefix_popc(XPc)] = su;
-            wave_mem_sync();
-            if (try_donate(p, w, root, rs + 1, ksc, npc, nxc, Lc, vb)) continue;
+            uint32_t r = wl_try_pop(p, w);
+            if (r != kEmptySlot) {
+                Wg d = wg_view(p, r);
+                if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
+                if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
+                if ((XXc >> lane) & 1ull) d.xr[prefix_popc(XXc)] = xrank;
+                publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), (uint32_t)__popcll(XXc));
+                continue;
+            }
         }
-        // push current level, descend
         if (lane == 0) {
-            w.sP[depth] = P;
-            w.sXP[depth] = XP;
-            w.sB[depth] = B;
-            w.sK[depth] = ks;
-            w.sL[depth] = L;
-            w.sA[depth] = anc ? 1u : 0u;
+            S.fP[depth] = P;
+            S.fXP[depth] = XP;
+            S.fXX[depth] = XX;
+            S.fB[depth] = B;
+            S.fK[depth] = ks;
+            S.fA[depth] = anc ? 1u : 0u;
             w.R[rs] = vb;
+        }
+        anc = anc || (B != 0);
+        ++depth;
+        ++rs;
+        P = Pc;
+        XP = XPc;
+        XX = XXc;
+        ks = ksc;
+        goto enter;
+    }
+}
+
+// Fold X_X (xx[0, L), L <= 64) into registers and run the folded executor.
+// oidx: lane k's index in the task universe (X rows are over that universe).
+__device__ __forceinline__ void fold_and_run(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
+                             uint32_t oidx, uint64_t rowP, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks,
+                             uint32_t rs, bool anc)
+{
+    const uint32_t lane = lane_id();
+    const bool vx = lane < L;
+    const uint32_t xj = vx ? w.xx[lane] : 0u;
+    const uint32_t xrank = vx ? w.xr[xj] : 0u;
+    uint64_t xrowP = 0;
+    if (L) {
+        if (w.W == 1) {
+            // the small universe is the task universe itself (oidx = lane)
+            xrowP = vx ? w.xrows[xj] : 0ull;
+        } else {
+            const uint64_t* xrow = w.xrows + (uint64_t)xj * w.W;
+            for (uint32_t k = 0; k < m; ++k) {
+                uint32_t ok = rl32(oidx, k);
+                if (vx && ((xrow[ok >> 6] >> (ok & 63)) & 1ull)) xrowP |= 1ull << k;
+            }
+        }
+    }
+    uint64_t rowX = 0;
+    for (uint32_t j = 0; j < L; ++j) {
+        uint64_t wj = rl64(xrowP, j);
+        if ((wj >> lane) & 1ull) rowX |= 1ull << j;
+    }
+    run_folded(p, w, root, m, su, skey, rowP, rowX, xrowP, xrank, P, XP, low_mask(L), ks, rs, anc);
+}
+
+// ---------------------------------------------------------------- list executor
+// P-universe of m <= 64 vertices in registers; X_X stays the index list.
+// (c, C): at depth 0 descend only into branches t with t % C == c.
+__device__ __forceinline__ void run_list(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
+                         uint32_t oidx, uint64_t rowP, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks,
+                         uint32_t rs, bool anc, uint32_t c, uint32_t C)
+{
+    const uint32_t lane = lane_id();
+    const bool valid = lane < m;
+    const bool can_fold = w.have_xrows;
+    uint32_t depth = 0, t0 = 0;
+    uint64_t B;
+enter : {
+    stat_add(S_NODES, 1);
+    uint64_t cp = P | XP;
+    uint32_t key = 0;
+    if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
+    uint32_t best = wave_max(key);
+    uint32_t piv = 255u - (best & 255u);
+    B = P & ~rl64(rowP, piv);
+}
+    while (true) {
+        if (B == 0) {
+            if (depth == 0) return;
+            --depth;
+            P = S.lP[depth];
+            XP = S.lXP[depth];
+            B = S.lB[depth];
+            ks = S.lK[depth];
+            L = S.lL[depth];
+            anc = S.lA[depth] != 0;
+            --rs;
+            continue;
+        }
+        if ((++w.poll & 1023u) == 0 && check_deadline(p, w)) return;
+        uint32_t bb = (uint32_t)__builtin_ctzll(B);
+        B &= B - 1;
+        uint64_t rp = rl64(rowP, bb);
+        uint64_t Pc = P & rp;
+        uint64_t XPc = XP & rp;
+        P &= ~(1ull << bb);
+        XP |= 1ull << bb;
+        if (depth == 0 && C > 1) {
+            if ((t0++ % C) != c) continue;
+        }
+        uint32_t vb = rl32(su, bb);
+        uint32_t bidx = rl32(oidx, bb);
+        uint64_t ksc = ks + rl64(skey, bb);
+        if (Pc == 0) {
+            stat_add(S_NODES, 1);
+            if (XPc == 0 && !xx_any(p, w, L, bidx, vb)) {
+                if (p.flags & MCE_F_STREAM) {
+                    if (lane == 0) w.R[rs] = vb;
+                    wave_mem_sync();
+                }
+                report(p, w, rs + 1, ksc);
+            }
+            continue;
+        }
+        uint32_t Lc = xx_partition(p, w, L, bidx, vb);
+        uint32_t npc = (uint32_t)__popcll(Pc);
+        if (donation_wanted(p, w, npc, B != 0, anc || depth > 0, depth)) {
+            uint32_t r = wl_try_pop(p, w);
+            if (r != kEmptySlot) {
+                Wg d = wg_view(p, r);
+                if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
+                if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
+                for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), Lc);
+                continue;
+            }
+        }
+        if (lane == 0) w.R[rs] = vb;
+        if (Lc <= 64 && (can_fold || Lc == 0)) {
+            wave_mem_sync();
+            fold_and_run(p, w, root, m, su, skey, oidx, rowP, Pc, XPc, Lc, ksc, rs + 1, anc || (B != 0));
+            if (w.abort) return;
+            continue;
+        }
+        if (lane == 0) {
+            S.lP[depth] = P;
+            S.lXP[depth] = XP;
+            S.lB[depth] = B;
+            S.lK[depth] = ks;
+            S.lL[depth] = L;
+            S.lA[depth] = anc ? 1u : 0u;
         }
         anc = anc || (B != 0);
         ++depth;
@@ -533,118 +690,59 @@ enter : {
     }
 }
 
-// ---------------------------------------------------------------- bitmap rows
-// Build rows over U[0, nu) (sorted ranks) at row stride ws words: bit j of row i
-// is set iff U[i] and U[j] are adjacent.  rows is LDS or HBM.
-__device__ void build_rows(const Params& p, Wg& w, const uint32_t* U, uint32_t nu, uint32_t ws, uint64_t* rows)
+// ---------------------------------------------------------------- mid executor
+// Re-index a node whose P u X_P has at most 64 vertices into registers and run
+// it with the folded or the list executor.
+__device__ __forceinline__ void compact_and_run(const Params& p, Wg& w, uint32_t root, const uint64_t* rows, uint32_t ws,
+                                uint64_t Pc, uint64_t XPc, uint32_t L, uint64_t ks, uint32_t rs, bool anc)
 {
     const uint32_t lane = lane_id();
-    for (uint32_t i = lane; i < nu * ws; i += 64) rows[i] = 0;
-    wave_mem_sync();
-    const uint32_t umax = U[nu - 1];
-    for (uint32_t i = 0; i + 1 < nu; ++i) {
-        uint32_t u = U[i];
-        uint32_t beg = p.op[u], end = p.op[u + 1];
-        w.edges += end - beg;
-        for (uint32_t e0 = beg; e0 < end; e0 += 64) {
-            uint32_t e = e0 + lane;
-            uint32_t x = e < end ? p.oc[e] : 0xFFFFFFFFu;
-            if (x <= umax) {
-                // binary search x in U[i+1, nu)
-                uint32_t lo = i + 1, hi = nu;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    uint32_t y = U[mid];
-                    if (y < x) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo < nu && U[lo] == x) {
-                    atomicOr((unsigned long long*)&rows[(uint64_t)i * ws + (lo >> 6)], 1ull << (lo & 63));
-                    atomicOr((unsigned long long*)&rows[(uint64_t)lo * ws + (i >> 6)], 1ull << (i & 63));
-                }
-            }
-            // rows are sorted: once a chunk ends beyond U's largest rank, stop
-            if (p.oc[min(e0 + 63, end - 1)] > umax) break;
-        }
-    }
-    __threadfence();
-    wave_mem_sync();
-}
-
-// Small-universe rows directly in registers (nu <= 64): lane k gets row k.
-__device__ uint64_t build_small_rows(const Params& p, Wg& w, const uint32_t* U, uint32_t nu)
-{
-    const uint32_t lane = lane_id();
-    uint64_t up = 0;
-    if (lane < nu) {
-        uint32_t u = U[lane];
-        uint32_t beg = p.op[u], end = p.op[u + 1];
-        uint32_t umax = U[nu - 1];
-        uint32_t j = lane + 1;
-        // merge N+(u) (sorted) with U[lane+1, nu) (sorted)
-        for (uint32_t e = beg; e < end && j < nu; ++e) {
-            uint32_t x = p.oc[e];
-            if (x > umax) break;
-            while (j < nu && U[j] < x) ++j;
-            if (j < nu && U[j] == x) up |= 1ull << j;
-        }
-    }
-    w.edges += wave_sum(lane < nu ? (p.op[U[lane] + 1] - p.op[U[lane]]) : 0u);
-    uint64_t row = up;
-    for (uint32_t j = 0; j < nu; ++j) {
-        uint64_t upj = rl64(up, j);
-        if ((upj >> lane) & 1ull) row |= 1ull << j;
-    }
-    return lane < nu ? row : 0ull;
-}
-
-// Re-index the node (P u X_P, at most 64 vertices) into small mode and run it.
-__device__ void compact_and_run_small(const Params& p, Wg& w, uint32_t root, const uint32_t* U, const uint64_t* rows,
-                                      uint32_t ws, uint32_t W, uint64_t Pc, uint64_t XPc, uint32_t L, uint64_t ks,
-                                      uint32_t rs, bool anc)
-{
-    const uint32_t lane = lane_id();
+    const uint32_t W = w.W;
     uint64_t cand = lane < W ? (Pc | XPc) : 0ull;
     uint32_t cnt = (uint32_t)__popcll(cand);
     uint32_t pre = wave_excl_scan(cnt);
     uint32_t m = wave_sum(cnt);
-    uint64_t c = cand;
+    uint64_t cc = cand;
     uint32_t t = pre;
-    while (c) {
-        uint32_t bit = (uint32_t)__builtin_ctzll(c);
-        c &= c - 1;
-        w.sidx[t++] = lane * 64 + bit;
+    while (cc) {
+        uint32_t bit = (uint32_t)__builtin_ctzll(cc);
+        cc &= cc - 1;
+        S.sidx[t++] = lane * 64 + bit;
     }
-    __syncthreads();
-    bool valid = lane < m;
-    uint32_t o = valid ? w.sidx[lane] : 0u;
-    uint32_t su = valid ? U[o] : 0u;
-    uint64_t skey = valid ? w.ukey[o] : 0ull;
+    wave_mem_sync();
+    const bool valid = lane < m;
+    const uint32_t o = valid ? S.sidx[lane] : 0u;
+    const uint32_t su = valid ? w.uarr[o] : 0u;
+    const uint64_t skey = valid ? w.ukey[o] : 0ull;
     uint64_t row = 0;
+    const uint64_t* ro = rows + (uint64_t)o * ws;
     for (uint32_t k2 = 0; k2 < m; ++k2) {
-        uint32_t o2 = w.sidx[k2];
-        if (valid && ((rows[(uint64_t)o * ws + (o2 >> 6)] >> (o2 & 63)) & 1ull)) row |= 1ull << k2;
+        uint32_t o2 = S.sidx[k2];
+        if (valid && ((ro[o2 >> 6] >> (o2 & 63)) & 1ull)) row |= 1ull << k2;
     }
     uint64_t pword = shfl64(Pc, o >> 6);
     uint64_t xword = shfl64(XPc, o >> 6);
     uint64_t Ps = __ballot(valid && ((pword >> (o & 63)) & 1ull));
     uint64_t XPs = __ballot(valid && ((xword >> (o & 63)) & 1ull));
-    __syncthreads();
-    run_small(p, w, root, m, su, skey, row, Ps, XPs, L, ks, rs, anc);
+    wave_mem_sync();
+    if (L <= 64 && (w.have_xrows || L == 0))
+        fold_and_run(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc);
+    else
+        run_list(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc, 0, 1);
 }
 
-// ---------------------------------------------------------------- mid mode
-__device__ void run_mid(const Params& p, Wg& w, uint32_t root, const uint32_t* U, uint32_t nu, uint64_t* rows,
-                        uint32_t ws, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs)
+__device__ __forceinline__ void run_mid(const Params& p, Wg& w, uint32_t root, uint32_t nu, const uint64_t* rows, uint32_t ws,
+                        uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs, uint32_t c, uint32_t C)
 {
     const uint32_t lane = lane_id();
-    const uint32_t W = (nu + 63) >> 6;
-    const uint32_t gws = p.wg;  // stack stride in words
-    uint32_t depth = 0;
+    const uint32_t W = w.W;
+    const uint32_t gws = p.wg;
+    const uint32_t* U = w.uarr;
+    uint32_t depth = 0, t0 = 0;
     uint64_t B = 0;
     bool anc = false;
 enter : {
-    w.nodes += 1;
+    stat_add(S_NODES, 1);
     uint32_t best = 0;
     uint64_t cand = P | XP;
     for (uint32_t t = 0; t < W; ++t) {
@@ -667,7 +765,7 @@ enter : {
         if (bm == 0) {
             if (depth == 0) return;
             --depth;
-            uint64_t* lvl = w.gstack + (uint64_t)depth * 3 * gws;
+            const uint64_t* lvl = w.gstack + (uint64_t)depth * 3 * gws;
             if (lane < W) {
                 P = lvl[lane];
                 XP = lvl[gws + lane];
@@ -680,7 +778,7 @@ enter : {
             --rs;
             continue;
         }
-        if ((++w.poll & 1023u) == 0 && check_deadline(p, w)) return;
+        if ((++w.poll & 255u) == 0 && check_deadline(p, w)) return;
         uint32_t w0 = (uint32_t)__builtin_ctzll(bm);
         uint64_t word = rl64(B, w0);
         uint32_t bit = (uint32_t)__builtin_ctzll(word);
@@ -693,14 +791,17 @@ enter : {
             P &= ~(1ull << bit);
             XP |= 1ull << bit;
         }
+        if (depth == 0 && C > 1) {
+            if ((t0++ % C) != c) continue;
+        }
         uint32_t vb = U[bb];
         uint64_t ksc = ks + w.ukey[bb];
         uint32_t npc = wave_sum((uint32_t)__popcll(Pc));
         uint32_t nxc = wave_sum((uint32_t)__popcll(XPc));
         bool more_here = __ballot(B != 0) != 0;
         if (npc == 0) {
-            w.nodes += 1;
-            if (nxc == 0 && !xx_any(p, w, L, vb)) {
+            stat_add(S_NODES, 1);
+            if (nxc == 0 && !xx_any(p, w, L, bb, vb)) {
                 if (p.flags & MCE_F_STREAM) {
                     if (lane == 0) w.R[rs] = vb;
                     wave_mem_sync();
@@ -709,29 +810,32 @@ enter : {
             }
             continue;
         }
-        uint32_t Lc = xx_partition(p, w, L, vb);
+        uint32_t Lc = xx_partition(p, w, L, bb, vb);
         if (donation_wanted(p, w, npc, more_here, anc || depth > 0, depth)) {
-            // stage ids of P' and X_P' (ascending) in the own mailbox arrays
-            uint32_t bp = 0, bx = 0;
-            for (uint32_t t = 0; t < W; ++t) {
-                uint64_t pw_ = rl64(Pc, t), xw_ = rl64(XPc, t);
-                uint32_t u = t * 64 + lane;
-                if ((pw_ >> lane) & 1ull) w.mP[bp + prefix_popc(pw_)] = U[u];
-                if ((xw_ >> lane) & 1ull) w.mXP[bx + prefix_popc(xw_)] = U[u];
-                bp += (uint32_t)__popcll(pw_);
-                bx += (uint32_t)__popcll(xw_);
+            uint32_t r = wl_try_pop(p, w);
+            if (r != kEmptySlot) {
+                Wg d = wg_view(p, r);
+                uint32_t bp = 0, bx = 0;
+                for (uint32_t t = 0; t < W; ++t) {
+                    uint64_t pw_ = rl64(Pc, t), xw_ = rl64(XPc, t);
+                    uint32_t u = t * 64 + lane;
+                    if ((pw_ >> lane) & 1ull) d.mP[bp + prefix_popc(pw_)] = U[u];
+                    if ((xw_ >> lane) & 1ull) d.mXP[bx + prefix_popc(xw_)] = U[u];
+                    bp += (uint32_t)__popcll(pw_);
+                    bx += (uint32_t)__popcll(xw_);
+                }
+                for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                publish_task(p, w, r, root, rs, vb, ksc, npc, nxc, Lc);
+                continue;
             }
-            wave_mem_sync();
-            if (try_donate(p, w, root, rs + 1, ksc, npc, nxc, Lc, vb)) continue;
         }
         if (lane == 0) w.R[rs] = vb;
         if (npc + nxc <= 64) {
             wave_mem_sync();
-            compact_and_run_small(p, w, root, U, rows, ws, W, Pc, XPc, Lc, ksc, rs + 1, anc || more_here);
+            compact_and_run(p, w, root, rows, ws, Pc, XPc, Lc, ksc, rs + 1, anc || more_here || depth > 0);
             if (w.abort) return;
             continue;
         }
-        // push current level, descend
         uint64_t* lvl = w.gstack + (uint64_t)depth * 3 * gws;
         if (lane < W) {
             lvl[lane] = P;
@@ -752,93 +856,203 @@ enter : {
     }
 }
 
-// ---------------------------------------------------------------- tasks
-// Run a task whose universe U (ascending ranks) is in w.uarr[0, nu), with P / X_P
-// as bitmasks staged in w.pw / w.xw (word per entry), X_X in w.xx[0, L).
-__device__ void run_universe(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks,
-                             uint32_t rs)
+// ---------------------------------------------------------------- bitmap construction
+// For every list entry i < cnt (mode 0: U[i]; mode 1: xr[i]) scan its later
+// neighbours and, for each one found in U[0, nu) at position j, set bit j of
+// row i (mode 0 also sets bit i of row j: the P x P rows are symmetric).  All
+// 64 lanes take consecutive entries of the concatenated lists, so loads are
+// independent and lanes stay busy across short lists.
+__device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uint32_t cnt, uint32_t nu, uint64_t* rows, uint32_t ws)
 {
     const uint32_t lane = lane_id();
-    if (nu <= 64) {
-        uint64_t row = build_small_rows(p, w, w.uarr, nu);
-        uint64_t P = w.pw[0], XP = w.xw[0];
-        uint32_t su = lane < nu ? w.uarr[lane] : 0u;
-        uint64_t skey = lane < nu ? p.vkey[su] : 0ull;
-        run_small(p, w, root, nu, su, skey, row, P, XP, L, ks, rs, false);
-        return;
+    const uint32_t* U = w.uarr;
+    const uint32_t umin = U[0], umax = U[nu - 1];
+    for (uint32_t g0 = 0; g0 < cnt; g0 += 64) {
+        uint32_t i = g0 + lane;
+        uint32_t beg = 0, len = 0;
+        if (i < cnt) {
+            uint32_t v = mode == 0 ? U[i] : w.xr[i];
+            beg = p.op[v];
+            len = p.op[v + 1] - beg;
+        }
+        uint32_t off = wave_excl_scan(len);
+        uint32_t total = wave_sum(len);
+        S.soff[lane] = off;
+        S.sbeg[lane] = beg;
+        wave_mem_sync();
+        stat_add(S_EDGES, total);
+        const uint32_t nrows = min(64u, cnt - g0);
+        for (uint32_t t = 0; t < total; t += 64) {
+            uint32_t f = t + lane;
+            if (f < total) {
+                uint32_t lo = 0, hi = nrows;  // last row with soff <= f
+                while (hi - lo > 1) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (S.soff[mid] <= f) lo = mid;
+                    else hi = mid;
+                }
+                uint32_t x = p.oc[S.sbeg[lo] + (f - S.soff[lo])];
+                if (x >= umin && x <= umax) {
+                    uint32_t a = 0, b = nu;
+                    while (a < b) {
+                        uint32_t mid = (a + b) >> 1;
+                        if (U[mid] < x) a = mid + 1;
+                        else b = mid;
+                    }
+                    if (a < nu && U[a] == x) {
+                        uint32_t r = g0 + lo;
+                        atomicOr((unsigned long long*)&rows[(uint64_t)r * ws + (a >> 6)], 1ull << (a & 63));
+                        if (mode == 0)
+                            atomicOr((unsigned long long*)&rows[(uint64_t)a * ws + (r >> 6)], 1ull << (r & 63));
+                    }
+                }
+            }
+        }
+        wave_mem_sync();
     }
-    for (uint32_t i = lane; i < nu; i += 64) w.ukey[i] = p.vkey[w.uarr[i]];
+}
+
+// ---------------------------------------------------------------- tasks
+__device__ inline void begin_task(const Params& p, Wg& w, uint32_t root)
+{
+    uint32_t g = p.gid ? uni(p.gid[root]) : 0u;
+    if (g != w.cur_gid) {
+        flush_graph(p, w);
+        w.cur_gid = g;
+    }
+    if (__lane_id() == 0) {
+        S.stat[S_CTASK] = 0;
+        S.stat[S_HTASK] = 0;
+        S.stat[S_NODES + S_COUNT] = S.stat[S_NODES];  // nodes at task start
+    }
+    w.task_t0 = uni64(now_ticks());
+}
+
+__device__ void finish_task(const Params& p, Wg& w, uint32_t root)
+{
+    stat_add(S_TASKS, 1);
+    // keep the per-size LDS counters (32-bit) far from overflow
+    if (w.count > (1ull << 30)) flush_graph(p, w);
+    uint64_t dt = uni64(now_ticks()) - w.task_t0;
+    if (lane_id() == 0) {
+        S.stat[S_BUSY] += dt;
+        S.stat[S_MAXTASK] = max(S.stat[S_MAXTASK], dt);
+        if (p.flags & MCE_F_ROOT_STATS) {
+            uint32_t id = p.perm[root];
+            atomicAdd(&p.root_count[id], (unsigned long long)S.stat[S_CTASK]);
+            atomicAdd(&p.root_hash[id], (unsigned long long)S.stat[S_HTASK]);
+            atomicAdd(&p.root_nodes[id], (unsigned long long)(S.stat[S_NODES] - S.stat[S_NODES + S_COUNT]));
+        }
+    }
+}
+
+// Run a task whose universe U (ascending ranks) is in w.uarr[0, nu), with P
+// and X_P as bitmasks in S.pw / S.xw and the initial X_X ranks in w.xr[0, L).
+__device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks, uint32_t rs,
+                         uint32_t c, uint32_t C)
+{
+    const uint32_t lane = lane_id();
     const uint32_t W = (nu + 63) >> 6;
+    w.W = W;
+    for (uint32_t i = lane; i < nu; i += 64) w.ukey[i] = p.vkey[w.uarr[i]];
+    for (uint32_t i = lane; i < L; i += 64) w.xx[i] = i;
+    w.have_xrows = L > 0 && (uint64_t)L * W <= p.xrow_budget && L <= p.xrow_ratio * max(nu, 64u);
+    if (w.have_xrows) {
+        for (uint64_t i = lane; i < (uint64_t)L * W; i += 64) w.xrows[i] = 0;
+        wave_mem_sync();
+        scan_lists(p, w, 1, L, nu, w.xrows, W);
+        stat_add(S_XROW, 1);
+    }
     uint64_t* rows;
     uint32_t ws;
-    if (nu <= p.lds_cap) {
+    if (nu <= 64) {
         rows = w.lrows;
-        ws = ((p.lds_cap + 63) >> 6) | 1u;
+        ws = 1;
+    } else if (nu <= p.lds_cap) {
+        rows = w.lrows;
+        ws = W | 1u;
     } else {
         rows = w.grows;
         ws = W | 1u;
-        w.hbm_tasks += 1;
+        stat_add(S_HBM, 1);
     }
-    build_rows(p, w, w.uarr, nu, ws, rows);
-    uint64_t P = lane < W ? w.pw[lane] : 0ull;
-    uint64_t XP = lane < W ? w.xw[lane] : 0ull;
-    run_mid(p, w, root, w.uarr, nu, rows, ws, P, XP, L, ks, rs);
+    for (uint32_t i = lane; i < nu * ws; i += 64) rows[i] = 0;
+    wave_mem_sync();
+    scan_lists(p, w, 0, nu, nu, rows, ws);
+    if (nu <= 64) {
+        const bool valid = lane < nu;
+        uint32_t su = valid ? w.uarr[lane] : 0u;
+        uint64_t skey = valid ? w.ukey[lane] : 0ull;
+        uint64_t rowP = valid ? rows[lane] : 0ull;
+        uint64_t P = S.pw[0], XP = S.xw[0];
+        wave_mem_sync();
+        if (C == 1 && L <= 64 && (w.have_xrows || L == 0))
+            fold_and_run(p, w, root, nu, su, skey, lane, rowP, P, XP, L, ks, rs, false);
+        else
+            run_list(p, w, root, nu, su, skey, lane, rowP, P, XP, L, ks, rs, false, c, C);
+    } else {
+        uint64_t P = lane < W ? S.pw[lane] : 0ull;
+        uint64_t XP = lane < W ? S.xw[lane] : 0ull;
+        wave_mem_sync();
+        run_mid(p, w, root, nu, rows, ws, P, XP, L, ks, rs, c, C);
+    }
 }
 
-__device__ void finish_task(const Params& p, Wg& w, uint32_t root, uint64_t c0, uint64_t h0, uint64_t n0)
-{
-    flush_hist(p, w);
-    w.tasks += 1;
-    uint64_t dt = uni64(now_ticks()) - w.task_t0;
-    w.busy_ticks += dt;
-    w.max_task_ticks = max(w.max_task_ticks, dt);
-    if ((p.flags & MCE_F_ROOT_STATS) && lane_id() == 0) {
-        uint32_t id = p.perm[root];
-        atomicAdd(&p.root_count[id], (unsigned long long)(w.count - c0));
-        atomicAdd(&p.root_hash[id], (unsigned long long)(w.hash - h0));
-        atomicAdd(&p.root_nodes[id], (unsigned long long)(w.nodes - n0));
-    }
-}
+// Task parameters set up by either source of work.
+struct TaskArgs {
+    uint32_t root, nu, L, rs, c, C;
+    uint64_t ks;
+};
 
-// First-level subtree of root v (Algorithm 3): P = later neighbours, X = earlier.
-__device__ void run_root(const Params& p, Wg& w, uint32_t v)
+// First-level subtree of root v (Algorithm 3): P = later neighbours, X =
+// earlier neighbours; with a split (c, C) only level-1 branches t % C == c.
+__device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t v, uint32_t split)
 {
     const uint32_t lane = lane_id();
-    uint64_t c0 = w.count, h0 = w.hash, n0 = w.nodes;
-    w.task_t0 = uni64(now_ticks());
     uint32_t beg = p.op[v], nu = p.op[v + 1] - beg;
     uint32_t ib = p.ip[v], L = p.ip[v + 1] - ib;
     for (uint32_t i = lane; i < nu; i += 64) w.uarr[i] = p.oc[beg + i];
-    for (uint32_t i = lane; i < L; i += 64) w.xx[i] = p.ic[ib + i];
-    w.root_list_words += nu + L;
+    for (uint32_t i = lane; i < L; i += 64) w.xr[i] = p.ic[ib + i];
+    stat_add(S_ROOTW, nu + L);
     if (lane == 0) w.R[0] = v;
     const uint32_t W = (nu + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
-        uint32_t rem = nu - q * 64;
-        w.pw[q] = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
-        w.xw[q] = 0;
+        S.pw[q] = low_mask(nu - q * 64);
+        S.xw[q] = 0;
     }
     wave_mem_sync();
-    run_universe(p, w, v, nu, L, p.vkey[v], 1);
-    finish_task(p, w, v, c0, h0, n0);
+    TaskArgs t;
+    t.root = v;
+    t.nu = nu;
+    t.L = L;
+    t.rs = 1;
+    t.C = split >> 16;
+    t.c = split & 0xFFFFu;
+    if (t.C == 0) t.C = 1;
+    t.ks = p.vkey[v];
+    return t;
 }
 
 // A task received through the worker list; its lists are in this workgroup's mailbox.
-__device__ void run_received(const Params& p, Wg& w)
+__device__ __forceinline__ TaskArgs setup_received(const Params& p, Wg& w)
 {
     const uint32_t lane = lane_id();
-    uint64_t c0 = w.count, h0 = w.hash, n0 = w.nodes;
-    w.task_t0 = uni64(now_ticks());
     MboxHdr h = *w.mbox;
-    uint32_t np = uni(h.np), nxp = uni(h.nxp), L = uni(h.nxx), rs = uni(h.rsize), root = uni(h.root);
-    uint64_t ks = uni64(h.keysum);
-    uint32_t nu = np + nxp;
-    uint32_t W = (nu + 63) >> 6;
+    uint32_t np = uni(h.np), nxp = uni(h.nxp);
+    TaskArgs t;
+    t.root = uni(h.root);
+    t.L = uni(h.nxx);
+    t.rs = uni(h.rsize);
+    t.ks = uni64(h.keysum);
+    t.c = 0;
+    t.C = 1;
+    t.nu = np + nxp;
+    uint32_t W = (t.nu + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
-        w.pw[q] = 0;
-        w.xw[q] = 0;
+        S.pw[q] = 0;
+        S.xw[q] = 0;
     }
-    __syncthreads();
+    wave_mem_sync();
     // merge the two ascending lists into U; mark P / X_P membership
     for (uint32_t i = lane; i < np; i += 64) {
         uint32_t x = w.mP[i];
@@ -850,7 +1064,7 @@ __device__ void run_received(const Params& p, Wg& w)
         }
         uint32_t pos = i + lo;
         w.uarr[pos] = x;
-        atomicOr((unsigned long long*)&w.pw[pos >> 6], 1ull << (pos & 63));
+        atomicOr((unsigned long long*)&S.pw[pos >> 6], 1ull << (pos & 63));
     }
     for (uint32_t i = lane; i < nxp; i += 64) {
         uint32_t x = w.mXP[i];
@@ -862,11 +1076,80 @@ __device__ void run_received(const Params& p, Wg& w)
         }
         uint32_t pos = i + lo;
         w.uarr[pos] = x;
-        atomicOr((unsigned long long*)&w.xw[pos >> 6], 1ull << (pos & 63));
+        atomicOr((unsigned long long*)&S.xw[pos >> 6], 1ull << (pos & 63));
     }
     wave_mem_sync();
-    run_universe(p, w, root, nu, L, ks, rs);
-    finish_task(p, w, root, c0, h0, n0);
+    return t;
+}
+
+// Next unit of work: a (root, split) entry of the queue in phase 1, a donated
+// branch in phase 2.  Returns false when the kernel is done for this workgroup.
+__device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, TaskArgs& t)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t me = w.me;
+    if (phase1) {
+        uint32_t idx = 0;
+        if (lane == 0) idx = atomicAdd(&p.ctrl->root_cursor, 1u);
+        idx = uni(idx);
+        if (idx < p.nroots) {
+            uint32_t v = p.roots[idx];
+            t = setup_root(p, w, v, p.splits ? p.splits[idx] : 0u);
+            return true;
+        }
+        phase1 = false;
+    }
+    if (!(p.flags & MCE_F_WORKER_LIST)) return false;
+    // worker list: become idle, wait for a donated branch or termination
+    uint32_t terminate = 0;
+    if (lane == 0) {
+        __hip_atomic_store(&p.wflags[me], kFlagIdle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // acq_rel: orders this workgroup's flag reset before a terminator's stores
+        unsigned long long old =
+            __hip_atomic_fetch_add(&p.ctrl->packed, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t idle = (uint32_t)old + 1, started = (uint32_t)(old >> 32);
+        terminate = idle == started;
+        if (!terminate) {
+            unsigned long long tl =
+                __hip_atomic_fetch_add(&p.ctrl->ring_tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t* slot = &p.ring[tl & p.ring_mask];
+            while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kEmptySlot) {
+                if (now_ticks() > w.deadline) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __hip_atomic_fetch_add(&p.ctrl->waiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(slot, me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    terminate = uni(terminate);
+    if (terminate) {
+        for (uint32_t g = lane; g < p.nwg; g += 64)
+            __hip_atomic_store(&p.wflags[g], kFlagTerm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+    }
+    uint32_t f = kFlagIdle;
+    uint64_t t0 = now_ticks();
+    if (lane == 0) {
+        uint32_t sleep = 1;
+        // poll with relaxed loads (an acquire load would invalidate caches on
+        // every iteration); acquire once below when a task has arrived
+        while ((f = __hip_atomic_load(&p.wflags[me], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kFlagIdle) {
+            if (now_ticks() > w.deadline) break;
+            if (sleep < 32) sleep <<= 1;
+            for (uint32_t s = 0; s < sleep; ++s) __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    f = uni(f);
+    stat_add(S_IDLE, now_ticks() - t0);
+    if (f == kFlagIdle) {
+        if (lane == 0) atomicOr(&p.ctrl->err, 1u);
+        w.abort = true;
+        return false;
+    }
+    if (f == kFlagTerm) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    t = setup_received(p, w);
+    return true;
 }
 
 __global__ void __launch_bounds__(64) k_enumerate(Params p)
@@ -876,130 +1159,66 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     const uint32_t me = blockIdx.x;
     Wg w = wg_view(p, me);
     uint8_t* base = p.scratch + (uint64_t)me * p.stride;
+    w.xx = reinterpret_cast<uint32_t*>(base + p.off_xx);
     w.xflag = reinterpret_cast<uint64_t*>(base + p.off_flag);
     w.hpos = reinterpret_cast<uint32_t*>(base + p.off_hpos);
     w.spos = reinterpret_cast<uint32_t*>(base + p.off_spos);
     w.grows = reinterpret_cast<uint64_t*>(base + p.off_rows);
+    w.xrows = reinterpret_cast<uint64_t*>(base + p.off_xrows);
     w.gstack = reinterpret_cast<uint64_t*>(base + p.off_stack);
     w.gmeta = reinterpret_cast<uint64_t*>(base + p.off_meta);
-    // LDS carve-up
     unsigned char* l = lds;
-    w.pw = reinterpret_cast<uint64_t*>(l); l += 64 * 8;
-    w.xw = reinterpret_cast<uint64_t*>(l); l += 64 * 8;
-    w.sP = reinterpret_cast<uint64_t*>(l); l += kSmallDepth * 8;
-    w.sXP = reinterpret_cast<uint64_t*>(l); l += kSmallDepth * 8;
-    w.sB = reinterpret_cast<uint64_t*>(l); l += kSmallDepth * 8;
-    w.sK = reinterpret_cast<uint64_t*>(l); l += kSmallDepth * 8;
-    w.sL = reinterpret_cast<uint32_t*>(l); l += kSmallDepth * 4;
-    w.sA = reinterpret_cast<uint32_t*>(l); l += kSmallDepth * 4;
-    w.hist = reinterpret_cast<uint32_t*>(l); l += kHistLds * 4;
-    w.sidx = reinterpret_cast<uint32_t*>(l); l += 64 * 4;
-    w.uarr = reinterpret_cast<uint32_t*>(l); l += ((p.ucap + 1) & ~1u) * 4;
-    w.ukey = reinterpret_cast<uint64_t*>(l); l += (size_t)p.ucap * 8;
+    w.ukey = reinterpret_cast<uint64_t*>(l);
+    l += (size_t)p.ucap * 8;
+    w.uarr = reinterpret_cast<uint32_t*>(l);
+    l += (size_t)((p.ucap + 3) & ~3u) * 4;
     w.lrows = reinterpret_cast<uint64_t*>(l);
-    for (uint32_t k = lane; k < (uint32_t)kHistLds; k += 64) w.hist[k] = 0;
-    __syncthreads();
-    w.count = w.hash = w.nodes = w.donations = w.tasks = w.xtests = w.edges = w.hbm_tasks = w.idle_ticks = 0;
-    w.root_list_words = 0;
-    w.probes = 0;
-    w.busy_ticks = w.max_task_ticks = w.task_t0 = 0;
+    for (uint32_t k = lane; k < (uint32_t)kHistLds; k += 64) S.hist[k] = 0;
+    for (uint32_t k = lane; k < (uint32_t)S_COUNT + 2; k += 64) S.stat[k] = 0;
+    wave_mem_sync();
+    w.count = w.hash = 0;
+    w.cur_gid = 0;
     w.hmax = 0;
-    w.wl_tick = 0;
-    w.wl_seen = 0;
-    w.poll = 0;
+    w.task_t0 = 0;
+    w.probes = 0;
+    w.wl_tick = w.wl_seen = w.poll = 0;
     w.me = me;
     w.abort = false;
+    w.W = 1;
+    w.have_xrows = false;
     w.deadline = uni64(now_ticks()) + p.timeout_ticks;
 
-    const bool use_wl = (p.flags & MCE_F_WORKER_LIST) != 0;
-    if (use_wl && lane == 0)
+    if ((p.flags & MCE_F_WORKER_LIST) && lane == 0)
         __hip_atomic_fetch_add(&p.ctrl->packed, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    // phase 1: first-level subtrees from the shared counter
-    while (!w.abort) {
-        uint32_t idx = 0;
-        if (lane == 0) idx = atomicAdd(&p.ctrl->root_cursor, 1u);
-        idx = uni(idx);
-        if (idx >= p.nroots) break;
-        run_root(p, w, p.roots[idx]);
-        if (w.abort) break;
+    // phase 1: queue entries from the shared counter; phase 2: worker list
+    bool phase1 = true;
+    TaskArgs t;
+    while (!w.abort && next_task(p, w, phase1, t)) {
+        begin_task(p, w, t.root);
+        run_task(p, w, t.root, t.nu, t.L, t.ks, t.rs, t.c, t.C);
+        finish_task(p, w, t.root);
     }
-    // phase 2: worker list
-    while (use_wl && !w.abort) {
-        uint32_t terminate = 0;
-        if (lane == 0) {
-            __hip_atomic_store(&p.wflags[me], kFlagIdle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned long long old =
-                __hip_atomic_fetch_add(&p.ctrl->packed, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t idle = (uint32_t)old + 1, started = (uint32_t)(old >> 32);
-            terminate = idle == started;
-            if (!terminate) {
-                unsigned long long t =
-                    __hip_atomic_fetch_add(&p.ctrl->ring_tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t* slot = &p.ring[t & p.ring_mask];
-                while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kEmptySlot) {
-                    if (now_ticks() > w.deadline) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                __hip_atomic_fetch_add(&p.ctrl->waiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(slot, me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        terminate = uni(terminate);
-        if (terminate) {
-            for (uint32_t g = lane; g < p.nwg; g += 64)
-                __hip_atomic_store(&p.wflags[g], kFlagTerm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
-        uint32_t f = kFlagIdle;
-        uint64_t t0 = now_ticks();
-        if (lane == 0) {
-            uint32_t sleep = 1;
-            // poll with relaxed loads (an acquire load would invalidate caches on
-            // every iteration); acquire once below when a task has arrived
-            while ((f = __hip_atomic_load(&p.wflags[me], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kFlagIdle) {
-                if (now_ticks() > w.deadline) break;
-                if (sleep < 32) sleep <<= 1;
-                for (uint32_t s = 0; s < sleep; ++s) __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        f = uni(f);
-        w.idle_ticks += now_ticks() - t0;
-        if (f == kFlagIdle) {
-            if (lane == 0) atomicOr(&p.ctrl->err, 1u);
-            w.abort = true;
-            break;
-        }
-        if (f == kFlagTerm) break;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        run_received(p, w);
-    }
-    flush_hist(p, w);
-    uint64_t probes = 0;
-    {
-        uint32_t pl = w.probes;
-        for (int off = 32; off > 0; off >>= 1) pl += (uint32_t)__shfl_xor((int)pl, off, 64);
-        probes = pl;
-    }
+    flush_graph(p, w);
+    uint32_t pl = wave_sum(w.probes);
     if (lane == 0) {
-        atomicAdd(&p.acc[2 + MCE_STAT_PROBES], (unsigned long long)probes);
-        atomicAdd(&p.acc[2 + MCE_STAT_BUSY_NS], (unsigned long long)w.busy_ticks);
-        atomicMax(&p.acc[2 + MCE_STAT_MAX_TASK_NS], (unsigned long long)w.max_task_ticks);
-        atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)w.root_list_words);
-        atomicAdd(&p.acc[0], (unsigned long long)w.count);
-        atomicAdd(&p.acc[1], (unsigned long long)w.hash);
-        atomicAdd(&p.acc[2 + MCE_STAT_NODES], (unsigned long long)w.nodes);
-        atomicAdd(&p.acc[2 + MCE_STAT_DONATIONS], (unsigned long long)w.donations);
-        atomicAdd(&p.acc[2 + MCE_STAT_TASKS], (unsigned long long)w.tasks);
-        atomicAdd(&p.acc[2 + MCE_STAT_XTESTS], (unsigned long long)w.xtests);
-        atomicAdd(&p.acc[2 + MCE_STAT_BUILD_EDGES], (unsigned long long)w.edges);
-        atomicAdd(&p.acc[2 + MCE_STAT_HBM_ROWS], (unsigned long long)w.hbm_tasks);
-        atomicAdd(&p.acc[2 + MCE_STAT_IDLE_NS], (unsigned long long)w.idle_ticks);
+        atomicAdd(&p.acc[2 + MCE_STAT_PROBES], (unsigned long long)pl);
+        atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)S.stat[S_ROOTW]);
+        atomicAdd(&p.acc[2 + MCE_STAT_BUSY_NS], (unsigned long long)S.stat[S_BUSY]);
+        atomicMax(&p.acc[2 + MCE_STAT_MAX_TASK_NS], (unsigned long long)S.stat[S_MAXTASK]);
+        atomicAdd(&p.acc[2 + MCE_STAT_NODES], (unsigned long long)S.stat[S_NODES]);
+        atomicAdd(&p.acc[2 + MCE_STAT_DONATIONS], (unsigned long long)S.stat[S_DONATIONS]);
+        atomicAdd(&p.acc[2 + MCE_STAT_TASKS], (unsigned long long)S.stat[S_TASKS]);
+        atomicAdd(&p.acc[2 + MCE_STAT_XTESTS], (unsigned long long)S.stat[S_XTESTS]);
+        atomicAdd(&p.acc[2 + MCE_STAT_BUILD_EDGES], (unsigned long long)S.stat[S_EDGES]);
+        atomicAdd(&p.acc[2 + MCE_STAT_HBM_ROWS], (unsigned long long)S.stat[S_HBM]);
+        atomicAdd(&p.acc[2 + MCE_STAT_IDLE_NS], (unsigned long long)S.stat[S_IDLE]);
+        atomicAdd(&p.acc[2 + MCE_STAT_XROW_TASKS], (unsigned long long)S.stat[S_XROW]);
     }
 }
 
 // ---------------------------------------------------------------- root queue
-// flags[i] = 1 if the i-th root in processing order is in the window and has P != {}.
+// flag[i] = 1 if the i-th root in processing order is in the window and has P != {}.
 __global__ void k_root_flags(const uint32_t* __restrict__ op, const uint32_t* __restrict__ core_r, uint32_t n,
                              uint32_t c, uint32_t mode, const uint32_t* __restrict__ custom,
                              const uint32_t* __restrict__ rank, uint32_t* __restrict__ cand,
@@ -1024,24 +1243,16 @@ __global__ void k_root_compact(const uint32_t* __restrict__ cand, const uint32_t
 
 // Isolated vertices are maximal cliques of size 1 (Algorithm 3 with P = X = {}).
 __global__ void k_isolated(const uint32_t* __restrict__ op, const uint32_t* __restrict__ ip,
-                           const uint64_t* __restrict__ vkey, uint32_t n, unsigned long long* acc,
-                           unsigned long long* hist)
+                           const uint64_t* __restrict__ vkey, const uint32_t* __restrict__ gid, uint32_t n,
+                           unsigned long long* gacc, unsigned long long* ghist, uint32_t hist_len)
 {
-    uint64_t cnt = 0, h = 0;
     for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (size_t)gridDim.x * blockDim.x) {
         if (op[r + 1] == op[r] && ip[r + 1] == ip[r]) {
-            cnt += 1;
-            h += fmix64(vkey[r] + kGamma);
+            uint32_t g = gid ? gid[r] : 0u;
+            atomicAdd(&gacc[2 * g], 1ull);
+            atomicAdd(&gacc[2 * g + 1], (unsigned long long)fmix64(vkey[r] + kGamma));
+            atomicAdd(&ghist[(uint64_t)g * hist_len + 1], 1ull);
         }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        cnt += shfl64(cnt, lane_id() ^ off);
-        h += shfl64(h, lane_id() ^ off);
-    }
-    if (lane_id() == 0 && cnt) {
-        atomicAdd(&acc[0], (unsigned long long)cnt);
-        atomicAdd(&acc[1], (unsigned long long)h);
-        atomicAdd(&hist[1], (unsigned long long)cnt);
     }
 }
 
@@ -1057,12 +1268,52 @@ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
+                            uint32_t* nroots_out)
+{
+    mce_status rc;
+    const uint32_t n = g.n;
+    const size_t nn = n ? n : 1;
+    if ((rc = st.roots.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = st.tmp_a.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = st.tmp_b.alloc((nn + 1) * 4)) != MCE_OK) return rc;
+    if ((rc = st.tmp_c.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = st.scan_tmp.alloc(scan_tmp_words(nn + 1) * 8 + 64)) != MCE_OK) return rc;
+    if ((rc = st.small.alloc(64)) != MCE_OK) return rc;
+    uint32_t mode = 0;
+    if (cfg.flags & MCE_F_CUSTOM_ORDER) mode = 2;
+    else if (cfg.flags & MCE_F_REVERSE_ORDER) mode = 1;
+    if (mode == 2 && !cfg.root_order) {
+        set_error("MCE_F_CUSTOM_ORDER without root_order");
+        return MCE_ERR_INVALID_ARG;
+    }
+    uint32_t nroots = 0;
+    if (n) {
+        uint32_t* dtotal = st.small.as<uint32_t>();
+        k_root_flags<<<blocks_for(n, 256, 8192), 256, 0, s>>>(g.op.as<uint32_t>(), g.core_r.as<uint32_t>(), n,
+                                                              cfg.max_root_core, mode, cfg.root_order,
+                                                              g.rank.as<uint32_t>(), st.tmp_a.as<uint32_t>(),
+                                                              st.tmp_c.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        if ((rc = exclusive_scan_u32(st.tmp_c.as<uint32_t>(), st.tmp_b.as<uint32_t>(), n, dtotal,
+                                     st.scan_tmp.as<uint64_t>(), s)) != MCE_OK)
+            return rc;
+        k_root_compact<<<blocks_for(n, 256, 8192), 256, 0, s>>>(st.tmp_a.as<uint32_t>(), st.tmp_c.as<uint32_t>(),
+                                                                st.tmp_b.as<uint32_t>(), n, st.roots.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        MCE_HIP_TRY(hipMemcpyAsync(&nroots, dtotal, 4, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    *nroots_out = nroots;
+    return MCE_OK;
+}
+
 mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
                            EnumOutput& out)
 {
     mce_status rc;
     const uint32_t n = g.n;
-    const size_t nn = n ? n : 1;
+    const uint32_t ng = std::max<uint32_t>(g.ngraphs, 1u);
     const uint32_t ucap = std::max(g.max_out, 1u);
     if (ucap > kMaxUniverse) {
         set_error("first-level P larger than " + std::to_string(kMaxUniverse) + " vertices is not supported");
@@ -1071,18 +1322,18 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint32_t hist_len = g.degeneracy + 3;
     const uint32_t xcap = std::max(g.max_in, 1u);
     const uint32_t rcap = g.degeneracy + 3;
-    const uint32_t wg_words = (ucap + 63) / 64;  // words per set at the largest universe
+    const uint32_t wg_words = (ucap + 63) / 64;
     const uint32_t ws_g = wg_words | 1u;
 
-    // LDS budget for bitmap rows
+    // LDS budget for bitmap rows (universes up to 64 always fit)
     uint32_t lds_cap = cfg.bitmap_max_p ? cfg.bitmap_max_p : 256u;
-    lds_cap = std::min(lds_cap, ucap);
-    if (lds_cap < 64) lds_cap = 64;
-    const uint32_t ws_l = ((lds_cap + 63) / 64) | 1u;
-    size_t lds_bytes = 64 * 8 * 2 + kSmallDepth * (8 * 4 + 4 * 2) + kHistLds * 4 + 64 * 4 +
-                       (size_t)((ucap + 1) & ~1u) * 4 + (size_t)ucap * 8 + (size_t)lds_cap * ws_l * 8;
-    lds_bytes = align_up(lds_bytes, 16);
-    if (lds_bytes > 160 * 1024) {
+    lds_cap = std::max(64u, std::min(lds_cap, std::max(ucap, 64u)));
+    const uint32_t ws_l = lds_cap <= 64 ? 1u : (((lds_cap + 63) / 64) | 1u);
+    size_t lds_bytes = 0;                                      // dynamic part (static LdsFixed comes first)
+    lds_bytes += (size_t)ucap * 8;                             // ukey
+    lds_bytes += (size_t)((ucap + 3) & ~3u) * 4;               // uarr
+    lds_bytes += (size_t)std::max(lds_cap * ws_l, 64u) * 8;    // rows
+    if (lds_bytes + sizeof(LdsFixed) > 160 * 1024) {
         set_error("LDS budget exceeded; lower bitmap_max_p");
         return MCE_ERR_INVALID_ARG;
     }
@@ -1100,36 +1351,33 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     if (G == 0) G = 1;
 
     // per-workgroup scratch layout
+    const uint64_t xrow_words = std::min<uint64_t>(cfg.xrow_budget_words, (uint64_t)xcap * wg_words);
     uint64_t off = align_up(sizeof(MboxHdr), 256);
     const uint64_t off_P = off; off = align_up(off + (uint64_t)ucap * 4, 256);
     const uint64_t off_XP = off; off = align_up(off + (uint64_t)ucap * 4, 256);
     const uint64_t off_R = off; off = align_up(off + (uint64_t)rcap * 4, 256);
+    const uint64_t off_xr = off; off = align_up(off + (uint64_t)xcap * 4, 256);
     const uint64_t off_xx = off; off = align_up(off + (uint64_t)xcap * 4, 256);
     const uint64_t off_flag = off; off = align_up(off + ((uint64_t)xcap / 64 + 2) * 8, 256);
     const uint64_t off_hpos = off; off = align_up(off + ((uint64_t)xcap / 2 + 2) * 4, 256);
     const uint64_t off_spos = off; off = align_up(off + ((uint64_t)xcap / 2 + 2) * 4, 256);
     const uint64_t off_rows = off; off = align_up(off + (uint64_t)ucap * ws_g * 8, 256);
+    const uint64_t off_xrows = off; off = align_up(off + xrow_words * 8 + 8, 256);
     const uint64_t off_stack = off; off = align_up(off + (uint64_t)(ucap + 2) * 3 * wg_words * 8, 256);
     const uint64_t off_meta = off; off = align_up(off + (uint64_t)(ucap + 2) * 16, 256);
     const uint64_t stride = off;
-
-    // a budget of 16 GiB of scratch at most; shrink the grid if needed
-    const uint64_t budget = 16ull << 30;
-    if ((uint64_t)G * stride > budget) G = std::max<uint64_t>(1, budget / stride);
+    const uint64_t budget = 32ull << 30;
+    if ((uint64_t)G * stride > budget) G = (uint32_t)std::max<uint64_t>(1, budget / stride);
 
     if ((rc = st.scratch.alloc((size_t)G * stride)) != MCE_OK) return rc;
     if ((rc = st.ctrl.alloc(sizeof(Ctrl))) != MCE_OK) return rc;
     if ((rc = st.acc.alloc(32 * 8)) != MCE_OK) return rc;
-    if ((rc = st.hist.alloc((size_t)hist_len * 8)) != MCE_OK) return rc;
+    if ((rc = st.gacc.alloc((size_t)ng * 16)) != MCE_OK) return rc;
+    if ((rc = st.hist.alloc((size_t)ng * hist_len * 8)) != MCE_OK) return rc;
     uint32_t ring_cap = 1;
     while (ring_cap < 2 * G) ring_cap <<= 1;
     if ((rc = st.ring.alloc((size_t)ring_cap * 4)) != MCE_OK) return rc;
     if ((rc = st.flags.alloc((size_t)G * 4)) != MCE_OK) return rc;
-    if ((rc = st.roots.alloc(nn * 4)) != MCE_OK) return rc;
-    if ((rc = st.tmp_a.alloc(nn * 4)) != MCE_OK) return rc;
-    if ((rc = st.tmp_b.alloc((nn + 1) * 4)) != MCE_OK) return rc;
-    if ((rc = st.tmp_c.alloc(nn * 4)) != MCE_OK) return rc;
-    if ((rc = st.scan_tmp.alloc(scan_tmp_words(nn + 1) * 8 + 64)) != MCE_OK) return rc;
 
     hipEvent_t e0, e1, e2;
     MCE_HIP_TRY(hipEventCreate(&e0));
@@ -1140,46 +1388,29 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     // reset control state (fill kernels, no memset nodes)
     fill_u64(reinterpret_cast<uint64_t*>(st.ctrl.p), 0, sizeof(Ctrl) / 8, s);
     fill_u64(st.acc.as<uint64_t>(), 0, 32, s);
-    fill_u64(st.hist.as<uint64_t>(), 0, hist_len, s);
+    fill_u64(st.gacc.as<uint64_t>(), 0, (size_t)ng * 2, s);
+    fill_u64(st.hist.as<uint64_t>(), 0, (size_t)ng * hist_len, s);
     fill_u32(st.ring.as<uint32_t>(), kEmptySlot, ring_cap, s);
     fill_u32(st.flags.as<uint32_t>(), kFlagIdle, G, s);
 
-    // root queue: window filter + order-preserving compaction
-    uint32_t mode = 0;
-    if (cfg.flags & MCE_F_CUSTOM_ORDER) mode = 2;
-    else if (cfg.flags & MCE_F_REVERSE_ORDER) mode = 1;
-    if (mode == 2 && !cfg.root_order) {
-        set_error("MCE_F_CUSTOM_ORDER without root_order");
-        return MCE_ERR_INVALID_ARG;
-    }
-    uint32_t* dpos = st.tmp_b.as<uint32_t>();
-    uint32_t* dtotal = reinterpret_cast<uint32_t*>(st.acc.as<uint64_t>() + 30);
-    if (n) {
-        k_root_flags<<<blocks_for(n, 256, 8192), 256, 0, s>>>(g.op.as<uint32_t>(), g.core_r.as<uint32_t>(), n,
-                                                              cfg.max_root_core, mode, cfg.root_order,
-                                                              g.rank.as<uint32_t>(), st.tmp_a.as<uint32_t>(),
-                                                              st.tmp_c.as<uint32_t>());
-        MCE_HIP_TRY(hipGetLastError());
-        if ((rc = exclusive_scan_u32(st.tmp_c.as<uint32_t>(), dpos, n, dtotal, st.scan_tmp.as<uint64_t>(), s)) !=
-            MCE_OK)
-            return rc;
-        k_root_compact<<<blocks_for(n, 256, 8192), 256, 0, s>>>(st.tmp_a.as<uint32_t>(), st.tmp_c.as<uint32_t>(), dpos,
-                                                                n, st.roots.as<uint32_t>());
-        MCE_HIP_TRY(hipGetLastError());
-        k_isolated<<<blocks_for(n, 256, 4096), 256, 0, s>>>(g.op.as<uint32_t>(), g.ip.as<uint32_t>(),
-                                                            g.vkey.as<uint64_t>(), n,
-                                                            reinterpret_cast<unsigned long long*>(st.acc.p),
-                                                            reinterpret_cast<unsigned long long*>(st.hist.p));
-        MCE_HIP_TRY(hipGetLastError());
-        MCE_HIP_TRY(hipStreamSynchronize(s));
-    }
     uint32_t nroots = 0;
-    if (n) {
-        MCE_HIP_TRY(hipMemcpyAsync(&nroots, dtotal, 4, hipMemcpyDeviceToHost, s));
-        MCE_HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t* roots = nullptr;
+    const uint32_t* splits = nullptr;
+    if (cfg.queue_roots) {
+        roots = cfg.queue_roots;
+        splits = cfg.queue_splits;
+        nroots = cfg.queue_len;
+    } else {
+        if ((rc = build_root_queue(g, cfg, st, s, &nroots)) != MCE_OK) return rc;
+        roots = st.roots.as<uint32_t>();
     }
-    // (acc[30] doubles as the scan total; clear it before the kernel accumulates)
-    fill_u64(st.acc.as<uint64_t>() + 30, 0, 1, s);
+    if (n) {
+        k_isolated<<<blocks_for(n, 256, 4096), 256, 0, s>>>(
+            g.op.as<uint32_t>(), g.ip.as<uint32_t>(), g.vkey.as<uint64_t>(),
+            g.ngraphs > 1 ? g.gid.as<uint32_t>() : nullptr, n, reinterpret_cast<unsigned long long*>(st.gacc.p),
+            reinterpret_cast<unsigned long long*>(st.hist.p), hist_len);
+        MCE_HIP_TRY(hipGetLastError());
+    }
     MCE_HIP_TRY(hipEventRecord(e1, s));
 
     Params p{};
@@ -1189,24 +1420,31 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.ic = g.ic.as<uint32_t>();
     p.vkey = g.vkey.as<uint64_t>();
     p.perm = g.perm.as<uint32_t>();
-    p.roots = st.roots.as<uint32_t>();
+    p.gid = g.ngraphs > 1 ? g.gid.as<uint32_t>() : nullptr;
+    p.roots = roots;
+    p.splits = splits;
     p.nroots = nroots;
     p.ctrl = reinterpret_cast<Ctrl*>(st.ctrl.p);
     p.acc = reinterpret_cast<unsigned long long*>(st.acc.p);
-    p.hist = reinterpret_cast<unsigned long long*>(st.hist.p);
+    p.gacc = reinterpret_cast<unsigned long long*>(st.gacc.p);
+    p.ghist = reinterpret_cast<unsigned long long*>(st.hist.p);
     p.hist_len = hist_len;
     p.scratch = st.scratch.as<uint8_t>();
     p.stride = stride;
     p.off_P = off_P;
     p.off_XP = off_XP;
     p.off_R = off_R;
+    p.off_xr = off_xr;
     p.off_xx = off_xx;
     p.off_flag = off_flag;
     p.off_hpos = off_hpos;
     p.off_spos = off_spos;
     p.off_rows = off_rows;
+    p.off_xrows = off_xrows;
     p.off_stack = off_stack;
     p.off_meta = off_meta;
+    p.xrow_budget = xrow_words;
+    p.xrow_ratio = cfg.xrow_ratio;
     p.ring = st.ring.as<uint32_t>();
     p.ring_mask = ring_cap - 1;
     p.wflags = st.flags.as<uint32_t>();
@@ -1243,10 +1481,12 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     MCE_HIP_TRY(hipEventRecord(e2, s));
     uint64_t acc[32];
     Ctrl ctrl;
-    out.hist.assign(hist_len, 0);
+    std::vector<uint64_t> gacc((size_t)ng * 2);
+    std::vector<uint64_t> ghist((size_t)ng * hist_len);
     MCE_HIP_TRY(hipMemcpyAsync(acc, st.acc.p, sizeof(acc), hipMemcpyDeviceToHost, s));
     MCE_HIP_TRY(hipMemcpyAsync(&ctrl, st.ctrl.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    MCE_HIP_TRY(hipMemcpyAsync(out.hist.data(), st.hist.p, (size_t)hist_len * 8, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipMemcpyAsync(gacc.data(), st.gacc.p, gacc.size() * 8, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipMemcpyAsync(ghist.data(), st.hist.p, ghist.size() * 8, hipMemcpyDeviceToHost, s));
     MCE_HIP_TRY(hipStreamSynchronize(s));
     float ms_setup = 0, ms_kernel = 0;
     (void)hipEventElapsedTime(&ms_setup, e0, e1);
@@ -1255,8 +1495,21 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
 
-    out.count = acc[0];
-    out.hash = acc[1];
+    out.graphs.assign(ng, EnumOutput::PerGraph());
+    out.count = out.hash = 0;
+    for (uint32_t gi = 0; gi < ng; ++gi) {
+        auto& pg = out.graphs[gi];
+        pg.count = gacc[2 * gi];
+        pg.hash = gacc[2 * gi + 1];
+        pg.hist.assign(ghist.begin() + (size_t)gi * hist_len, ghist.begin() + (size_t)(gi + 1) * hist_len);
+        pg.max_size = 0;
+        for (uint32_t k = 0; k < hist_len; ++k)
+            if (pg.hist[k]) pg.max_size = k;
+        out.count += pg.count;
+        out.hash += pg.hash;
+    }
+    out.hist = out.graphs[0].hist;
+    out.max_size = out.graphs[0].max_size;
     for (int i = 0; i < 16; ++i) out.stats[i] = acc[2 + i];
     out.stats[MCE_STAT_ROOTS] = nroots;
     out.stats[MCE_STAT_WORKGROUPS] = G;
@@ -1265,10 +1518,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     out.stats[MCE_STAT_IDLE_NS] = acc[2 + MCE_STAT_IDLE_NS] * 10;  // 100 MHz ticks -> ns
     out.stats[MCE_STAT_BUSY_NS] = acc[2 + MCE_STAT_BUSY_NS] * 10;
     out.stats[MCE_STAT_MAX_TASK_NS] = acc[2 + MCE_STAT_MAX_TASK_NS] * 10;
-    out.stats[MCE_STAT_LDS_BYTES] = lds_bytes;
-    out.max_size = 0;
-    for (uint32_t k = 0; k < hist_len; ++k)
-        if (out.hist[k]) out.max_size = k;
+    out.stats[MCE_STAT_LDS_BYTES] = lds_bytes + sizeof(LdsFixed);
+    out.xrow_tasks = acc[2 + MCE_STAT_XROW_TASKS];
     out.stream_c = ctrl.stream_c;
     out.stream_v = ctrl.stream_v;
     out.stream_truncated = ctrl.stream_trunc != 0;

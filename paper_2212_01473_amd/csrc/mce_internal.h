@@ -83,7 +83,18 @@ mce_status stable_sort_pairs_u32(uint32_t* keys, uint32_t* vals, size_t n, int k
                                  RadixTmp& tmp, hipStream_t s);
 
 // Preprocessing (preprocess.hip) ---------------------------------------------------
+struct GraphMeta {
+    uint32_t n = 0;
+    uint64_t nnz = 0;
+    uint32_t max_degree = 0, degeneracy = 0, max_out = 0, max_in = 0;
+    uint64_t n_isolated = 0;
+    uint32_t voff = 0;  // first union vertex of this graph
+};
+
 struct Oriented {
+    uint32_t ngraphs = 1;             // > 1: a batch enumerated as one disjoint union
+    std::vector<GraphMeta> meta;      // per graph (batch) or one entry
+    DevBuf gid;                       // graph of each rank (batch only)
     uint32_t n = 0;
     uint64_t nnz = 0;
     uint32_t max_degree = 0, degeneracy = 0, rounds = 0;
@@ -101,8 +112,17 @@ struct Oriented {
 };
 
 // rp/ci are device pointers (input space).  validate: run the graph-rule checks.
+// gid_in / voff (device, optional): graph of each input vertex and first vertex
+// of each graph, for a batch loaded as one disjoint union (keys then use the
+// vertex id local to its graph).
 mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t nnz,
-                            bool validate, hipStream_t s, Oriented& g);
+                            bool validate, hipStream_t s, Oriented& g, const uint32_t* gid_in = nullptr,
+                            const uint32_t* voff = nullptr, uint32_t ngraphs = 1);
+
+// Build the union CSR of a batch on the device (host inputs) and preprocess it.
+mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, const uint64_t* row_off,
+                            const uint64_t* col_off, uint32_t n_graphs, bool validate, hipStream_t s,
+                            Oriented& g);
 
 // Enumeration (enumerate.hip) ----------------------------------------------------------
 struct EnumConfig {
@@ -121,9 +141,22 @@ struct EnumConfig {
     uint64_t stream_vcap = 0;
     uint64_t* stream_offsets = nullptr;
     uint64_t stream_ocap = 0;
+    uint64_t xrow_budget_words = 1ull << 18;  // X rows per workgroup (words)
+    uint32_t xrow_ratio = 8;                 // X rows when |X| <= ratio * max(|U|, 64)
+    // explicit work queue (learned order / split); otherwise built from the window
+    const uint32_t* queue_roots = nullptr;
+    const uint32_t* queue_splits = nullptr;
+    uint32_t queue_len = 0;
 };
 
 struct EnumOutput {
+    struct PerGraph {
+        uint64_t count = 0, hash = 0;
+        std::vector<uint64_t> hist;
+        uint32_t max_size = 0;
+    };
+    std::vector<PerGraph> graphs;
+    uint64_t xrow_tasks = 0;
     uint64_t count = 0, hash = 0;
     std::vector<uint64_t> hist;  // index = size
     uint32_t max_size = 0;
@@ -135,13 +168,18 @@ struct EnumOutput {
 
 // One graph's enumeration state kept across calls (scratch sized to the graph).
 struct EnumState {
-    DevBuf roots, ctrl, acc, hist, scratch, ring, flags;
+    DevBuf roots, ctrl, acc, gacc, hist, scratch, ring, flags, small;
     DevBuf tmp_a, tmp_b, tmp_c, scan_tmp;
     size_t scratch_stride = 0;
     uint32_t grid = 0;
     uint32_t lds_cap = 0;
 };
 
+// internal statistic slot beyond the public 16
+constexpr int MCE_STAT_XROW_TASKS = 16;
+
+mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
+                            uint32_t* nroots_out);
 mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
                            EnumOutput& out);
 

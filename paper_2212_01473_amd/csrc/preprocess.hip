@@ -211,16 +211,76 @@ __global__ void k_peel_decrement(const uint32_t* __restrict__ rp, const uint32_t
 }
 
 // ---- orientation -------------------------------------------------------------------
+// rank[], core by rank, key by rank (key of the id local to the vertex's graph),
+// and the graph of each rank when a batch is loaded as one disjoint union.
 __global__ void k_rank_from_order(const uint32_t* __restrict__ order, uint32_t n, uint32_t* __restrict__ rank,
                                   const uint32_t* __restrict__ core, uint32_t* __restrict__ core_r,
-                                  uint64_t* __restrict__ vkey)
+                                  uint64_t* __restrict__ vkey, const uint32_t* __restrict__ gid_in,
+                                  const uint32_t* __restrict__ voff, uint32_t* __restrict__ gid_r)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         uint32_t v = order[i];
         rank[v] = (uint32_t)i;
         core_r[i] = core[v];
-        vkey[i] = fmix64((uint64_t)v * kGamma + kGamma);
+        uint32_t local = v;
+        if (gid_in) {
+            uint32_t g = gid_in[v];
+            local = v - voff[g];
+            gid_r[i] = g;
+        }
+        vkey[i] = fmix64((uint64_t)local * kGamma + kGamma);
+    }
+}
+
+// Per-graph maxima and isolated counts (u32 slots: max degree, degeneracy,
+// max out-degree, max in-degree, isolated vertices).
+__global__ void k_graph_meta(const uint32_t* __restrict__ op, const uint32_t* __restrict__ ip,
+                             const uint32_t* __restrict__ core_r, const uint32_t* __restrict__ gid_r, uint32_t n,
+                             unsigned int* __restrict__ meta)
+{
+    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (size_t)gridDim.x * blockDim.x) {
+        uint32_t g = gid_r[r];
+        uint32_t out = op[r + 1] - op[r], in = ip[r + 1] - ip[r];
+        unsigned int* m = meta + (size_t)g * 8;
+        atomicMax(&m[0], out + in);
+        atomicMax(&m[1], core_r[r]);
+        atomicMax(&m[2], out);
+        atomicMax(&m[3], in);
+        if (out + in == 0) atomicAdd(&m[4], 1u);
+    }
+}
+
+// Union CSR of a batch: row pointers shifted by each graph's first arc, column
+// ids by each graph's first vertex; a column outside its own graph is an error.
+__global__ void k_union_rows(const uint32_t* __restrict__ rp_cat, const uint64_t* __restrict__ row_off,
+                             const uint64_t* __restrict__ col_off, const uint32_t* __restrict__ voff,
+                             const uint32_t* __restrict__ gid_in, uint32_t n, uint32_t* __restrict__ urp)
+{
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        uint32_t g = gid_in[v];
+        urp[v] = rp_cat[row_off[g] + (v - voff[g])] + (uint32_t)col_off[g];
+    }
+}
+
+__global__ void k_union_cols(const uint32_t* __restrict__ ci_cat, const uint32_t* __restrict__ urp,
+                             const uint32_t* __restrict__ gid_in, const uint32_t* __restrict__ voff,
+                             const uint32_t* __restrict__ nloc, uint32_t n, uint32_t* __restrict__ uci,
+                             unsigned long long* err)
+{
+    const uint32_t lane = lane_id();
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
+        uint32_t g = gid_in[v];
+        uint32_t beg = urp[v], end = urp[v + 1];
+        for (uint32_t e = beg + lane; e < end; e += 64) {
+            uint32_t c = ci_cat[e];
+            if (c >= nloc[g]) {
+                atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kErrColRange);
+                c = 0;
+            }
+            uci[e] = c + voff[g];
+        }
     }
 }
 
@@ -314,7 +374,8 @@ __global__ void __launch_bounds__(64) k_sort_rows(const uint32_t* __restrict__ o
 }  // namespace
 
 mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t nnz,
-                            bool validate, hipStream_t s, Oriented& g)
+                            bool validate, hipStream_t s, Oriented& g, const uint32_t* gid_in,
+                            const uint32_t* voff, uint32_t ngraphs)
 {
     mce_status st;
     g.n = n;
@@ -456,10 +517,15 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     if ((st = rank.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = g.core_r.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = g.vkey.alloc(nn * 8)) != MCE_OK) return st;
+    g.ngraphs = std::max(ngraphs, 1u);
+    if (gid_in) {
+        if ((st = g.gid.alloc(nn * 4)) != MCE_OK) return st;
+    }
     if (n) {
         k_rank_from_order<<<blocks_for(n, 256, 4096), 256, 0, s>>>(order.as<uint32_t>(), n, rank.as<uint32_t>(),
                                                                     dcore, g.core_r.as<uint32_t>(),
-                                                                    g.vkey.as<uint64_t>());
+                                                                    g.vkey.as<uint64_t>(), gid_in, voff,
+                                                                    gid_in ? g.gid.as<uint32_t>() : nullptr);
         MCE_HIP_TRY(hipGetLastError());
     }
 
@@ -522,7 +588,144 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     g.perm.bytes = order.bytes;
     order.p = nullptr;
     order.bytes = 0;
+    if (!gid_in) {
+        g.meta.assign(1, GraphMeta());
+        GraphMeta& m = g.meta[0];
+        m.n = n;
+        m.nnz = nnz;
+        m.max_degree = g.max_degree;
+        m.degeneracy = g.degeneracy;
+        m.max_out = g.max_out;
+        m.max_in = g.max_in;
+        m.n_isolated = g.n_isolated;
+        m.voff = 0;
+    } else if (n) {
+        DevBuf dmeta;
+        if ((st = dmeta.alloc((size_t)g.ngraphs * 32)) != MCE_OK) return st;
+        fill_u32(dmeta.as<uint32_t>(), 0, (size_t)g.ngraphs * 8, s);
+        k_graph_meta<<<blocks_for(n, 256, 4096), 256, 0, s>>>(g.op.as<uint32_t>(), g.ip.as<uint32_t>(),
+                                                               g.core_r.as<uint32_t>(), g.gid.as<uint32_t>(), n,
+                                                               dmeta.as<unsigned int>());
+        MCE_HIP_TRY(hipGetLastError());
+        std::vector<uint32_t> hm((size_t)g.ngraphs * 8);
+        MCE_HIP_TRY(hipMemcpyAsync(hm.data(), dmeta.p, hm.size() * 4, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        g.meta.resize(g.ngraphs);
+        for (uint32_t i = 0; i < g.ngraphs; ++i) {
+            GraphMeta& m = g.meta[i];
+            m.max_degree = hm[i * 8 + 0];
+            m.degeneracy = hm[i * 8 + 1];
+            m.max_out = hm[i * 8 + 2];
+            m.max_in = hm[i * 8 + 3];
+            m.n_isolated = hm[i * 8 + 4];
+        }
+    }
     MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, const uint64_t* row_off,
+                            const uint64_t* col_off, uint32_t ng, bool validate, hipStream_t s, Oriented& g)
+{
+    mce_status st;
+    std::vector<uint32_t> voff(ng + 1), nloc(ng);
+    uint64_t N = 0, NNZ = col_off[ng] - col_off[0];
+    for (uint32_t i = 0; i < ng; ++i) {
+        uint64_t ni = row_off[i + 1] - row_off[i] - 1;
+        voff[i] = (uint32_t)N;
+        nloc[i] = (uint32_t)ni;
+        if (validate) {
+            uint64_t nnzi = col_off[i + 1] - col_off[i];
+            if (rp_cat[row_off[i]] != 0 || (uint64_t)rp_cat[row_off[i] + ni] != nnzi) {
+                set_error("invalid graph " + std::to_string(i) + ": row_ptr[0] != 0 or row_ptr[n] != nnz");
+                return MCE_ERR_INVALID_GRAPH;
+            }
+        }
+        N += ni;
+    }
+    voff[ng] = (uint32_t)N;
+    if (N >= 0xFFFFFFFFull || NNZ >= (1ull << 32)) {
+        set_error("batch too large for uint32 ids");
+        return MCE_ERR_UNSUPPORTED;
+    }
+    std::vector<uint32_t> gid_in(N ? N : 1);
+    for (uint32_t i = 0; i < ng; ++i)
+        std::fill(gid_in.begin() + voff[i], gid_in.begin() + voff[i + 1], i);
+    DevBuf d_rp, d_ci, d_roff, d_coff, d_voff, d_nloc, d_gid, urp, uci, err;
+    size_t rp_words = row_off[ng] - row_off[0];
+    if ((st = d_rp.alloc(rp_words * 4)) != MCE_OK) return st;
+    if ((st = d_ci.alloc((NNZ ? NNZ : 1) * 4)) != MCE_OK) return st;
+    if ((st = d_roff.alloc((size_t)(ng + 1) * 8)) != MCE_OK) return st;
+    if ((st = d_coff.alloc((size_t)(ng + 1) * 8)) != MCE_OK) return st;
+    if ((st = d_voff.alloc((size_t)(ng + 1) * 4)) != MCE_OK) return st;
+    if ((st = d_nloc.alloc((size_t)ng * 4)) != MCE_OK) return st;
+    if ((st = d_gid.alloc(gid_in.size() * 4)) != MCE_OK) return st;
+    if ((st = urp.alloc((N + 1) * 4)) != MCE_OK) return st;
+    if ((st = uci.alloc((NNZ ? NNZ : 1) * 4)) != MCE_OK) return st;
+    if ((st = err.alloc(8)) != MCE_OK) return st;
+    std::vector<uint64_t> roff(ng + 1), coff(ng + 1);
+    for (uint32_t i = 0; i <= ng; ++i) {
+        roff[i] = row_off[i] - row_off[0];
+        coff[i] = col_off[i] - col_off[0];
+    }
+    MCE_HIP_TRY(hipMemcpyAsync(d_rp.p, rp_cat + row_off[0], rp_words * 4, hipMemcpyHostToDevice, s));
+    if (NNZ) MCE_HIP_TRY(hipMemcpyAsync(d_ci.p, ci_cat + col_off[0], NNZ * 4, hipMemcpyHostToDevice, s));
+    MCE_HIP_TRY(hipMemcpyAsync(d_roff.p, roff.data(), (ng + 1) * 8, hipMemcpyHostToDevice, s));
+    MCE_HIP_TRY(hipMemcpyAsync(d_coff.p, coff.data(), (ng + 1) * 8, hipMemcpyHostToDevice, s));
+    MCE_HIP_TRY(hipMemcpyAsync(d_voff.p, voff.data(), (ng + 1) * 4, hipMemcpyHostToDevice, s));
+    MCE_HIP_TRY(hipMemcpyAsync(d_nloc.p, nloc.data(), ng * 4, hipMemcpyHostToDevice, s));
+    MCE_HIP_TRY(hipMemcpyAsync(d_gid.p, gid_in.data(), gid_in.size() * 4, hipMemcpyHostToDevice, s));
+    uint64_t einit = ~0ull;
+    MCE_HIP_TRY(hipMemcpyAsync(err.p, &einit, 8, hipMemcpyHostToDevice, s));
+    uint32_t nnz32 = (uint32_t)NNZ;
+    MCE_HIP_TRY(hipMemcpyAsync(urp.as<uint32_t>() + N, &nnz32, 4, hipMemcpyHostToDevice, s));
+    if (N) {
+        k_union_rows<<<blocks_for(N, 256, 8192), 256, 0, s>>>(d_rp.as<uint32_t>(), d_roff.as<uint64_t>(),
+                                                              d_coff.as<uint64_t>(), d_voff.as<uint32_t>(),
+                                                              d_gid.as<uint32_t>(), (uint32_t)N, urp.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        if (validate) {
+            // row pointers must be monotone before any column range is read
+            k_validate_rowptr<<<blocks_for(N + 1, 256), 256, 0, s>>>(urp.as<uint32_t>(), (uint32_t)N, NNZ,
+                                                                     err.as<unsigned long long>());
+            MCE_HIP_TRY(hipGetLastError());
+            uint64_t rerr = 0;
+            MCE_HIP_TRY(hipMemcpyAsync(&rerr, err.p, 8, hipMemcpyDeviceToHost, s));
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+            if (rerr != ~0ull) {
+                uint32_t v = (uint32_t)(rerr >> 32);
+                uint32_t gi = v < N ? gid_in[v] : ng - 1;
+                set_error("invalid graph " + std::to_string(gi) + ": row_ptr not monotone at row " +
+                          std::to_string(v - voff[gi]));
+                return MCE_ERR_INVALID_GRAPH;
+            }
+        }
+        k_union_cols<<<blocks_for(N, 4, 16384), 256, 0, s>>>(d_ci.as<uint32_t>(), urp.as<uint32_t>(),
+                                                             d_gid.as<uint32_t>(), d_voff.as<uint32_t>(),
+                                                             d_nloc.as<uint32_t>(), (uint32_t)N, uci.as<uint32_t>(),
+                                                             err.as<unsigned long long>());
+        MCE_HIP_TRY(hipGetLastError());
+    }
+    uint64_t herr = 0;
+    MCE_HIP_TRY(hipMemcpyAsync(&herr, err.p, 8, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    d_rp.release();
+    d_ci.release();
+    if (validate && herr != ~0ull) {
+        uint32_t v = (uint32_t)(herr >> 32);
+        uint32_t gi = gid_in[v];
+        set_error("invalid graph " + std::to_string(gi) + ": column out of range at row " +
+                  std::to_string(v - voff[gi]));
+        return MCE_ERR_INVALID_GRAPH;
+    }
+    st = preprocess_graph(urp.as<uint32_t>(), uci.as<uint32_t>(), (uint32_t)N, NNZ, validate, s, g,
+                          d_gid.as<uint32_t>(), d_voff.as<uint32_t>(), ng);
+    if (st != MCE_OK) return st;
+    for (uint32_t i = 0; i < ng; ++i) {
+        g.meta[i].n = nloc[i];
+        g.meta[i].nnz = col_off[i + 1] - col_off[i];
+        g.meta[i].voff = voff[i];
+    }
     return MCE_OK;
 }
 

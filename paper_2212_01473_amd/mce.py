@@ -66,7 +66,8 @@ class Options(C.Structure):
                 ("wg_per_cu", C.c_uint32), ("bitmap_max_p", C.c_uint32), ("donate_min_p", C.c_uint32),
                 ("donate_max_depth", C.c_uint32), ("split_top", C.c_uint32), ("model", C.c_void_p),
                 ("stream", C.c_void_p), ("timeout_ms", C.c_uint64), ("root_order", C.c_void_p),
-                ("root_count", C.c_void_p), ("root_hash", C.c_void_p), ("root_nodes", C.c_void_p)]
+                ("root_count", C.c_void_p), ("root_hash", C.c_void_p), ("root_nodes", C.c_void_p),
+                ("xrow_ratio", C.c_uint32), ("reserved", C.c_uint32), ("xrow_budget_words", C.c_uint64)]
 
 
 class Result(C.Structure):
@@ -244,8 +245,11 @@ def load_batch(graphs, validate: bool = True) -> Graph:
 
 def make_options(max_root_core: int = FULL, worker_list: bool = True, flags: int = 0, wg_per_cu: int = 0,
                  bitmap_max_p: int = 0, donate_min_p: int = 0, donate_max_depth: int = 0,
-                 timeout_ms: int = 0, stream=None, root_order=None, root_stats=None) -> Options:
+                 timeout_ms: int = 0, stream=None, root_order=None, root_stats=None, xrow_ratio: int = 0,
+                 xrow_budget_words: int = 0) -> Options:
     o = Options()
+    o.xrow_ratio = xrow_ratio
+    o.xrow_budget_words = xrow_budget_words
     o.struct_size = C.sizeof(Options)
     o.flags = flags | (F_WORKER_LIST if worker_list else 0) | F_STATS
     o.max_root_core = int(max_root_core) & 0xFFFFFFFF

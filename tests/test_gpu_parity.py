@@ -292,3 +292,27 @@ def test_batch_api(gpu_lib):
     for g, r in zip(graphs, res):
         exp = oracle.mce(g)
         assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
+
+
+def test_batch_union_matches_per_graph_oracle(gpu_lib):
+    graphs = I.batch_graphs(count=48, seed=104, nmin=30, nmax=400)
+    graphs.append(I.empty_graph(7))
+    graphs.append(I.complete_graph(70))
+    with gpu_lib.load_batch(graphs) as dg:
+        res = gpu_lib.enumerate_batch(dg)
+        info = [dg.info(i) for i in range(len(graphs))]
+        core, rnd, order = dg.order_arrays(3)
+    for i, (g, r) in enumerate(zip(graphs, res)):
+        exp = oracle_result(g)
+        assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist)), i
+        assert info[i].n == g.n and info[i].degeneracy == exp.degeneracy
+    # core numbers of a member graph are its own (the union does not mix graphs)
+    c3, _, _ = oracle.sync_peel(graphs[3])
+    assert (core == c3).all()
+    assert sorted(order.tolist()) == list(range(graphs[3].n))
+
+
+def test_no_x_rows_variant(gpu_lib):
+    # X rows disabled: every X_X test goes to the original graph
+    check(gpu_lib, I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 62), xrow_budget_words=1)
+    check(gpu_lib, _dense(2), xrow_budget_words=1)
