@@ -125,8 +125,9 @@ mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t
 
 /* ---- enumeration flags */
 #define MCE_F_WORKER_LIST   0x01u  /* donate branches to idle wavefronts (Section III-C) */
-#define MCE_F_LEARNED_ORDER 0x02u  /* order roots by the cost model in opt->model */
-#define MCE_F_SPLIT         0x04u  /* split the costliest roots into level-1 branch tasks */
+#define MCE_F_LEARNED_ORDER 0x02u  /* order roots by descending cost predicted by opt->model */
+#define MCE_F_SPLIT         0x04u  /* with LEARNED_ORDER: split the costliest roots into groups of
+                                      level-1 branches (group c of C takes branches t, t % C == c) */
 #define MCE_F_STATS         0x08u  /* fill mce_result.stats */
 #define MCE_F_STREAM        0x10u  /* write cliques to the stream buffers */
 #define MCE_F_ROOT_STATS    0x20u  /* per-root counters into opt->root_* (device arrays) */
@@ -220,6 +221,47 @@ mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res);
  */
 mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result* res,
                                uint32_t n_res);
+
+/* ---- learned root ordering (all arrays are device memory) */
+
+/* Floats in a cost model: W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64],
+ * b3[64], W4[64], b4, then the per-feature mean[4] and std[4] used to
+ * normalise inputs.  Hidden layers use ReLU; the output predicts
+ * log(1 + search-tree nodes) of a first-level subtree. */
+#define MCE_MODEL_FLOATS 8713
+
+/*
+ * Cheap features of first-level subtrees, 4 floats per root: log(1+degree),
+ * log(1+core number), log(1+2-hop count) (sum of neighbour degrees), and the
+ * edge density of the root's later-neighbour set P.  root_ids: device
+ * uint32[n_roots] input vertex ids of a single-graph handle; feat: device
+ * float[n_roots * 4].
+ */
+mce_status mce_root_features(const mce_graph* g, const uint32_t* root_ids, uint32_t n_roots, float* feat,
+                             void* stream);
+
+/* BF16 inference (weights and activations rounded to bfloat16, FP32 sums):
+ * out[i] = predicted log(1 + nodes) for feat[i*4 .. i*4+3]. */
+mce_status mce_model_predict(const float* model, const float* feat, uint32_t n, float* out, void* stream);
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(mce_train_options) */
+    uint32_t epochs;       /* full-batch Adam steps */
+    float lr, beta1, beta2, eps;
+    uint32_t fit_norm;     /* 1: set mean/std of the model from feat before training */
+    uint32_t reserved;
+} mce_train_options;
+
+/* Train a model in place with FP32 forward/backward kernels and Adam
+ * (Kingma and Ba, 2015) on mean squared error; model holds the initial
+ * weights.  loss_history: host float[epochs] or NULL. */
+mce_status mce_model_train(float* model, const float* feat, const float* target, uint32_t n,
+                           const mce_train_options* opt, float* loss_history, void* stream);
+
+/* One FP32 forward and backward pass: grad (device float[MCE_MODEL_FLOATS],
+ * zero for mean/std) of the mean squared error, and the loss (host). */
+mce_status mce_model_loss_grad(const float* model, const float* feat, const float* target, uint32_t n,
+                               float* grad, float* loss, void* stream);
 
 /* Release a handle (NULL is a no-op). */
 void mce_free(mce_graph* g);

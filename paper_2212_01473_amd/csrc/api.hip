@@ -94,6 +94,12 @@ mce_status config_from(const mce_options* opt, EnumConfig& cfg)
     cfg.root_count = opt->root_count;
     cfg.root_hash = opt->root_hash;
     cfg.root_nodes = opt->root_nodes;
+    cfg.model = opt->model;
+    cfg.split_top = opt->split_top;
+    if ((cfg.flags & MCE_F_SPLIT) && !(cfg.flags & MCE_F_LEARNED_ORDER))
+        return fail(MCE_ERR_INVALID_ARG, "MCE_F_SPLIT needs MCE_F_LEARNED_ORDER");
+    if ((cfg.flags & MCE_F_LEARNED_ORDER) && (cfg.flags & (MCE_F_CUSTOM_ORDER | MCE_F_REVERSE_ORDER)))
+        return fail(MCE_ERR_INVALID_ARG, "learned order excludes custom and reverse orders");
     if (cfg.bitmap_max_p > 4096) return fail(MCE_ERR_INVALID_ARG, "bitmap_max_p must be <= 4096");
     return MCE_OK;
 }
@@ -220,8 +226,6 @@ mce_status mce_enumerate(mce_graph* g, const mce_options* opt, mce_result* res)
         cfg.stream_offsets = res->stream_offsets;
         cfg.stream_ocap = res->stream_ocap;
     }
-    if (cfg.flags & (MCE_F_LEARNED_ORDER | MCE_F_SPLIT))
-        return fail(MCE_ERR_UNSUPPORTED, "learned ordering is not available in this build");
     hipStream_t s = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
     EnumOutput eo;
     st = enumerate_graph(*g->graphs[0], cfg, g->state, s, eo);
@@ -240,8 +244,6 @@ mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result*
     if (st != MCE_OK) return st;
     if (cfg.flags & (MCE_F_STREAM | MCE_F_ROOT_STATS | MCE_F_CUSTOM_ORDER))
         return fail(MCE_ERR_INVALID_ARG, "stream, per-root statistics and custom order are single-graph only");
-    if (cfg.flags & (MCE_F_LEARNED_ORDER | MCE_F_SPLIT))
-        return fail(MCE_ERR_UNSUPPORTED, "learned ordering is not available in this build");
     for (uint32_t i = 0; i < o.ngraphs; ++i)
         if (res[i].hist_len && !res[i].hist) return fail(MCE_ERR_INVALID_ARG, "hist is NULL with hist_len > 0");
     hipStream_t s = opt ? reinterpret_cast<hipStream_t>(opt->stream) : nullptr;
@@ -255,6 +257,54 @@ mce_status mce_enumerate_batch(mce_graph* g, const mce_options* opt, mce_result*
         else if (si > 0 && worst == MCE_OK) worst = si;
     }
     return worst;
+}
+
+mce_status mce_root_features(const mce_graph* g, const uint32_t* root_ids, uint32_t n_roots, float* feat,
+                             void* stream)
+{
+    set_error("");
+    if (!g || (!root_ids && n_roots) || (!feat && n_roots)) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    if (g->batch) return fail(MCE_ERR_INVALID_ARG, "features are for single-graph handles");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Oriented& o = *g->graphs[0];
+    DevBuf ranks;
+    mce_status st;
+    if ((st = ranks.alloc((size_t)(n_roots ? n_roots : 1) * 4)) != MCE_OK) return st;
+    if ((st = ids_to_ranks(o, root_ids, n_roots, ranks.as<uint32_t>(), s)) != MCE_OK) return st;
+    if ((st = root_features(o, ranks.as<uint32_t>(), n_roots, feat, s)) != MCE_OK) return st;
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+mce_status mce_model_predict(const float* model, const float* feat, uint32_t n, float* out, void* stream)
+{
+    set_error("");
+    if (!model || (n && (!feat || !out))) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    mce_status st = model_predict(model, feat, n, out, s);
+    if (st != MCE_OK) return st;
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+mce_status mce_model_train(float* model, const float* feat, const float* target, uint32_t n,
+                           const mce_train_options* opt, float* loss_history, void* stream)
+{
+    set_error("");
+    if (!model || !feat || !target || !opt) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    if (opt->struct_size != sizeof(mce_train_options))
+        return fail(MCE_ERR_INVALID_ARG, "mce_train_options.struct_size must be sizeof(mce_train_options)");
+    if (n == 0 || opt->epochs == 0) return fail(MCE_ERR_INVALID_ARG, "no samples or no epochs");
+    return model_train(model, feat, target, n, opt->epochs, opt->lr, opt->beta1, opt->beta2, opt->eps,
+                       opt->fit_norm != 0, loss_history, reinterpret_cast<hipStream_t>(stream));
+}
+
+mce_status mce_model_loss_grad(const float* model, const float* feat, const float* target, uint32_t n,
+                               float* grad, float* loss, void* stream)
+{
+    set_error("");
+    if (!model || !feat || !target || !grad) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    return model_loss_grad(model, feat, target, n, grad, loss, reinterpret_cast<hipStream_t>(stream));
 }
 
 void mce_free(mce_graph* g) { delete g; }

@@ -1400,6 +1400,15 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
         roots = cfg.queue_roots;
         splits = cfg.queue_splits;
         nroots = cfg.queue_len;
+    } else if (cfg.flags & MCE_F_LEARNED_ORDER) {
+        if (!cfg.model) {
+            set_error("MCE_F_LEARNED_ORDER without a model");
+            return MCE_ERR_INVALID_ARG;
+        }
+        if ((rc = learned_queue(g, cfg, st, s, G, st.lq)) != MCE_OK) return rc;
+        roots = st.lq.qroots;
+        splits = st.lq.qsplits;
+        nroots = st.lq.len;
     } else {
         if ((rc = build_root_queue(g, cfg, st, s, &nroots)) != MCE_OK) return rc;
         roots = st.roots.as<uint32_t>();

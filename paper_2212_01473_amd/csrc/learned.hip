@@ -1,0 +1,617 @@
+// Learned root ordering: cheap per-root features, a 4-64-64-64-1 MLP trained on
+// the GPU (FP32 forward, backward and Adam) from subtree costs the plain
+// enumeration measures, BF16 inference, and the work queue built from the
+// predictions (roots in descending predicted cost, the costliest split into
+// level-1 branch groups).  None of this changes which cliques are found: the
+// queue is a permutation of the window's roots, and a split root's groups
+// together cover exactly its level-1 branches.
+#include "mce_internal.h"
+
+#include <cmath>
+
+namespace mce {
+
+namespace {
+
+// Model layout (floats): W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64],
+// b3[64], W4[64], b4, mean[4], std[4].
+constexpr int kIn = 4, kH = 64;
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+              ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kH, oMean = ob4 + 1, oStd = oMean + kIn,
+              kModel = oStd + kIn;
+static_assert(kModel == MCE_MODEL_FLOATS, "model layout");
+constexpr int kTrainable = oMean;  // mean/std are fitted, not trained
+
+unsigned blocks_for(size_t items, unsigned per_block, unsigned cap = 65536)
+{
+    size_t b = (items + per_block - 1) / per_block;
+    if (b == 0) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------- features
+// Per root v (rank): log1p(degree), log1p(core), log1p(2-hop count = sum of
+// neighbour degrees), and the edge density of its later-neighbour set P
+// (edges inside P / C(|P|, 2); 0 when |P| < 2).  One wave per root; P is
+// staged in LDS (|P| <= 4095) and every later list of a P vertex is searched
+// in it.
+constexpr int kFeatWaves = 4;
+constexpr int kFeatCap = 4096;
+
+__global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __restrict__ op,
+                                                             const uint32_t* __restrict__ oc,
+                                                             const uint32_t* __restrict__ ip,
+                                                             const uint32_t* __restrict__ ic,
+                                                             const uint32_t* __restrict__ core_r,
+                                                             const uint32_t* __restrict__ roots, uint32_t nr,
+                                                             float* __restrict__ feat)
+{
+    __shared__ uint32_t buf[kFeatWaves][kFeatCap];
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x >> 6;
+    uint32_t* P = buf[wv];
+    for (size_t k = (size_t)blockIdx.x * kFeatWaves + wv; k < nr; k += (size_t)gridDim.x * kFeatWaves) {
+        uint32_t v = roots[k];
+        uint32_t pb = op[v], np = op[v + 1] - pb;
+        uint32_t xb = ip[v], nx = ip[v + 1] - xb;
+        // 2-hop count
+        uint64_t two = 0;
+        for (uint32_t i = lane; i < np + nx; i += 64) {
+            uint32_t u = i < np ? oc[pb + i] : ic[xb + i - np];
+            two += (uint64_t)(op[u + 1] - op[u]) + (ip[u + 1] - ip[u]);
+        }
+        // density of P
+        uint64_t tri = 0;
+        if (np >= 2) {
+            for (uint32_t i = lane; i < np; i += 64) P[i] = oc[pb + i];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t pmax = P[np - 1];
+            for (uint32_t a = 0; a < np; ++a) {
+                uint32_t u = P[a];
+                uint32_t ub = op[u], ue = op[u + 1];
+                for (uint32_t e = ub + lane; e < ue; e += 64) {
+                    uint32_t x = oc[e];
+                    if (x <= pmax) {
+                        uint32_t lo = a + 1, hi = np;
+                        while (lo < hi) {
+                            uint32_t mid = (lo + hi) >> 1;
+                            if (P[mid] < x) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        tri += lo < np && P[lo] == x;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            two += __shfl_xor(two, off, 64);
+            tri += __shfl_xor(tri, off, 64);
+        }
+        if (lane == 0) {
+            float* f = feat + (size_t)k * 4;
+            f[0] = log1pf((float)(np + nx));
+            f[1] = log1pf((float)core_r[v]);
+            f[2] = log1pf((float)two);
+            f[3] = np >= 2 ? (float)((double)tri / (0.5 * (double)np * (double)(np - 1))) : 0.f;
+        }
+    }
+}
+
+__global__ void k_ids_to_ranks(const uint32_t* __restrict__ ids, uint32_t n, const uint32_t* __restrict__ rank,
+                               uint32_t* __restrict__ out)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = rank[ids[i]];
+}
+
+// ---------------------------------------------------------------- BF16 inference
+__device__ inline uint16_t to_bf16(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(b >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Weights and activations rounded to BF16, sums accumulated in FP32.
+__global__ void __launch_bounds__(256) k_mlp_infer_bf16(const float* __restrict__ model,
+                                                        const float* __restrict__ feat, uint32_t n,
+                                                        float* __restrict__ out)
+{
+    __shared__ uint16_t w[kModel];
+    __shared__ float norm[2 * kIn];
+    for (int i = threadIdx.x; i < kModel; i += blockDim.x) w[i] = to_bf16(model[i]);
+    if (threadIdx.x < 2 * kIn) norm[threadIdx.x] = model[oMean + threadIdx.x];
+    __syncthreads();
+    for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+        float a0[kIn];
+        for (int i = 0; i < kIn; ++i)
+            a0[i] = from_bf16(to_bf16((feat[s * kIn + i] - norm[i]) / norm[kIn + i]));
+        float h1[kH], h2[kH];
+        for (int j = 0; j < kH; ++j) {
+            float acc = from_bf16(w[ob1 + j]);
+            for (int i = 0; i < kIn; ++i) acc += from_bf16(w[oW1 + j * kIn + i]) * a0[i];
+            h1[j] = from_bf16(to_bf16(fmaxf(acc, 0.f)));
+        }
+        for (int j = 0; j < kH; ++j) {
+            float acc = from_bf16(w[ob2 + j]);
+            for (int k = 0; k < kH; ++k) acc += from_bf16(w[oW2 + j * kH + k]) * h1[k];
+            h2[j] = from_bf16(to_bf16(fmaxf(acc, 0.f)));
+        }
+        float y = from_bf16(w[ob4]);
+        for (int j = 0; j < kH; ++j) {
+            float acc = from_bf16(w[ob3 + j]);
+            for (int k = 0; k < kH; ++k) acc += from_bf16(w[oW3 + j * kH + k]) * h2[k];
+            y += from_bf16(w[oW4 + j]) * from_bf16(to_bf16(fmaxf(acc, 0.f)));
+        }
+        out[s] = y;
+    }
+}
+
+// ---------------------------------------------------------------- FP32 training
+// Activations are stored feature-major ([64][n]) so a thread per sample reads
+// and writes coalesced columns.
+struct TrainBufs {
+    float *a0, *h1, *h2, *h3, *d1, *d2, *d3, *dy, *part;
+};
+
+// Forward, loss term and backward through the activations for one sample per
+// thread: stores a0 (normalised input), h1..h3, dy = dL/dy, d3..d1 = dL/dz
+// (pre-activation gradients).  Loss = mean over samples of (y - t)^2.
+__global__ void __launch_bounds__(256) k_mlp_fwd_bwd(const float* __restrict__ model,
+                                                     const float* __restrict__ feat,
+                                                     const float* __restrict__ target, uint32_t n, TrainBufs b,
+                                                     float* __restrict__ loss_part)
+{
+    __shared__ float w[kModel];
+    __shared__ float red[256];
+    for (int i = threadIdx.x; i < kModel; i += blockDim.x) w[i] = model[i];
+    __syncthreads();
+    float lsum = 0.f;
+    for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+        float a0[kIn];
+        for (int i = 0; i < kIn; ++i) {
+            a0[i] = (feat[s * kIn + i] - w[oMean + i]) / w[oStd + i];
+            b.a0[(size_t)i * n + s] = a0[i];
+        }
+        float h[kH];
+        for (int j = 0; j < kH; ++j) {
+            float acc = w[ob1 + j];
+            for (int i = 0; i < kIn; ++i) acc += w[oW1 + j * kIn + i] * a0[i];
+            h[j] = fmaxf(acc, 0.f);
+            b.h1[(size_t)j * n + s] = h[j];
+        }
+        float g[kH];
+        for (int j = 0; j < kH; ++j) {
+            float acc = w[ob2 + j];
+            for (int k = 0; k < kH; ++k) acc += w[oW2 + j * kH + k] * h[k];
+            g[j] = fmaxf(acc, 0.f);
+            b.h2[(size_t)j * n + s] = g[j];
+        }
+        float y = w[ob4];
+        for (int j = 0; j < kH; ++j) {
+            float acc = w[ob3 + j];
+            for (int k = 0; k < kH; ++k) acc += w[oW3 + j * kH + k] * g[k];
+            float h3 = fmaxf(acc, 0.f);
+            b.h3[(size_t)j * n + s] = h3;
+            y += w[oW4 + j] * h3;
+        }
+        float r = y - target[s];
+        lsum += r * r;
+        float dy = 2.f * r / (float)n;
+        b.dy[s] = dy;
+        // backward through the activations
+        float d3[kH];
+        for (int j = 0; j < kH; ++j) {
+            d3[j] = b.h3[(size_t)j * n + s] > 0.f ? dy * w[oW4 + j] : 0.f;
+            b.d3[(size_t)j * n + s] = d3[j];
+        }
+        float d2[kH];
+        for (int k = 0; k < kH; ++k) {
+            float acc = 0.f;
+            for (int j = 0; j < kH; ++j) acc += d3[j] * w[oW3 + j * kH + k];
+            d2[k] = g[k] > 0.f ? acc : 0.f;
+            b.d2[(size_t)k * n + s] = d2[k];
+        }
+        for (int k = 0; k < kH; ++k) {
+            float acc = 0.f;
+            for (int j = 0; j < kH; ++j) acc += d2[j] * w[oW2 + j * kH + k];
+            b.d1[(size_t)k * n + s] = h[k] > 0.f ? acc : 0.f;
+        }
+    }
+    red[threadIdx.x] = lsum;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// Weight gradients: per block, sums over one chunk of samples for every
+// trainable parameter (dW_l[j][k] = sum_s d_l[j][s] * x_{l-1}[k][s]); partial
+// sums go to part[block][param] and are reduced in a fixed order afterwards,
+// so the result does not depend on scheduling.
+constexpr int kGradChunk = 4096;
+constexpr int kTile = 64;
+
+__global__ void __launch_bounds__(256) k_mlp_grad_partial(TrainBufs b, uint32_t n)
+{
+    __shared__ float dt[kH][kTile + 1];
+    __shared__ float xt[kH][kTile + 1];
+    const uint32_t s0 = blockIdx.x * kGradChunk;
+    const uint32_t s1 = min(n, s0 + kGradChunk);
+    float* part = b.part + (size_t)blockIdx.x * kTrainable;
+    // the four layers: (delta, input, rows, cols, W offset, b offset)
+    for (int layer = 0; layer < 4; ++layer) {
+        const float* D = layer == 0 ? b.d1 : layer == 1 ? b.d2 : layer == 2 ? b.d3 : b.dy;
+        const float* X = layer == 0 ? b.a0 : layer == 1 ? b.h1 : layer == 2 ? b.h2 : b.h3;
+        const int rows = layer == 3 ? 1 : kH;
+        const int cols = layer == 0 ? kIn : kH;
+        const int oW = layer == 0 ? oW1 : layer == 1 ? oW2 : layer == 2 ? oW3 : oW4;
+        const int oB = layer == 0 ? ob1 : layer == 1 ? ob2 : layer == 2 ? ob3 : ob4;
+        // each thread owns up to 16 (j, k) pairs of this layer plus bias terms
+        float accw[16];
+        float accb = 0.f;
+        for (int q = 0; q < 16; ++q) accw[q] = 0.f;
+        for (uint32_t t0 = s0; t0 < s1; t0 += kTile) {
+            uint32_t cnt = min((uint32_t)kTile, s1 - t0);
+            for (int idx = threadIdx.x; idx < kH * kTile; idx += blockDim.x) {
+                int r = idx / kTile, c = idx % kTile;
+                dt[r][c] = (r < rows && (uint32_t)c < cnt) ? D[(size_t)r * n + t0 + c] : 0.f;
+                xt[r][c] = (r < cols && (uint32_t)c < cnt) ? X[(size_t)r * n + t0 + c] : 0.f;
+            }
+            __syncthreads();
+            for (int q = 0; q < 16; ++q) {
+                int pidx = threadIdx.x * 16 + q;  // 0 .. 4095
+                int j = pidx / kH, k = pidx % kH;
+                if (j < rows && k < cols) {
+                    float a = 0.f;
+                    for (uint32_t c = 0; c < cnt; ++c) a += dt[j][c] * xt[k][c];
+                    accw[q] += a;
+                }
+            }
+            if ((int)threadIdx.x < rows) {
+                float a = 0.f;
+                for (uint32_t c = 0; c < cnt; ++c) a += dt[threadIdx.x][c];
+                accb += a;
+            }
+            __syncthreads();
+        }
+        for (int q = 0; q < 16; ++q) {
+            int pidx = threadIdx.x * 16 + q;
+            int j = pidx / kH, k = pidx % kH;
+            if (j < rows && k < cols) part[oW + (layer == 3 ? k : j * cols + k)] = accw[q];
+        }
+        if ((int)threadIdx.x < rows) part[oB + threadIdx.x] = accb;
+        __syncthreads();
+    }
+}
+
+__global__ void k_grad_reduce(const float* __restrict__ part, uint32_t nparts, float* __restrict__ grad)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kModel; i += gridDim.x * blockDim.x) {
+        float a = 0.f;
+        if (i < kTrainable)
+            for (uint32_t p = 0; p < nparts; ++p) a += part[(size_t)p * kTrainable + i];
+        grad[i] = a;
+    }
+}
+
+// Adam (Kingma and Ba, 2015), bias-corrected, on the trainable parameters.
+__global__ void k_adam(float* __restrict__ model, const float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kTrainable; i += gridDim.x * blockDim.x) {
+        float g = grad[i];
+        float mi = b1 * m[i] + (1.f - b1) * g;
+        float vi = b2 * v[i] + (1.f - b2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        float mh = mi / c1, vh = vi / c2;
+        model[i] -= lr * mh / (sqrtf(vh) + eps);
+    }
+}
+
+// mean / std of each feature column (two passes, double accumulation) into the model.
+__global__ void k_fit_norm(const float* __restrict__ feat, uint32_t n, float* __restrict__ model)
+{
+    __shared__ double red[256];
+    int f = blockIdx.x;  // one block per feature
+    double s = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) s += feat[(size_t)i * kIn + f];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    double mean = red[0] / (n ? n : 1);
+    __syncthreads();
+    double q = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double d = feat[(size_t)i * kIn + f] - mean;
+        q += d * d;
+    }
+    red[threadIdx.x] = q;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double sd = sqrt(red[0] / (n ? n : 1));
+        model[oMean + f] = (float)mean;
+        model[oStd + f] = (float)(sd > 1e-6 ? sd : 1.0);
+    }
+}
+
+// ---------------------------------------------------------------- learned queue
+// Sort key: descending predicted cost (quantised log-cost), stable in rank order.
+__global__ void k_score_keys(const float* __restrict__ score, uint32_t n, uint32_t* __restrict__ key)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float s = fminf(fmaxf(score[i], 0.f), 63.f);
+        uint32_t q = (uint32_t)(s * 65536.f);  // < 2^22
+        key[i] = (1u << 22) - 1u - q;
+    }
+}
+
+// Number of groups each queued root is split into: predicted nodes divided by
+// the target task size, capped; only the first split_top roots of the order.
+__global__ void k_split_counts(const float* __restrict__ score_sorted, uint32_t n, uint32_t split_top,
+                               float target, uint32_t* __restrict__ groups)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t c = 1;
+        if (i < split_top) {
+            float nodes = expm1f(fminf(fmaxf(score_sorted[i], 0.f), 40.f));
+            float g = ceilf(nodes / target);
+            c = (uint32_t)fminf(fmaxf(g, 1.f), 64.f);
+        }
+        groups[i] = c;
+    }
+}
+
+__global__ void k_split_expand(const uint32_t* __restrict__ roots_sorted, const uint32_t* __restrict__ groups,
+                               const uint32_t* __restrict__ pos, uint32_t n, uint32_t* __restrict__ qroots,
+                               uint32_t* __restrict__ qsplits)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t C = groups[i], base = pos[i], r = roots_sorted[i];
+        for (uint32_t c = 0; c < C; ++c) {
+            qroots[base + c] = r;
+            qsplits[base + c] = C > 1 ? ((C << 16) | c) : 0u;
+        }
+    }
+}
+
+template <class T>
+__global__ void k_gather(const T* __restrict__ src, const uint32_t* __restrict__ idx, uint32_t n,
+                         T* __restrict__ dst)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[idx[i]];
+}
+
+}  // namespace
+
+mce_status root_features(const Oriented& g, const uint32_t* roots_rank, uint32_t nr, float* feat, hipStream_t s)
+{
+    if (nr == 0) return MCE_OK;
+    if (g.max_out >= (uint32_t)kFeatCap) {
+        set_error("first-level P too large for the feature kernel");
+        return MCE_ERR_UNSUPPORTED;
+    }
+    k_features<<<blocks_for(nr, kFeatWaves, 65536), 64 * kFeatWaves, 0, s>>>(
+        g.op.as<uint32_t>(), g.oc.as<uint32_t>(), g.ip.as<uint32_t>(), g.ic.as<uint32_t>(), g.core_r.as<uint32_t>(),
+        roots_rank, nr, feat);
+    MCE_HIP_TRY(hipGetLastError());
+    return MCE_OK;
+}
+
+mce_status ids_to_ranks(const Oriented& g, const uint32_t* ids, uint32_t n, uint32_t* out, hipStream_t s)
+{
+    if (!n) return MCE_OK;
+    k_ids_to_ranks<<<blocks_for(n, 256, 8192), 256, 0, s>>>(ids, n, g.rank.as<uint32_t>(), out);
+    MCE_HIP_TRY(hipGetLastError());
+    return MCE_OK;
+}
+
+mce_status model_predict(const float* model, const float* feat, uint32_t n, float* out, hipStream_t s)
+{
+    if (!n) return MCE_OK;
+    k_mlp_infer_bf16<<<blocks_for(n, 256, 4096), 256, 0, s>>>(model, feat, n, out);
+    MCE_HIP_TRY(hipGetLastError());
+    return MCE_OK;
+}
+
+namespace {
+struct TrainState {
+    DevBuf act, part, grad, m, v, lpart;
+    TrainBufs b;
+    uint32_t nparts = 0, nloss = 0;
+    mce_status setup(uint32_t n)
+    {
+        mce_status st;
+        size_t cols = (size_t)kIn + 6 * kH + 1;  // a0, h1..h3, d1..d3, dy
+        if ((st = act.alloc(cols * n * 4 + 64)) != MCE_OK) return st;
+        nparts = (n + kGradChunk - 1) / kGradChunk;
+        if ((st = part.alloc((size_t)nparts * kTrainable * 4 + 64)) != MCE_OK) return st;
+        if ((st = grad.alloc(kModel * 4)) != MCE_OK) return st;
+        if ((st = m.alloc(kModel * 4)) != MCE_OK) return st;
+        if ((st = v.alloc(kModel * 4)) != MCE_OK) return st;
+        nloss = blocks_for(n, 256, 2048);
+        if ((st = lpart.alloc((size_t)nloss * 4)) != MCE_OK) return st;
+        float* a = act.as<float>();
+        b.a0 = a;
+        b.h1 = b.a0 + (size_t)kIn * n;
+        b.h2 = b.h1 + (size_t)kH * n;
+        b.h3 = b.h2 + (size_t)kH * n;
+        b.d1 = b.h3 + (size_t)kH * n;
+        b.d2 = b.d1 + (size_t)kH * n;
+        b.d3 = b.d2 + (size_t)kH * n;
+        b.dy = b.d3 + (size_t)kH * n;
+        b.part = part.as<float>();
+        return MCE_OK;
+    }
+    mce_status loss_grad(const float* model, const float* feat, const float* target, uint32_t n, hipStream_t s,
+                         float* loss_host)
+    {
+        k_mlp_fwd_bwd<<<nloss, 256, 0, s>>>(model, feat, target, n, b, lpart.as<float>());
+        MCE_HIP_TRY(hipGetLastError());
+        k_mlp_grad_partial<<<nparts, 256, 0, s>>>(b, n);
+        MCE_HIP_TRY(hipGetLastError());
+        k_grad_reduce<<<blocks_for(kModel, 256), 256, 0, s>>>(part.as<float>(), nparts, grad.as<float>());
+        MCE_HIP_TRY(hipGetLastError());
+        if (loss_host) {
+            std::vector<float> lp(nloss);
+            MCE_HIP_TRY(hipMemcpyAsync(lp.data(), lpart.p, nloss * 4, hipMemcpyDeviceToHost, s));
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+            double t = 0;
+            for (float x : lp) t += x;
+            *loss_host = (float)(t / (n ? n : 1));
+        }
+        return MCE_OK;
+    }
+};
+}  // namespace
+
+mce_status model_loss_grad(const float* model, const float* feat, const float* target, uint32_t n, float* grad,
+                           float* loss, hipStream_t s)
+{
+    if (n == 0) {
+        set_error("no samples");
+        return MCE_ERR_INVALID_ARG;
+    }
+    TrainState ts;
+    mce_status st = ts.setup(n);
+    if (st != MCE_OK) return st;
+    if ((st = ts.loss_grad(model, feat, target, n, s, loss)) != MCE_OK) return st;
+    MCE_HIP_TRY(hipMemcpyAsync(grad, ts.grad.p, kModel * 4, hipMemcpyDeviceToDevice, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+mce_status model_fit_norm(float* model, const float* feat, uint32_t n, hipStream_t s)
+{
+    k_fit_norm<<<kIn, 256, 0, s>>>(feat, n, model);
+    MCE_HIP_TRY(hipGetLastError());
+    return MCE_OK;
+}
+
+mce_status model_train(float* model, const float* feat, const float* target, uint32_t n, uint32_t epochs, float lr,
+                       float b1, float b2, float eps, bool fit_norm, float* loss_hist, hipStream_t s)
+{
+    if (n == 0) {
+        set_error("no samples");
+        return MCE_ERR_INVALID_ARG;
+    }
+    TrainState ts;
+    mce_status st = ts.setup(n);
+    if (st != MCE_OK) return st;
+    if (fit_norm && (st = model_fit_norm(model, feat, n, s)) != MCE_OK) return st;
+    fill_u32(reinterpret_cast<uint32_t*>(ts.m.p), 0, kModel, s);
+    fill_u32(reinterpret_cast<uint32_t*>(ts.v.p), 0, kModel, s);
+    double c1 = 1.0, c2 = 1.0;
+    for (uint32_t e = 0; e < epochs; ++e) {
+        float l = 0;
+        if ((st = ts.loss_grad(model, feat, target, n, s, loss_hist ? &l : nullptr)) != MCE_OK) return st;
+        if (loss_hist) loss_hist[e] = l;
+        c1 *= b1;
+        c2 *= b2;
+        k_adam<<<blocks_for(kTrainable, 256), 256, 0, s>>>(model, ts.grad.as<float>(), ts.m.as<float>(),
+                                                            ts.v.as<float>(), lr, b1, b2, eps, (float)(1.0 - c1),
+                                                            (float)(1.0 - c2));
+        MCE_HIP_TRY(hipGetLastError());
+    }
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+// Work queue from a model: window roots (rank order) -> features -> scores ->
+// stable descending sort -> optional split of the costliest roots.
+mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s, uint32_t grid,
+                         LearnedQueue& q)
+{
+    mce_status rc;
+    uint32_t nroots = 0;
+    EnumConfig plain = cfg;
+    plain.flags &= ~(MCE_F_CUSTOM_ORDER | MCE_F_REVERSE_ORDER);
+    if ((rc = build_root_queue(g, plain, st, s, &nroots)) != MCE_OK) return rc;
+    q.n = nroots;
+    if (!nroots) return MCE_OK;
+    size_t nn = nroots;
+    if ((rc = q.feat.alloc(nn * 16)) != MCE_OK) return rc;
+    if ((rc = q.score.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = q.keys.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = q.sorted.alloc(nn * 4)) != MCE_OK) return rc;
+    uint32_t* roots = st.roots.as<uint32_t>();
+    if ((rc = root_features(g, roots, nroots, q.feat.as<float>(), s)) != MCE_OK) return rc;
+    if ((rc = model_predict(reinterpret_cast<const float*>(cfg.model), q.feat.as<float>(), nroots,
+                            q.score.as<float>(), s)) != MCE_OK)
+        return rc;
+    k_score_keys<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score.as<float>(), nroots, q.keys.as<uint32_t>());
+    MCE_HIP_TRY(hipGetLastError());
+    // sort queue positions 0..n-1 by key; then gather roots and scores
+    iota_u32(q.sorted.as<uint32_t>(), nn, s);
+    {
+        RadixTmp rt;
+        if ((rc = stable_sort_pairs_u32(q.keys.as<uint32_t>(), q.sorted.as<uint32_t>(), nn, 22, rt, s)) != MCE_OK)
+            return rc;
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    if ((rc = q.roots.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = q.score_sorted.alloc(nn * 4)) != MCE_OK) return rc;
+    k_gather<uint32_t><<<blocks_for(nn, 256, 8192), 256, 0, s>>>(roots, q.sorted.as<uint32_t>(), nroots,
+                                                                 q.roots.as<uint32_t>());
+    k_gather<float><<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score.as<float>(), q.sorted.as<uint32_t>(), nroots,
+                                                              q.score_sorted.as<float>());
+    MCE_HIP_TRY(hipGetLastError());
+    if (!(cfg.flags & MCE_F_SPLIT)) {
+        q.qroots = q.roots.as<uint32_t>();
+        q.qsplits = nullptr;
+        q.len = nroots;
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        return MCE_OK;
+    }
+    // split: total predicted nodes spread over `grid` workgroups, 4 tasks each
+    std::vector<float> sc(nn);
+    MCE_HIP_TRY(hipMemcpyAsync(sc.data(), q.score_sorted.p, nn * 4, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    double total = 0;
+    for (float x : sc) total += std::expm1((double)std::min(std::max(x, 0.f), 40.f));
+    float target = (float)std::max(64.0, total / (4.0 * std::max(grid, 1u)));
+    uint32_t top = cfg.split_top ? std::min(cfg.split_top, nroots) : nroots;
+    if ((rc = q.groups.alloc((nn + 1) * 4)) != MCE_OK) return rc;
+    if ((rc = q.pos.alloc((nn + 1) * 4)) != MCE_OK) return rc;
+    if ((rc = q.scan_tmp.alloc(scan_tmp_words(nn + 1) * 8 + 64)) != MCE_OK) return rc;
+    if ((rc = q.total.alloc(8)) != MCE_OK) return rc;
+    k_split_counts<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score_sorted.as<float>(), nroots, top, target,
+                                                             q.groups.as<uint32_t>());
+    MCE_HIP_TRY(hipGetLastError());
+    if ((rc = exclusive_scan_u32(q.groups.as<uint32_t>(), q.pos.as<uint32_t>(), nn, q.total.as<uint32_t>(),
+                                 q.scan_tmp.as<uint64_t>(), s)) != MCE_OK)
+        return rc;
+    uint32_t len = 0;
+    MCE_HIP_TRY(hipMemcpyAsync(&len, q.total.p, 4, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    if ((rc = q.sroots.alloc((size_t)len * 4 + 4)) != MCE_OK) return rc;
+    if ((rc = q.ssplits.alloc((size_t)len * 4 + 4)) != MCE_OK) return rc;
+    k_split_expand<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.roots.as<uint32_t>(), q.groups.as<uint32_t>(),
+                                                             q.pos.as<uint32_t>(), nroots, q.sroots.as<uint32_t>(),
+                                                             q.ssplits.as<uint32_t>());
+    MCE_HIP_TRY(hipGetLastError());
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    q.qroots = q.sroots.as<uint32_t>();
+    q.qsplits = q.ssplits.as<uint32_t>();
+    q.len = len;
+    return MCE_OK;
+}
+
+}  // namespace mce

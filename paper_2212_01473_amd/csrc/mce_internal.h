@@ -143,6 +143,8 @@ struct EnumConfig {
     uint64_t stream_ocap = 0;
     uint64_t xrow_budget_words = 1ull << 18;  // X rows per workgroup (words)
     uint32_t xrow_ratio = 8;                 // X rows when |X| <= ratio * max(|U|, 64)
+    const void* model = nullptr;             // MLP weights (device) for MCE_F_LEARNED_ORDER
+    uint32_t split_top = 0;
     // explicit work queue (learned order / split); otherwise built from the window
     const uint32_t* queue_roots = nullptr;
     const uint32_t* queue_splits = nullptr;
@@ -166,8 +168,17 @@ struct EnumOutput {
     bool timed_out = false;
 };
 
+// Work queue built from the learned model.
+struct LearnedQueue {
+    DevBuf feat, score, keys, sorted, roots, score_sorted, groups, pos, scan_tmp, total, sroots, ssplits;
+    const uint32_t* qroots = nullptr;
+    const uint32_t* qsplits = nullptr;
+    uint32_t n = 0, len = 0;
+};
+
 // One graph's enumeration state kept across calls (scratch sized to the graph).
 struct EnumState {
+    LearnedQueue lq;
     DevBuf roots, ctrl, acc, gacc, hist, scratch, ring, flags, small;
     DevBuf tmp_a, tmp_b, tmp_c, scan_tmp;
     size_t scratch_stride = 0;
@@ -182,5 +193,17 @@ mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState&
                             uint32_t* nroots_out);
 mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
                            EnumOutput& out);
+
+// Learned part (learned.hip) ------------------------------------------------------------
+mce_status root_features(const Oriented& g, const uint32_t* roots_rank, uint32_t nr, float* feat, hipStream_t s);
+mce_status ids_to_ranks(const Oriented& g, const uint32_t* ids, uint32_t n, uint32_t* out, hipStream_t s);
+mce_status model_predict(const float* model, const float* feat, uint32_t n, float* out, hipStream_t s);
+mce_status model_loss_grad(const float* model, const float* feat, const float* target, uint32_t n, float* grad,
+                           float* loss, hipStream_t s);
+mce_status model_fit_norm(float* model, const float* feat, uint32_t n, hipStream_t s);
+mce_status model_train(float* model, const float* feat, const float* target, uint32_t n, uint32_t epochs, float lr,
+                       float b1, float b2, float eps, bool fit_norm, float* loss_hist, hipStream_t s);
+mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s, uint32_t grid,
+                         LearnedQueue& q);
 
 }  // namespace mce
