@@ -155,7 +155,7 @@ typedef struct {
     uint64_t* root_nodes;       /* MCE_F_ROOT_STATS: device uint64[n] (search-tree nodes) */
     uint32_t xrow_ratio;        /* build X bitmap rows for a task when |X| <= ratio * max(|P u X_P|, 64);
                                    0 = default 8; larger X uses lookups in the original graph */
-    uint32_t reserved;
+    uint32_t xrow_min_u;        /* ... and only when |P u X_P| >= xrow_min_u; 0 = default 16 */
     uint64_t xrow_budget_words; /* X bitmap rows per workgroup, 64-bit words; 0 = default 2^18 */
 } mce_options;
 
@@ -176,7 +176,9 @@ enum {
     MCE_STAT_PROBES = 12,      /* adjacency-list entries read by X_X binary searches */
     MCE_STAT_ROOT_WORDS = 13,  /* P and X ids staged from the oriented CSR for roots */
     MCE_STAT_BUSY_NS = 14,     /* summed task time over workgroups (ns) */
-    MCE_STAT_MAX_TASK_NS = 15  /* longest single task (ns) */
+    MCE_STAT_MAX_TASK_NS = 15, /* longest single task (ns) */
+    MCE_STAT_XROW_TASKS = 16,  /* tasks that built X bitmap rows */
+    MCE_STAT_BUILD_NS = 17     /* summed bitmap-construction time over workgroups (ns) */
 };
 
 typedef struct {
@@ -193,7 +195,7 @@ typedef struct {
     uint64_t stream_ocap;
     uint64_t stream_vertices_written; /* out */
     uint64_t stream_cliques_written;  /* out */
-    uint64_t stats[16];               /* out (MCE_F_STATS): see MCE_STAT_* */
+    uint64_t stats[24];               /* out (MCE_F_STATS): see MCE_STAT_* */
 } mce_result;
 
 /*

@@ -1,0 +1,135 @@
+"""FP64 reference of the cost model and its features -- TEST INFRASTRUCTURE ONLY.
+
+Same layout as the library's model (a flat float array of 8713 entries):
+W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[64], b4,
+mean[4], std[4].  Forward: a0 = (x - mean) / std, h1 = relu(W1 a0 + b1),
+h2 = relu(W2 h1 + b2), h3 = relu(W3 h2 + b3), y = W4 . h3 + b4.  Loss: mean of
+(y - t)^2.  Backward: reverse-mode differentiation of that loss.  Adam:
+Kingma and Ba, "Adam: A Method for Stochastic Optimization", ICLR 2015
+(bias-corrected first and second moments).
+
+Features of a first-level subtree of root v (plain definitions): log(1 +
+degree), log(1 + core number), log(1 + sum of neighbour degrees), and the edge
+density of P = the later neighbours of v (edges inside P over C(|P|, 2), 0 if
+|P| < 2).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+IN, H = 4, 64
+oW1 = 0
+ob1 = oW1 + H * IN
+oW2 = ob1 + H
+ob2 = oW2 + H * H
+oW3 = ob2 + H
+ob3 = oW3 + H * H
+oW4 = ob3 + H
+ob4 = oW4 + H
+oMean = ob4 + 1
+oStd = oMean + IN
+N_PARAMS = oStd + IN
+N_TRAINABLE = oMean
+
+
+def unpack(theta):
+    t = np.asarray(theta, dtype=np.float64)
+    return dict(
+        W1=t[oW1:ob1].reshape(H, IN), b1=t[ob1:oW2], W2=t[oW2:ob2].reshape(H, H), b2=t[ob2:oW3],
+        W3=t[oW3:ob3].reshape(H, H), b3=t[ob3:oW4], W4=t[oW4:ob4], b4=t[ob4], mean=t[oMean:oStd],
+        std=t[oStd:N_PARAMS])
+
+
+def forward(theta, X):
+    """Outputs y (n,) and the intermediate values needed by backward."""
+    p = unpack(theta)
+    X = np.asarray(X, dtype=np.float64)
+    a0 = (X - p["mean"]) / p["std"]
+    z1 = a0 @ p["W1"].T + p["b1"]
+    h1 = np.maximum(z1, 0)
+    z2 = h1 @ p["W2"].T + p["b2"]
+    h2 = np.maximum(z2, 0)
+    z3 = h2 @ p["W3"].T + p["b3"]
+    h3 = np.maximum(z3, 0)
+    y = h3 @ p["W4"] + p["b4"]
+    return y, dict(a0=a0, z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, h3=h3)
+
+
+def loss(theta, X, t):
+    y, _ = forward(theta, X)
+    return float(np.mean((y - np.asarray(t, dtype=np.float64)) ** 2))
+
+
+def loss_grad(theta, X, t):
+    """(loss, gradient over all 8713 entries; zero for mean/std)."""
+    p = unpack(theta)
+    y, c = forward(theta, X)
+    n = y.shape[0]
+    r = y - np.asarray(t, dtype=np.float64)
+    dy = 2.0 * r / n
+    g = np.zeros(N_PARAMS)
+    g[oW4:ob4] = c["h3"].T @ dy
+    g[ob4] = dy.sum()
+    dz3 = np.outer(dy, p["W4"]) * (c["z3"] > 0)
+    g[oW3:ob3] = (dz3.T @ c["h2"]).ravel()
+    g[ob3:oW4] = dz3.sum(0)
+    dz2 = (dz3 @ p["W3"]) * (c["z2"] > 0)
+    g[oW2:ob2] = (dz2.T @ c["h1"]).ravel()
+    g[ob2:oW3] = dz2.sum(0)
+    dz1 = (dz2 @ p["W2"]) * (c["z1"] > 0)
+    g[oW1:ob1] = (dz1.T @ c["a0"]).ravel()
+    g[ob1:oW2] = dz1.sum(0)
+    return float(np.mean(r ** 2)), g
+
+
+class Adam:
+    def __init__(self, lr=3e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
+        self.m = np.zeros(N_TRAINABLE)
+        self.v = np.zeros(N_TRAINABLE)
+        self.t = 0
+
+    def step(self, theta, grad):
+        self.t += 1
+        g = grad[:N_TRAINABLE]
+        self.m = self.b1 * self.m + (1 - self.b1) * g
+        self.v = self.b2 * self.v + (1 - self.b2) * g * g
+        mh = self.m / (1 - self.b1 ** self.t)
+        vh = self.v / (1 - self.b2 ** self.t)
+        out = np.array(theta, dtype=np.float64)
+        out[:N_TRAINABLE] -= self.lr * mh / (np.sqrt(vh) + self.eps)
+        return out
+
+
+def fit_norm(theta, X):
+    out = np.array(theta, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    sd = X.std(0)
+    out[oMean:oStd] = X.mean(0)
+    out[oStd:N_PARAMS] = np.where(sd > 1e-6, sd, 1.0)
+    return out
+
+
+def features(g, roots, order):
+    """Features of the given roots (input ids) under the given vertex order."""
+    n = g.n
+    pos = np.empty(n, dtype=np.int64)
+    pos[np.asarray(order, dtype=np.int64)] = np.arange(n)
+    deg = g.degrees()
+    import oracle
+
+    core, _, _ = oracle.sync_peel(g)
+    out = np.zeros((len(roots), 4))
+    for i, v in enumerate(roots):
+        nb = g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]].astype(np.int64)
+        P = nb[pos[nb] > pos[v]]
+        Pset = set(P.tolist())
+        e = 0
+        for u in P:
+            for w in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                if int(w) in Pset and pos[w] > pos[u]:
+                    e += 1
+        k = len(P)
+        out[i] = [np.log1p(deg[v]), np.log1p(core[v]), np.log1p(deg[nb].sum()),
+                  e / (k * (k - 1) / 2) if k >= 2 else 0.0]
+    return out

@@ -80,6 +80,7 @@ mce_status config_from(const mce_options* opt, EnumConfig& cfg)
     if (opt->struct_size == sizeof(mce_options)) {
         if (opt->xrow_ratio) cfg.xrow_ratio = opt->xrow_ratio;
         if (opt->xrow_budget_words) cfg.xrow_budget_words = opt->xrow_budget_words;
+        if (opt->xrow_min_u) cfg.xrow_min_u = opt->xrow_min_u;
     }
     if (opt->struct_size != sizeof(mce_options))
         return fail(MCE_ERR_INVALID_ARG, "mce_options.struct_size must be sizeof(mce_options)");
@@ -110,7 +111,7 @@ mce_status finish_result(const EnumOutput& eo, size_t gi, mce_result* res, mce_s
     res->count = pg.count;
     res->hash = pg.hash;
     res->max_clique_size = pg.max_size;
-    for (int i = 0; i < 16; ++i) res->stats[i] = eo.stats[i];
+    for (int i = 0; i < 24; ++i) res->stats[i] = eo.stats[i];
     res->stream_cliques_written = eo.stream_c < res->stream_ocap ? eo.stream_c : res->stream_ocap;
     res->stream_vertices_written = eo.stream_v < res->stream_vcap ? eo.stream_v : res->stream_vcap;
     if (st != MCE_OK) return st;

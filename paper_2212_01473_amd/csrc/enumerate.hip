@@ -86,6 +86,7 @@ struct Params {
         off_meta;
     uint64_t xrow_budget;      // words of X rows per workgroup
     uint32_t xrow_ratio;       // build X rows when |X| <= ratio * max(|U|, 64)
+    uint32_t xrow_min_u;       // ... and |U| >= xrow_min_u
     uint32_t* ring;
     uint32_t ring_mask;
     uint32_t* wflags;
@@ -186,7 +187,7 @@ __device__ inline uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ul
 // Statistics counters kept in LDS (updated by lane 0) to spare scalar registers.
 enum : int {
     S_NODES = 0, S_DONATIONS, S_TASKS, S_XTESTS, S_EDGES, S_HBM, S_IDLE, S_ROOTW, S_XROW, S_BUSY, S_MAXTASK,
-    S_CTASK, S_HTASK, S_PENDING, S_COUNT
+    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_COUNT
 };
 
 // Fixed-size LDS of a workgroup (static offsets: no pointer registers).
@@ -577,10 +578,17 @@ __device__ __forceinline__ void fold_and_run(const Params& p, Wg& w, uint32_t ro
             // the small universe is the task universe itself (oidx = lane)
             xrowP = vx ? w.xrows[xj] : 0ull;
         } else {
+            // o_k ascend with k: load each X-row word once
             const uint64_t* xrow = w.xrows + (uint64_t)xj * w.W;
-            for (uint32_t k = 0; k < m; ++k) {
-                uint32_t ok = rl32(oidx, k);
-                if (vx && ((xrow[ok >> 6] >> (ok & 63)) & 1ull)) xrowP |= 1ull << k;
+            uint32_t k = 0;
+            while (k < m) {
+                uint32_t q = rl32(oidx, k) >> 6;
+                uint64_t word = vx ? xrow[q] : 0ull;
+                for (; k < m; ++k) {
+                    uint32_t ok = rl32(oidx, k);
+                    if ((ok >> 6) != q) break;
+                    xrowP |= ((word >> (ok & 63)) & 1ull) << k;
+                }
             }
         }
     }
@@ -714,11 +722,21 @@ __device__ __forceinline__ void compact_and_run(const Params& p, Wg& w, uint32_t
     const uint32_t o = valid ? S.sidx[lane] : 0u;
     const uint32_t su = valid ? w.uarr[o] : 0u;
     const uint64_t skey = valid ? w.ukey[o] : 0ull;
+    // local row of vertex k: bit k2 set iff o_k and o_k2 are adjacent; the
+    // sorted o_k2 visit each source word once, so each word is loaded once
     uint64_t row = 0;
     const uint64_t* ro = rows + (uint64_t)o * ws;
-    for (uint32_t k2 = 0; k2 < m; ++k2) {
-        uint32_t o2 = S.sidx[k2];
-        if (valid && ((ro[o2 >> 6] >> (o2 & 63)) & 1ull)) row |= 1ull << k2;
+    {
+        uint32_t k2 = 0;
+        while (k2 < m) {
+            uint32_t q = S.sidx[k2] >> 6;
+            uint64_t word = valid ? ro[q] : 0ull;
+            for (; k2 < m; ++k2) {
+                uint32_t o2 = S.sidx[k2];
+                if ((o2 >> 6) != q) break;
+                row |= ((word >> (o2 & 63)) & 1ull) << k2;
+            }
+        }
     }
     uint64_t pword = shfl64(Pc, o >> 6);
     uint64_t xword = shfl64(XPc, o >> 6);
@@ -953,10 +971,12 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
 {
     const uint32_t lane = lane_id();
     const uint32_t W = (nu + 63) >> 6;
+    const uint64_t tb0 = now_ticks();
     w.W = W;
     for (uint32_t i = lane; i < nu; i += 64) w.ukey[i] = p.vkey[w.uarr[i]];
     for (uint32_t i = lane; i < L; i += 64) w.xx[i] = i;
-    w.have_xrows = L > 0 && (uint64_t)L * W <= p.xrow_budget && L <= p.xrow_ratio * max(nu, 64u);
+    w.have_xrows = L > 0 && nu >= p.xrow_min_u && (uint64_t)L * W <= p.xrow_budget &&
+                   L <= p.xrow_ratio * max(nu, 64u);
     if (w.have_xrows) {
         for (uint64_t i = lane; i < (uint64_t)L * W; i += 64) w.xrows[i] = 0;
         wave_mem_sync();
@@ -979,6 +999,7 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
     for (uint32_t i = lane; i < nu * ws; i += 64) rows[i] = 0;
     wave_mem_sync();
     scan_lists(p, w, 0, nu, nu, rows, ws);
+    stat_add(S_BUILD, now_ticks() - tb0);
     if (nu <= 64) {
         const bool valid = lane < nu;
         uint32_t su = valid ? w.uarr[lane] : 0u;
@@ -1214,6 +1235,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         atomicAdd(&p.acc[2 + MCE_STAT_HBM_ROWS], (unsigned long long)S.stat[S_HBM]);
         atomicAdd(&p.acc[2 + MCE_STAT_IDLE_NS], (unsigned long long)S.stat[S_IDLE]);
         atomicAdd(&p.acc[2 + MCE_STAT_XROW_TASKS], (unsigned long long)S.stat[S_XROW]);
+        atomicAdd(&p.acc[2 + MCE_STAT_BUILD_TICKS], (unsigned long long)S.stat[S_BUILD]);
     }
 }
 
@@ -1454,6 +1476,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.off_meta = off_meta;
     p.xrow_budget = xrow_words;
     p.xrow_ratio = cfg.xrow_ratio;
+    p.xrow_min_u = cfg.xrow_min_u;
     p.ring = st.ring.as<uint32_t>();
     p.ring_mask = ring_cap - 1;
     p.wflags = st.flags.as<uint32_t>();
@@ -1519,7 +1542,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     }
     out.hist = out.graphs[0].hist;
     out.max_size = out.graphs[0].max_size;
-    for (int i = 0; i < 16; ++i) out.stats[i] = acc[2 + i];
+    for (int i = 0; i < 24; ++i) out.stats[i] = acc[2 + i];
     out.stats[MCE_STAT_ROOTS] = nroots;
     out.stats[MCE_STAT_WORKGROUPS] = G;
     out.stats[MCE_STAT_KERNEL_NS] = (uint64_t)(ms_kernel * 1e6);
@@ -1528,7 +1551,9 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     out.stats[MCE_STAT_BUSY_NS] = acc[2 + MCE_STAT_BUSY_NS] * 10;
     out.stats[MCE_STAT_MAX_TASK_NS] = acc[2 + MCE_STAT_MAX_TASK_NS] * 10;
     out.stats[MCE_STAT_LDS_BYTES] = lds_bytes + sizeof(LdsFixed);
+    out.stats[MCE_STAT_BUILD_NS] = acc[2 + MCE_STAT_BUILD_TICKS] * 10;
     out.xrow_tasks = acc[2 + MCE_STAT_XROW_TASKS];
+    out.build_ns = acc[2 + MCE_STAT_BUILD_TICKS] * 10;
     out.stream_c = ctrl.stream_c;
     out.stream_v = ctrl.stream_v;
     out.stream_truncated = ctrl.stream_trunc != 0;

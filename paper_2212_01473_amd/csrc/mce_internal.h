@@ -143,6 +143,7 @@ struct EnumConfig {
     uint64_t stream_ocap = 0;
     uint64_t xrow_budget_words = 1ull << 18;  // X rows per workgroup (words)
     uint32_t xrow_ratio = 8;                 // X rows when |X| <= ratio * max(|U|, 64)
+    uint32_t xrow_min_u = 16;                // ... and |U| >= xrow_min_u
     const void* model = nullptr;             // MLP weights (device) for MCE_F_LEARNED_ORDER
     uint32_t split_top = 0;
     // explicit work queue (learned order / split); otherwise built from the window
@@ -158,11 +159,11 @@ struct EnumOutput {
         uint32_t max_size = 0;
     };
     std::vector<PerGraph> graphs;
-    uint64_t xrow_tasks = 0;
+    uint64_t xrow_tasks = 0, build_ns = 0;
     uint64_t count = 0, hash = 0;
     std::vector<uint64_t> hist;  // index = size
     uint32_t max_size = 0;
-    uint64_t stats[16] = {0};
+    uint64_t stats[24] = {0};
     uint64_t stream_v = 0, stream_c = 0;
     bool stream_truncated = false;
     bool timed_out = false;
@@ -186,8 +187,8 @@ struct EnumState {
     uint32_t lds_cap = 0;
 };
 
-// internal statistic slot beyond the public 16
-constexpr int MCE_STAT_XROW_TASKS = 16;
+// raw tick counter slot of the build time
+constexpr int MCE_STAT_BUILD_TICKS = MCE_STAT_BUILD_NS;
 
 mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
                             uint32_t* nroots_out);

@@ -41,12 +41,15 @@ F_CUSTOM_ORDER = 0x80
 
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
               "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words",
-              "busy_ns", "max_task_ns"]
+              "busy_ns", "max_task_ns", "xrow_tasks", "build_ns"]
 
 FULL = 0xFFFFFFFF
 
 EXPORTED = ["mce_load_csr", "mce_load_csr_batch", "mce_graph_get_info", "mce_graph_copy_order", "mce_enumerate",
-            "mce_enumerate_batch", "mce_free", "mce_status_string", "mce_last_error", "mce_version"]
+            "mce_enumerate_batch", "mce_free", "mce_status_string", "mce_last_error", "mce_version",
+            "mce_root_features", "mce_model_predict", "mce_model_train", "mce_model_loss_grad"]
+
+MODEL_FLOATS = 8713
 
 
 class MCEError(RuntimeError):
@@ -67,7 +70,12 @@ class Options(C.Structure):
                 ("donate_max_depth", C.c_uint32), ("split_top", C.c_uint32), ("model", C.c_void_p),
                 ("stream", C.c_void_p), ("timeout_ms", C.c_uint64), ("root_order", C.c_void_p),
                 ("root_count", C.c_void_p), ("root_hash", C.c_void_p), ("root_nodes", C.c_void_p),
-                ("xrow_ratio", C.c_uint32), ("reserved", C.c_uint32), ("xrow_budget_words", C.c_uint64)]
+                ("xrow_ratio", C.c_uint32), ("xrow_min_u", C.c_uint32), ("xrow_budget_words", C.c_uint64)]
+
+
+class TrainOptions(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_uint32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("fit_norm", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Result(C.Structure):
@@ -76,7 +84,7 @@ class Result(C.Structure):
                 ("stream_vertices", C.c_void_p), ("stream_vcap", C.c_uint64),
                 ("stream_offsets", C.c_void_p), ("stream_ocap", C.c_uint64),
                 ("stream_vertices_written", C.c_uint64), ("stream_cliques_written", C.c_uint64),
-                ("stats", C.c_uint64 * 16)]
+                ("stats", C.c_uint64 * 24)]
 
 
 def load_library(path: str | None = None):
@@ -111,6 +119,16 @@ def load_library(path: str | None = None):
     lib.mce_last_error.argtypes = []
     lib.mce_version.restype = C.c_char_p
     lib.mce_version.argtypes = []
+    lib.mce_root_features.restype = C.c_int
+    lib.mce_root_features.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.mce_model_predict.restype = C.c_int
+    lib.mce_model_predict.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.mce_model_train.restype = C.c_int
+    lib.mce_model_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(TrainOptions),
+                                    C.c_void_p, C.c_void_p]
+    lib.mce_model_loss_grad.restype = C.c_int
+    lib.mce_model_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                        C.POINTER(C.c_float), C.c_void_p]
     _lib = lib
     return lib
 
@@ -244,12 +262,18 @@ def load_batch(graphs, validate: bool = True) -> Graph:
 
 
 def make_options(max_root_core: int = FULL, worker_list: bool = True, flags: int = 0, wg_per_cu: int = 0,
+                 model=None, split: bool = False, split_top: int = 0,
                  bitmap_max_p: int = 0, donate_min_p: int = 0, donate_max_depth: int = 0,
                  timeout_ms: int = 0, stream=None, root_order=None, root_stats=None, xrow_ratio: int = 0,
-                 xrow_budget_words: int = 0) -> Options:
+                 xrow_budget_words: int = 0, xrow_min_u: int = 0) -> Options:
     o = Options()
     o.xrow_ratio = xrow_ratio
+    o.xrow_min_u = xrow_min_u
     o.xrow_budget_words = xrow_budget_words
+    if model is not None:
+        o.flags |= F_LEARNED_ORDER | (F_SPLIT if split else 0)
+        o.model = C.c_void_p(model.data_ptr())
+        o.split_top = split_top
     o.struct_size = C.sizeof(Options)
     o.flags = flags | (F_WORKER_LIST if worker_list else 0) | F_STATS
     o.max_root_core = int(max_root_core) & 0xFFFFFFFF
@@ -321,3 +345,53 @@ def enumerate_batch(g: Graph, options: Options | None = None, **kw):
 
 def version() -> str:
     return load_library().mce_version().decode()
+
+
+# ---------------------------------------------------------------- learned cost model
+
+def root_features(g: Graph, root_ids):
+    """Device float32 [n, 4] features of the given roots (device int32 input ids)."""
+    import torch
+
+    n = int(root_ids.numel())
+    feat = torch.empty((max(n, 1), 4), dtype=torch.float32, device=root_ids.device)
+    _check(load_library().mce_root_features(g.handle, C.c_void_p(root_ids.data_ptr()), n,
+                                            C.c_void_p(feat.data_ptr()), _torch_stream()), "mce_root_features")
+    return feat[:n]
+
+
+def model_predict(model, feat):
+    import torch
+
+    n = int(feat.shape[0])
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
+    _check(load_library().mce_model_predict(C.c_void_p(model.data_ptr()), C.c_void_p(feat.data_ptr()), n,
+                                            C.c_void_p(out.data_ptr()), _torch_stream()), "mce_model_predict")
+    return out[:n]
+
+
+def model_loss_grad(model, feat, target):
+    import torch
+
+    grad = torch.empty(MODEL_FLOATS, dtype=torch.float32, device=feat.device)
+    loss = C.c_float()
+    _check(load_library().mce_model_loss_grad(C.c_void_p(model.data_ptr()), C.c_void_p(feat.data_ptr()),
+                                              C.c_void_p(target.data_ptr()), int(feat.shape[0]),
+                                              C.c_void_p(grad.data_ptr()), C.byref(loss), _torch_stream()),
+           "mce_model_loss_grad")
+    return grad, float(loss.value)
+
+
+def model_train(model, feat, target, epochs: int = 300, lr: float = 3e-3, beta1: float = 0.9,
+                beta2: float = 0.999, eps: float = 1e-8, fit_norm: bool = True) -> np.ndarray:
+    """Train in place (FP32 kernels, full-batch Adam); returns the loss per epoch."""
+    o = TrainOptions()
+    o.struct_size = C.sizeof(TrainOptions)
+    o.epochs = epochs
+    o.lr, o.beta1, o.beta2, o.eps = lr, beta1, beta2, eps
+    o.fit_norm = 1 if fit_norm else 0
+    hist = np.zeros(epochs, dtype=np.float32)
+    _check(load_library().mce_model_train(C.c_void_p(model.data_ptr()), C.c_void_p(feat.data_ptr()),
+                                          C.c_void_p(target.data_ptr()), int(feat.shape[0]), C.byref(o),
+                                          C.c_void_p(hist.ctypes.data), _torch_stream()), "mce_model_train")
+    return hist

@@ -40,6 +40,7 @@ int main(void) {
   printf("mce_result %zu\n", sizeof(mce_result));
   printf("mce_graph_info %zu\n", sizeof(mce_graph_info));
   F(mce_options, model); F(mce_options, stream); F(mce_options, timeout_ms); F(mce_options, root_nodes);
+  F(mce_options, xrow_min_u); F(mce_options, xrow_budget_words);
   F(mce_result, hist); F(mce_result, stream_vertices); F(mce_result, stats);
   F(mce_graph_info, n_isolated); F(mce_graph_info, n_graphs);
   return 0;
@@ -56,6 +57,8 @@ int main(void) {
     assert got["mce_options.stream"] == mce.Options.stream.offset
     assert got["mce_options.timeout_ms"] == mce.Options.timeout_ms.offset
     assert got["mce_options.root_nodes"] == mce.Options.root_nodes.offset
+    assert got["mce_options.xrow_min_u"] == mce.Options.xrow_min_u.offset
+    assert got["mce_options.xrow_budget_words"] == mce.Options.xrow_budget_words.offset
     assert got["mce_result.hist"] == mce.Result.hist.offset
     assert got["mce_result.stream_vertices"] == mce.Result.stream_vertices.offset
     assert got["mce_result.stats"] == mce.Result.stats.offset
