@@ -157,6 +157,8 @@ typedef struct {
                                    0 = default 8; larger X uses lookups in the original graph */
     uint32_t xrow_min_u;        /* ... and only when |P u X_P| >= xrow_min_u; 0 = default 16 */
     uint64_t xrow_budget_words; /* X bitmap rows per workgroup, 64-bit words; 0 = default 2^18 */
+    uint32_t donate_every;      /* offer every k-th eligible branch to the worker list; 0 = 1 */
+    uint32_t reserved2;
 } mce_options;
 
 /* indices into mce_result.stats */

@@ -81,6 +81,7 @@ mce_status config_from(const mce_options* opt, EnumConfig& cfg)
         if (opt->xrow_ratio) cfg.xrow_ratio = opt->xrow_ratio;
         if (opt->xrow_budget_words) cfg.xrow_budget_words = opt->xrow_budget_words;
         if (opt->xrow_min_u) cfg.xrow_min_u = opt->xrow_min_u;
+        if (opt->donate_every) cfg.donate_every = opt->donate_every;
     }
     if (opt->struct_size != sizeof(mce_options))
         return fail(MCE_ERR_INVALID_ARG, "mce_options.struct_size must be sizeof(mce_options)");

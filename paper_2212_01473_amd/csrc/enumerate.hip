@@ -92,7 +92,7 @@ struct Params {
     uint32_t* wflags;
     uint32_t ucap, lds_cap, wg, xcap, rcap;
     uint32_t flags;
-    uint32_t donate_min_p, donate_max_depth;
+    uint32_t donate_min_p, donate_max_depth, donate_every;
     uint32_t nwg;
     uint64_t timeout_ticks;
     unsigned long long* root_count;
@@ -441,7 +441,7 @@ __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child
     if (!(p.flags & MCE_F_WORKER_LIST)) return false;
     if (np_child < p.donate_min_p || !more_here || !anc) return false;
     if (p.donate_max_depth && depth > p.donate_max_depth) return false;
-    if ((++w.wl_tick & 3u) != 0) return false;
+    if (p.donate_every > 1 && (++w.wl_tick % p.donate_every) != 0) return false;
     uint32_t prev = w.wl_seen;
     w.wl_seen = __hip_atomic_load(&p.ctrl->waiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return uni(prev) != 0;
@@ -1488,6 +1488,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.flags = cfg.flags;
     p.donate_min_p = cfg.donate_min_p ? cfg.donate_min_p : 10u;
     p.donate_max_depth = cfg.donate_max_depth;
+    p.donate_every = cfg.donate_every ? cfg.donate_every : 1u;
     p.nwg = G;
     p.timeout_ticks = (cfg.timeout_ms ? cfg.timeout_ms : 600000ull) * 100000ull;  // 100 MHz clock
     p.root_count = reinterpret_cast<unsigned long long*>(cfg.root_count);

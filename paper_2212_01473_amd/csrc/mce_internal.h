@@ -132,6 +132,7 @@ struct EnumConfig {
     uint32_t bitmap_max_p = 0;
     uint32_t donate_min_p = 10;
     uint32_t donate_max_depth = 0;
+    uint32_t donate_every = 1;
     uint64_t timeout_ms = 600000;
     const uint32_t* root_order = nullptr;  // device, input ids
     uint64_t* root_count = nullptr;

@@ -70,7 +70,8 @@ class Options(C.Structure):
                 ("donate_max_depth", C.c_uint32), ("split_top", C.c_uint32), ("model", C.c_void_p),
                 ("stream", C.c_void_p), ("timeout_ms", C.c_uint64), ("root_order", C.c_void_p),
                 ("root_count", C.c_void_p), ("root_hash", C.c_void_p), ("root_nodes", C.c_void_p),
-                ("xrow_ratio", C.c_uint32), ("xrow_min_u", C.c_uint32), ("xrow_budget_words", C.c_uint64)]
+                ("xrow_ratio", C.c_uint32), ("xrow_min_u", C.c_uint32), ("xrow_budget_words", C.c_uint64),
+                ("donate_every", C.c_uint32), ("reserved2", C.c_uint32)]
 
 
 class TrainOptions(C.Structure):
@@ -265,8 +266,9 @@ def make_options(max_root_core: int = FULL, worker_list: bool = True, flags: int
                  model=None, split: bool = False, split_top: int = 0,
                  bitmap_max_p: int = 0, donate_min_p: int = 0, donate_max_depth: int = 0,
                  timeout_ms: int = 0, stream=None, root_order=None, root_stats=None, xrow_ratio: int = 0,
-                 xrow_budget_words: int = 0, xrow_min_u: int = 0) -> Options:
+                 xrow_budget_words: int = 0, xrow_min_u: int = 0, donate_every: int = 0) -> Options:
     o = Options()
+    o.donate_every = donate_every
     o.xrow_ratio = xrow_ratio
     o.xrow_min_u = xrow_min_u
     o.xrow_budget_words = xrow_budget_words
