@@ -133,6 +133,7 @@ mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t
 #define MCE_F_ROOT_STATS    0x20u  /* per-root counters into opt->root_* (device arrays) */
 #define MCE_F_REVERSE_ORDER 0x40u  /* process roots in reverse degeneracy order */
 #define MCE_F_CUSTOM_ORDER  0x80u  /* process roots in the order given by opt->root_order */
+#define MCE_F_TASK_LOG      0x100u /* record tasks slower than opt->task_log_min_us in opt->task_log */
 
 #define MCE_OPTIONS_VERSION 1u
 
@@ -158,7 +159,15 @@ typedef struct {
     uint32_t xrow_min_u;        /* ... and only when |P u X_P| >= xrow_min_u; 0 = default 16 */
     uint64_t xrow_budget_words; /* X bitmap rows per workgroup, 64-bit words; 0 = default 2^18 */
     uint32_t donate_every;      /* offer every k-th eligible branch to the worker list; 0 = 1 */
-    uint32_t reserved2;
+    uint32_t task_log_min_us;   /* MCE_F_TASK_LOG: record tasks that ran at least this long */
+    uint64_t* task_log;         /* MCE_F_TASK_LOG: device uint64[task_log_cap * 8], one record of 8
+                                   words per task, in completion order:
+                                   [0] root input id, [1] |R| << 32 | universe |P u X_P|,
+                                   [2] split group c << 48 | C << 32 | initial |X_X|,
+                                   [3] search-tree nodes, [4] task time (ns), [5] bitmap build
+                                   time (ns), [6] branches donated by the task,
+                                   [7] workgroup << 48 | start time (ns, device clock) */
+    uint64_t task_log_cap;      /* records that fit; MCE_STAT_TASK_LOG counts all qualifying tasks */
 } mce_options;
 
 /* indices into mce_result.stats */
@@ -180,7 +189,10 @@ enum {
     MCE_STAT_BUSY_NS = 14,     /* summed task time over workgroups (ns) */
     MCE_STAT_MAX_TASK_NS = 15, /* longest single task (ns) */
     MCE_STAT_XROW_TASKS = 16,  /* tasks that built X bitmap rows */
-    MCE_STAT_BUILD_NS = 17     /* summed bitmap-construction time over workgroups (ns) */
+    MCE_STAT_BUILD_NS = 17,    /* summed bitmap-construction time over workgroups (ns) */
+    MCE_STAT_TASK_LOG = 18,    /* tasks that qualified for the task log (may exceed its capacity) */
+    MCE_STAT_DONATE_NS = 19,   /* summed time spent offering branches to the worker list (ns) */
+    MCE_STAT_POP_FAILS = 20    /* offers that found no idle workgroup */
 };
 
 typedef struct {

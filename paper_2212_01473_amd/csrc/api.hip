@@ -77,14 +77,19 @@ void fill_info(const Oriented& o, uint32_t idx, mce_graph_info* out)
 mce_status config_from(const mce_options* opt, EnumConfig& cfg)
 {
     if (!opt) return MCE_OK;
-    if (opt->struct_size == sizeof(mce_options)) {
-        if (opt->xrow_ratio) cfg.xrow_ratio = opt->xrow_ratio;
-        if (opt->xrow_budget_words) cfg.xrow_budget_words = opt->xrow_budget_words;
-        if (opt->xrow_min_u) cfg.xrow_min_u = opt->xrow_min_u;
-        if (opt->donate_every) cfg.donate_every = opt->donate_every;
-    }
     if (opt->struct_size != sizeof(mce_options))
         return fail(MCE_ERR_INVALID_ARG, "mce_options.struct_size must be sizeof(mce_options)");
+    if (opt->xrow_ratio) cfg.xrow_ratio = opt->xrow_ratio;
+    if (opt->xrow_budget_words) cfg.xrow_budget_words = opt->xrow_budget_words;
+    if (opt->xrow_min_u) cfg.xrow_min_u = opt->xrow_min_u;
+    if (opt->donate_every) cfg.donate_every = opt->donate_every;
+    if (opt->flags & MCE_F_TASK_LOG) {
+        if (!opt->task_log && opt->task_log_cap)
+            return fail(MCE_ERR_INVALID_ARG, "MCE_F_TASK_LOG with task_log_cap > 0 needs task_log");
+        cfg.task_log = opt->task_log;
+        cfg.task_log_cap = opt->task_log ? opt->task_log_cap : 0;
+        cfg.task_log_min_us = opt->task_log_min_us;
+    }
     cfg.flags = opt->flags;
     cfg.max_root_core = opt->max_root_core;
     cfg.wg_per_cu = opt->wg_per_cu;

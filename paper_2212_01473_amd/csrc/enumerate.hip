@@ -54,7 +54,8 @@ struct Ctrl {
     unsigned int err;              // 1 = timeout
     unsigned int stream_trunc;
     unsigned int waiting;          // workgroups currently in the worker list
-    unsigned int pad[4];
+    unsigned int tlog_n;           // tasks that qualified for the task log
+    unsigned int pad[3];
 };
 
 struct MboxHdr {
@@ -82,15 +83,16 @@ struct Params {
     uint32_t hist_len;
     uint8_t* scratch;
     uint64_t stride;
-    uint64_t off_P, off_XP, off_R, off_xr, off_xx, off_flag, off_hpos, off_spos, off_rows, off_xrows, off_stack,
+    uint64_t off_P, off_XP, off_R, off_xr, off_xx, off_flag, off_hpos, off_spos, off_rows, off_xrows, off_xcols, off_stack,
         off_meta;
     uint64_t xrow_budget;      // words of X rows per workgroup
+    uint64_t xcol_budget;      // words of X columns per workgroup
     uint32_t xrow_ratio;       // build X rows when |X| <= ratio * max(|U|, 64)
     uint32_t xrow_min_u;       // ... and |U| >= xrow_min_u
     uint32_t* ring;
     uint32_t ring_mask;
     uint32_t* wflags;
-    uint32_t ucap, lds_cap, wg, xcap, rcap;
+    uint32_t ucap, lds_cap, wg, wgx, xcap, rcap;  // wg / wgx: words per stack level of P and X_X
     uint32_t flags;
     uint32_t donate_min_p, donate_max_depth, donate_every;
     uint32_t nwg;
@@ -102,6 +104,9 @@ struct Params {
     uint64_t s_vcap;
     unsigned long long* s_offs;
     uint64_t s_ocap;
+    unsigned long long* tlog;  // task log records (8 words each), or null
+    uint64_t tlog_cap;
+    uint64_t tlog_min_ticks;
 };
 
 // ---------------------------------------------------------------- wave helpers
@@ -187,7 +192,7 @@ __device__ inline uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ul
 // Statistics counters kept in LDS (updated by lane 0) to spare scalar registers.
 enum : int {
     S_NODES = 0, S_DONATIONS, S_TASKS, S_XTESTS, S_EDGES, S_HBM, S_IDLE, S_ROOTW, S_XROW, S_BUSY, S_MAXTASK,
-    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_COUNT
+    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_DONATE, S_POPFAIL, S_COUNT
 };
 
 // Fixed-size LDS of a workgroup (static offsets: no pointer registers).
@@ -195,10 +200,10 @@ struct LdsFixed {
     uint64_t pw[64], xw[64];
     uint64_t lP[kDepth], lXP[kDepth], lB[kDepth], lK[kDepth];  // list-mode stack
     uint64_t fP[kDepth], fXP[kDepth], fXX[kDepth], fB[kDepth], fK[kDepth];  // folded-mode stack
-    uint64_t stat[S_COUNT + 2];
+    uint64_t stat[S_COUNT + 4];  // + snapshots at task start: nodes, donations, build time
     uint32_t lL[kDepth], lA[kDepth], fA[kDepth];
     uint32_t hist[kHistLds];
-    uint32_t sidx[64], soff[64], sbeg[64];
+    uint32_t sidx[64], soff[64], sbeg[64], sxj[64];
 };
 __shared__ LdsFixed S;
 
@@ -220,6 +225,7 @@ struct Wg {
     uint32_t* spos;
     uint64_t* grows;
     uint64_t* xrows;
+    uint64_t* xcols;
     uint64_t* gstack;
     uint64_t* gmeta;
     // LDS sized per launch
@@ -228,12 +234,14 @@ struct Wg {
     uint64_t* lrows;
     // current task
     uint32_t W;         // words of the task's universe
+    uint32_t Wx;        // words of the task's X list bitmap (X columns built), else 0
     bool have_xrows;
     // accumulators (wave-uniform)
     uint64_t count, hash;   // since the last per-graph flush
     uint32_t cur_gid;
     uint32_t hmax;
     uint64_t task_t0;
+    uint64_t don_t0;  // start of the current donation attempt
     uint32_t probes;  // per lane
     uint32_t wl_tick, wl_seen, poll;
     uint64_t deadline;
@@ -323,7 +331,7 @@ __device__ __forceinline__ uint32_t xx_partition(const Params& p, Wg& w, uint32_
 }
 
 // ---------------------------------------------------------------- results
-__device__ void flush_graph(const Params& p, Wg& w)
+__device__ __forceinline__ void flush_graph(const Params& p, Wg& w)
 {
     const uint32_t lane = lane_id();
     if (lane == 0 && (w.count | w.hash)) {
@@ -407,6 +415,7 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
 __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
 {
     uint32_t r = kEmptySlot;
+    w.don_t0 = uni64(now_ticks());
     if (lane_id() == 0) {
         unsigned long long h = __hip_atomic_load(&p.ctrl->ring_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long t = __hip_atomic_load(&p.ctrl->ring_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -428,7 +437,12 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
             r = v;
         }
     }
-    return uni(r);
+    r = uni(r);
+    if (r == kEmptySlot) {
+        stat_add(S_POPFAIL, 1);
+        stat_add(S_DONATE, uni64(now_ticks()) - w.don_t0);
+    }
+    return r;
 }
 
 // Should this branch be offered to an idle workgroup (Section III-C)?  Only
@@ -470,6 +484,7 @@ __device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) __hip_atomic_store(&p.wflags[r], kFlagTask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     stat_add(S_DONATIONS, 1);
+    stat_add(S_DONATE, uni64(now_ticks()) - w.don_t0);
 }
 
 // ---------------------------------------------------------------- folded executor
@@ -565,12 +580,11 @@ enter : {
 // Fold X_X (xx[0, L), L <= 64) into registers and run the folded executor.
 // oidx: lane k's index in the task universe (X rows are over that universe).
 __device__ __forceinline__ void fold_and_run(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
-                             uint32_t oidx, uint64_t rowP, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks,
-                             uint32_t rs, bool anc)
+                             uint32_t oidx, uint64_t rowP, uint64_t P, uint64_t XP, uint32_t L, uint32_t xj,
+                             uint64_t ks, uint32_t rs, bool anc)
 {
     const uint32_t lane = lane_id();
     const bool vx = lane < L;
-    const uint32_t xj = vx ? w.xx[lane] : 0u;
     const uint32_t xrank = vx ? w.xr[xj] : 0u;
     uint64_t xrowP = 0;
     if (L) {
@@ -675,7 +689,8 @@ enter : {
         if (lane == 0) w.R[rs] = vb;
         if (Lc <= 64 && (can_fold || Lc == 0)) {
             wave_mem_sync();
-            fold_and_run(p, w, root, m, su, skey, oidx, rowP, Pc, XPc, Lc, ksc, rs + 1, anc || (B != 0));
+            const uint32_t xj = lane < Lc ? w.xx[lane] : 0u;
+            fold_and_run(p, w, root, m, su, skey, oidx, rowP, Pc, XPc, Lc, xj, ksc, rs + 1, anc || (B != 0));
             if (w.abort) return;
             continue;
         }
@@ -699,10 +714,32 @@ enter : {
 }
 
 // ---------------------------------------------------------------- mid executor
+// Members of a bitmap X_X (lane-per-word, w.Wx words) as indices into xr, in
+// ascending order.  to_list: written to w.xx[0, count); otherwise (count <= 64)
+// lane j returns the j-th member.
+__device__ __forceinline__ uint32_t xx_members(Wg& w, uint64_t XX, bool to_list)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t Wx = w.Wx;
+    uint32_t base = 0;
+    for (uint32_t t = 0; t < Wx; ++t) {
+        uint64_t word = rl64(XX, t);
+        if ((word >> lane) & 1ull) {
+            uint32_t pos = base + prefix_popc(word);
+            if (to_list) w.xx[pos] = t * 64 + lane;
+            else S.sxj[pos] = t * 64 + lane;
+        }
+        base += (uint32_t)__popcll(word);
+    }
+    wave_mem_sync();
+    return (!to_list && lane < base) ? S.sxj[lane] : 0u;
+}
+
 // Re-index a node whose P u X_P has at most 64 vertices into registers and run
 // it with the folded or the list executor.
 __device__ __forceinline__ void compact_and_run(const Params& p, Wg& w, uint32_t root, const uint64_t* rows, uint32_t ws,
-                                uint64_t Pc, uint64_t XPc, uint32_t L, uint64_t ks, uint32_t rs, bool anc)
+                                uint64_t Pc, uint64_t XPc, uint32_t L, uint64_t XXc, uint64_t ks, uint32_t rs,
+                                bool anc)
 {
     const uint32_t lane = lane_id();
     const uint32_t W = w.W;
@@ -743,21 +780,37 @@ __device__ __forceinline__ void compact_and_run(const Params& p, Wg& w, uint32_t
     uint64_t Ps = __ballot(valid && ((pword >> (o & 63)) & 1ull));
     uint64_t XPs = __ballot(valid && ((xword >> (o & 63)) & 1ull));
     wave_mem_sync();
-    if (L <= 64 && (w.have_xrows || L == 0))
-        fold_and_run(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc);
-    else
+    if (w.have_xrows) {
+        // X_X is a bitmap over the task's X list: fold its members, or list them
+        const uint32_t xj = xx_members(w, XXc, L > 64);
+        if (L <= 64) fold_and_run(p, w, root, m, su, skey, o, row, Ps, XPs, L, xj, ks, rs, anc);
+        else run_list(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc, 0, 1);
+    } else if (L == 0) {
+        fold_and_run(p, w, root, m, su, skey, o, row, Ps, XPs, 0, 0, ks, rs, anc);
+    } else {
         run_list(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc, 0, 1);
+    }
 }
 
+// Mid executor: universe of up to 4096 vertices, one 64-bit word per lane
+// (W words).  The pivot maximises |P n N(u)| over u in P u X_P (Section
+// III-E).  X_X is either a bitmap over the task's X list (lanes hold its Wx
+// words; a child's X_X is one AND with the X column of the branch vertex) or,
+// when the X columns were not built, the partitioned index list of Section
+// III-E.  The DFS stack lives in this workgroup's HBM scratch.
 __device__ __forceinline__ void run_mid(const Params& p, Wg& w, uint32_t root, uint32_t nu, const uint64_t* rows, uint32_t ws,
                         uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs, uint32_t c, uint32_t C)
 {
     const uint32_t lane = lane_id();
     const uint32_t W = w.W;
+    const bool xb = w.have_xrows;
+    const uint32_t Wx = xb ? w.Wx : 0u;
     const uint32_t gws = p.wg;
+    const uint32_t lvl_words = 3 * gws + p.wgx;
     const uint32_t* U = w.uarr;
     uint32_t depth = 0, t0 = 0;
     uint64_t B = 0;
+    uint64_t XX = lane < Wx ? low_mask(L - lane * 64) : 0ull;
     bool anc = false;
 enter : {
     stat_add(S_NODES, 1);
@@ -783,12 +836,13 @@ enter : {
         if (bm == 0) {
             if (depth == 0) return;
             --depth;
-            const uint64_t* lvl = w.gstack + (uint64_t)depth * 3 * gws;
+            const uint64_t* lvl = w.gstack + (uint64_t)depth * lvl_words;
             if (lane < W) {
                 P = lvl[lane];
                 XP = lvl[gws + lane];
                 B = lvl[2 * gws + lane];
             }
+            if (lane < Wx) XX = lvl[3 * gws + lane];
             uint64_t meta = w.gmeta[2 * depth];
             ks = w.gmeta[2 * depth + 1];
             L = (uint32_t)meta;
@@ -802,8 +856,10 @@ enter : {
         uint32_t bit = (uint32_t)__builtin_ctzll(word);
         uint32_t bb = w0 * 64 + bit;
         uint64_t rowb = lane < W ? rows[(uint64_t)bb * ws + lane] : 0ull;
+        uint64_t colb = lane < Wx ? w.xcols[(uint64_t)bb * Wx + lane] : 0ull;
         uint64_t Pc = P & rowb;
         uint64_t XPc = XP & rowb;
+        uint64_t XXc = XX & colb;
         if (lane == w0) {
             B &= ~(1ull << bit);
             P &= ~(1ull << bit);
@@ -819,7 +875,8 @@ enter : {
         bool more_here = __ballot(B != 0) != 0;
         if (npc == 0) {
             stat_add(S_NODES, 1);
-            if (nxc == 0 && !xx_any(p, w, L, bb, vb)) {
+            bool xhit = xb ? __ballot(XXc != 0) != 0 : (nxc == 0 && xx_any(p, w, L, bb, vb));
+            if (nxc == 0 && !xhit) {
                 if (p.flags & MCE_F_STREAM) {
                     if (lane == 0) w.R[rs] = vb;
                     wave_mem_sync();
@@ -828,7 +885,13 @@ enter : {
             }
             continue;
         }
-        uint32_t Lc = xx_partition(p, w, L, bb, vb);
+        uint32_t Lc;
+        if (xb) {
+            Lc = wave_sum((uint32_t)__popcll(XXc));
+            stat_add(S_XTESTS, Wx);
+        } else {
+            Lc = xx_partition(p, w, L, bb, vb);
+        }
         if (donation_wanted(p, w, npc, more_here, anc || depth > 0, depth)) {
             uint32_t r = wl_try_pop(p, w);
             if (r != kEmptySlot) {
@@ -842,7 +905,16 @@ enter : {
                     bp += (uint32_t)__popcll(pw_);
                     bx += (uint32_t)__popcll(xw_);
                 }
-                for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                if (xb) {
+                    uint32_t bq = 0;
+                    for (uint32_t t = 0; t < Wx; ++t) {
+                        uint64_t xxw = rl64(XXc, t);
+                        if ((xxw >> lane) & 1ull) d.xr[bq + prefix_popc(xxw)] = w.xr[t * 64 + lane];
+                        bq += (uint32_t)__popcll(xxw);
+                    }
+                } else {
+                    for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                }
                 publish_task(p, w, r, root, rs, vb, ksc, npc, nxc, Lc);
                 continue;
             }
@@ -850,16 +922,17 @@ enter : {
         if (lane == 0) w.R[rs] = vb;
         if (npc + nxc <= 64) {
             wave_mem_sync();
-            compact_and_run(p, w, root, rows, ws, Pc, XPc, Lc, ksc, rs + 1, anc || more_here || depth > 0);
+            compact_and_run(p, w, root, rows, ws, Pc, XPc, Lc, XXc, ksc, rs + 1, anc || more_here || depth > 0);
             if (w.abort) return;
             continue;
         }
-        uint64_t* lvl = w.gstack + (uint64_t)depth * 3 * gws;
+        uint64_t* lvl = w.gstack + (uint64_t)depth * lvl_words;
         if (lane < W) {
             lvl[lane] = P;
             lvl[gws + lane] = XP;
             lvl[2 * gws + lane] = B;
         }
+        if (lane < Wx) lvl[3 * gws + lane] = XX;
         // every lane stores the same meta words, so each later reads its own store
         w.gmeta[2 * depth] = ((uint64_t)(anc ? 1u : 0u) << 32) | L;
         w.gmeta[2 * depth + 1] = ks;
@@ -868,6 +941,7 @@ enter : {
         ++rs;
         P = Pc;
         XP = XPc;
+        XX = XXc;
         L = Lc;
         ks = ksc;
         goto enter;
@@ -877,10 +951,12 @@ enter : {
 // ---------------------------------------------------------------- bitmap construction
 // For every list entry i < cnt (mode 0: U[i]; mode 1: xr[i]) scan its later
 // neighbours and, for each one found in U[0, nu) at position j, set bit j of
-// row i (mode 0 also sets bit i of row j: the P x P rows are symmetric).  All
+// row i (mode 0 also sets bit i of row j: the P x P rows are symmetric; mode 1
+// with cols also sets bit i of column j).  All
 // 64 lanes take consecutive entries of the concatenated lists, so loads are
 // independent and lanes stay busy across short lists.
-__device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uint32_t cnt, uint32_t nu, uint64_t* rows, uint32_t ws)
+__device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uint32_t cnt, uint32_t nu, uint64_t* rows,
+                                           uint32_t ws, uint64_t* cols, uint32_t cws)
 {
     const uint32_t lane = lane_id();
     const uint32_t* U = w.uarr;
@@ -922,6 +998,8 @@ __device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uin
                         atomicOr((unsigned long long*)&rows[(uint64_t)r * ws + (a >> 6)], 1ull << (a & 63));
                         if (mode == 0)
                             atomicOr((unsigned long long*)&rows[(uint64_t)a * ws + (r >> 6)], 1ull << (r & 63));
+                        else if (cols)
+                            atomicOr((unsigned long long*)&cols[(uint64_t)a * cws + (r >> 6)], 1ull << (r & 63));
                     }
                 }
             }
@@ -941,12 +1019,15 @@ __device__ inline void begin_task(const Params& p, Wg& w, uint32_t root)
     if (__lane_id() == 0) {
         S.stat[S_CTASK] = 0;
         S.stat[S_HTASK] = 0;
-        S.stat[S_NODES + S_COUNT] = S.stat[S_NODES];  // nodes at task start
+        S.stat[S_COUNT] = S.stat[S_NODES];  // snapshots at task start
+        S.stat[S_COUNT + 1] = S.stat[S_DONATIONS];
+        S.stat[S_COUNT + 2] = S.stat[S_BUILD];
     }
     w.task_t0 = uni64(now_ticks());
 }
 
-__device__ void finish_task(const Params& p, Wg& w, uint32_t root)
+__device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint32_t rs, uint32_t c,
+                            uint32_t C)
 {
     stat_add(S_TASKS, 1);
     // keep the per-size LDS counters (32-bit) far from overflow
@@ -959,7 +1040,21 @@ __device__ void finish_task(const Params& p, Wg& w, uint32_t root)
             uint32_t id = p.perm[root];
             atomicAdd(&p.root_count[id], (unsigned long long)S.stat[S_CTASK]);
             atomicAdd(&p.root_hash[id], (unsigned long long)S.stat[S_HTASK]);
-            atomicAdd(&p.root_nodes[id], (unsigned long long)(S.stat[S_NODES] - S.stat[S_NODES + S_COUNT]));
+            atomicAdd(&p.root_nodes[id], (unsigned long long)(S.stat[S_NODES] - S.stat[S_COUNT]));
+        }
+        if ((p.flags & MCE_F_TASK_LOG) && dt >= p.tlog_min_ticks) {
+            uint32_t slot = atomicAdd(&p.ctrl->tlog_n, 1u);
+            if (slot < p.tlog_cap) {
+                unsigned long long* e = p.tlog + (uint64_t)slot * 8;
+                e[0] = p.perm[root];
+                e[1] = ((unsigned long long)rs << 32) | nu;
+                e[2] = ((unsigned long long)c << 48) | ((unsigned long long)C << 32) | L;
+                e[3] = S.stat[S_NODES] - S.stat[S_COUNT];
+                e[4] = dt * 10;  // 100 MHz clock -> ns
+                e[5] = (S.stat[S_BUILD] - S.stat[S_COUNT + 2]) * 10;
+                e[6] = S.stat[S_DONATIONS] - S.stat[S_COUNT + 1];
+                e[7] = ((unsigned long long)w.me << 48) | ((w.task_t0 * 10) & 0xFFFFFFFFFFFFull);
+            }
         }
     }
 }
@@ -975,12 +1070,19 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
     w.W = W;
     for (uint32_t i = lane; i < nu; i += 64) w.ukey[i] = p.vkey[w.uarr[i]];
     for (uint32_t i = lane; i < L; i += 64) w.xx[i] = i;
+    const uint32_t Wx = (L + 63) >> 6;
     w.have_xrows = L > 0 && nu >= p.xrow_min_u && (uint64_t)L * W <= p.xrow_budget &&
-                   L <= p.xrow_ratio * max(nu, 64u);
+                   (uint64_t)nu * Wx <= p.xcol_budget && Wx <= p.wgx && L <= p.xrow_ratio * max(nu, 64u);
+    w.Wx = w.have_xrows ? Wx : 0u;
     if (w.have_xrows) {
+        // X rows (per X entry, over U) for the register executors; X columns
+        // (per universe vertex, over X) for the mid executor
+        const bool cols = nu > 64;
         for (uint64_t i = lane; i < (uint64_t)L * W; i += 64) w.xrows[i] = 0;
+        if (cols)
+            for (uint64_t i = lane; i < (uint64_t)nu * Wx; i += 64) w.xcols[i] = 0;
         wave_mem_sync();
-        scan_lists(p, w, 1, L, nu, w.xrows, W);
+        scan_lists(p, w, 1, L, nu, w.xrows, W, cols ? w.xcols : nullptr, Wx);
         stat_add(S_XROW, 1);
     }
     uint64_t* rows;
@@ -998,7 +1100,7 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
     }
     for (uint32_t i = lane; i < nu * ws; i += 64) rows[i] = 0;
     wave_mem_sync();
-    scan_lists(p, w, 0, nu, nu, rows, ws);
+    scan_lists(p, w, 0, nu, nu, rows, ws, nullptr, 0);
     stat_add(S_BUILD, now_ticks() - tb0);
     if (nu <= 64) {
         const bool valid = lane < nu;
@@ -1008,7 +1110,7 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
         uint64_t P = S.pw[0], XP = S.xw[0];
         wave_mem_sync();
         if (C == 1 && L <= 64 && (w.have_xrows || L == 0))
-            fold_and_run(p, w, root, nu, su, skey, lane, rowP, P, XP, L, ks, rs, false);
+            fold_and_run(p, w, root, nu, su, skey, lane, rowP, P, XP, L, lane, ks, rs, false);
         else
             run_list(p, w, root, nu, su, skey, lane, rowP, P, XP, L, ks, rs, false, c, C);
     } else {
@@ -1186,6 +1288,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.spos = reinterpret_cast<uint32_t*>(base + p.off_spos);
     w.grows = reinterpret_cast<uint64_t*>(base + p.off_rows);
     w.xrows = reinterpret_cast<uint64_t*>(base + p.off_xrows);
+    w.xcols = reinterpret_cast<uint64_t*>(base + p.off_xcols);
     w.gstack = reinterpret_cast<uint64_t*>(base + p.off_stack);
     w.gmeta = reinterpret_cast<uint64_t*>(base + p.off_meta);
     unsigned char* l = lds;
@@ -1195,17 +1298,19 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     l += (size_t)((p.ucap + 3) & ~3u) * 4;
     w.lrows = reinterpret_cast<uint64_t*>(l);
     for (uint32_t k = lane; k < (uint32_t)kHistLds; k += 64) S.hist[k] = 0;
-    for (uint32_t k = lane; k < (uint32_t)S_COUNT + 2; k += 64) S.stat[k] = 0;
+    for (uint32_t k = lane; k < (uint32_t)S_COUNT + 4; k += 64) S.stat[k] = 0;
     wave_mem_sync();
     w.count = w.hash = 0;
     w.cur_gid = 0;
     w.hmax = 0;
     w.task_t0 = 0;
+    w.don_t0 = 0;
     w.probes = 0;
     w.wl_tick = w.wl_seen = w.poll = 0;
     w.me = me;
     w.abort = false;
     w.W = 1;
+    w.Wx = 0;
     w.have_xrows = false;
     w.deadline = uni64(now_ticks()) + p.timeout_ticks;
 
@@ -1218,7 +1323,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     while (!w.abort && next_task(p, w, phase1, t)) {
         begin_task(p, w, t.root);
         run_task(p, w, t.root, t.nu, t.L, t.ks, t.rs, t.c, t.C);
-        finish_task(p, w, t.root);
+        finish_task(p, w, t.root, t.nu, t.L, t.rs, t.c, t.C);
     }
     flush_graph(p, w);
     uint32_t pl = wave_sum(w.probes);
@@ -1236,6 +1341,8 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         atomicAdd(&p.acc[2 + MCE_STAT_IDLE_NS], (unsigned long long)S.stat[S_IDLE]);
         atomicAdd(&p.acc[2 + MCE_STAT_XROW_TASKS], (unsigned long long)S.stat[S_XROW]);
         atomicAdd(&p.acc[2 + MCE_STAT_BUILD_TICKS], (unsigned long long)S.stat[S_BUILD]);
+        atomicAdd(&p.acc[2 + MCE_STAT_DONATE_NS], (unsigned long long)S.stat[S_DONATE]);
+        atomicAdd(&p.acc[2 + MCE_STAT_POP_FAILS], (unsigned long long)S.stat[S_POPFAIL]);
     }
 }
 
@@ -1261,6 +1368,24 @@ __global__ void k_root_compact(const uint32_t* __restrict__ cand, const uint32_t
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         if (flag[i]) roots[pos[i]] = cand[i];
+}
+
+// A custom root order must be a permutation of 0..n-1: count each id, flag
+// ids out of range (err bit 0) and ids seen other than once (err bit 1).
+__global__ void k_perm_count(const uint32_t* __restrict__ ids, uint32_t n, uint32_t* __restrict__ seen,
+                             uint32_t* __restrict__ err)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t v = ids[i];
+        if (v >= n) atomicOr(err, 1u);
+        else atomicAdd(&seen[v], 1u);
+    }
+}
+
+__global__ void k_perm_check(const uint32_t* __restrict__ seen, uint32_t n, uint32_t* __restrict__ err)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (seen[i] != 1u) atomicOr(err, 2u);
 }
 
 // Isolated vertices are maximal cliques of size 1 (Algorithm 3 with P = X = {}).
@@ -1310,6 +1435,22 @@ mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState&
         return MCE_ERR_INVALID_ARG;
     }
     uint32_t nroots = 0;
+    if (n && mode == 2) {
+        uint32_t* seen = st.tmp_b.as<uint32_t>();
+        uint32_t* derr = st.small.as<uint32_t>();
+        fill_u32(seen, 0, n, s);
+        fill_u32(derr, 0, 1, s);
+        k_perm_count<<<blocks_for(n, 256, 8192), 256, 0, s>>>(cfg.root_order, n, seen, derr);
+        k_perm_check<<<blocks_for(n, 256, 8192), 256, 0, s>>>(seen, n, derr);
+        MCE_HIP_TRY(hipGetLastError());
+        uint32_t herr = 0;
+        MCE_HIP_TRY(hipMemcpyAsync(&herr, derr, 4, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        if (herr) {
+            set_error((herr & 1u) ? "root_order holds an id >= n" : "root_order is not a permutation");
+            return MCE_ERR_INVALID_ARG;
+        }
+    }
     if (n) {
         uint32_t* dtotal = st.small.as<uint32_t>();
         k_root_flags<<<blocks_for(n, 256, 8192), 256, 0, s>>>(g.op.as<uint32_t>(), g.core_r.as<uint32_t>(), n,
@@ -1345,6 +1486,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint32_t xcap = std::max(g.max_in, 1u);
     const uint32_t rcap = g.degeneracy + 3;
     const uint32_t wg_words = (ucap + 63) / 64;
+    const uint32_t wgx_words = std::min<uint32_t>(64u, (xcap + 63) / 64);  // X_X bitmaps: |X| <= 4096
     const uint32_t ws_g = wg_words | 1u;
 
     // LDS budget for bitmap rows (universes up to 64 always fit)
@@ -1374,6 +1516,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
 
     // per-workgroup scratch layout
     const uint64_t xrow_words = std::min<uint64_t>(cfg.xrow_budget_words, (uint64_t)xcap * wg_words);
+    const uint64_t xcol_words = std::min<uint64_t>(cfg.xrow_budget_words, (uint64_t)ucap * wgx_words);
     uint64_t off = align_up(sizeof(MboxHdr), 256);
     const uint64_t off_P = off; off = align_up(off + (uint64_t)ucap * 4, 256);
     const uint64_t off_XP = off; off = align_up(off + (uint64_t)ucap * 4, 256);
@@ -1385,7 +1528,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint64_t off_spos = off; off = align_up(off + ((uint64_t)xcap / 2 + 2) * 4, 256);
     const uint64_t off_rows = off; off = align_up(off + (uint64_t)ucap * ws_g * 8, 256);
     const uint64_t off_xrows = off; off = align_up(off + xrow_words * 8 + 8, 256);
-    const uint64_t off_stack = off; off = align_up(off + (uint64_t)(ucap + 2) * 3 * wg_words * 8, 256);
+    const uint64_t off_xcols = off; off = align_up(off + xcol_words * 8 + 8, 256);
+    const uint64_t off_stack = off; off = align_up(off + (uint64_t)(ucap + 2) * (3 * wg_words + wgx_words) * 8, 256);
     const uint64_t off_meta = off; off = align_up(off + (uint64_t)(ucap + 2) * 16, 256);
     const uint64_t stride = off;
     const uint64_t budget = 32ull << 30;
@@ -1472,9 +1616,11 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.off_spos = off_spos;
     p.off_rows = off_rows;
     p.off_xrows = off_xrows;
+    p.off_xcols = off_xcols;
     p.off_stack = off_stack;
     p.off_meta = off_meta;
     p.xrow_budget = xrow_words;
+    p.xcol_budget = xcol_words;
     p.xrow_ratio = cfg.xrow_ratio;
     p.xrow_min_u = cfg.xrow_min_u;
     p.ring = st.ring.as<uint32_t>();
@@ -1483,6 +1629,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.ucap = ucap;
     p.lds_cap = lds_cap;
     p.wg = wg_words;
+    p.wgx = wgx_words;
     p.xcap = xcap;
     p.rcap = rcap;
     p.flags = cfg.flags;
@@ -1491,6 +1638,9 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.donate_every = cfg.donate_every ? cfg.donate_every : 1u;
     p.nwg = G;
     p.timeout_ticks = (cfg.timeout_ms ? cfg.timeout_ms : 600000ull) * 100000ull;  // 100 MHz clock
+    p.tlog = (cfg.flags & MCE_F_TASK_LOG) ? reinterpret_cast<unsigned long long*>(cfg.task_log) : nullptr;
+    p.tlog_cap = p.tlog ? cfg.task_log_cap : 0;
+    p.tlog_min_ticks = (uint64_t)cfg.task_log_min_us * 100ull;
     p.root_count = reinterpret_cast<unsigned long long*>(cfg.root_count);
     p.root_hash = reinterpret_cast<unsigned long long*>(cfg.root_hash);
     p.root_nodes = reinterpret_cast<unsigned long long*>(cfg.root_nodes);
@@ -1553,6 +1703,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     out.stats[MCE_STAT_MAX_TASK_NS] = acc[2 + MCE_STAT_MAX_TASK_NS] * 10;
     out.stats[MCE_STAT_LDS_BYTES] = lds_bytes + sizeof(LdsFixed);
     out.stats[MCE_STAT_BUILD_NS] = acc[2 + MCE_STAT_BUILD_TICKS] * 10;
+    out.stats[MCE_STAT_TASK_LOG] = ctrl.tlog_n;
+    out.stats[MCE_STAT_DONATE_NS] = acc[2 + MCE_STAT_DONATE_NS] * 10;
     out.xrow_tasks = acc[2 + MCE_STAT_XROW_TASKS];
     out.build_ns = acc[2 + MCE_STAT_BUILD_TICKS] * 10;
     out.stream_c = ctrl.stream_c;

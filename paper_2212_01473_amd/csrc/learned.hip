@@ -102,11 +102,20 @@ __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __
     }
 }
 
-__global__ void k_ids_to_ranks(const uint32_t* __restrict__ ids, uint32_t n, const uint32_t* __restrict__ rank,
-                               uint32_t* __restrict__ out)
+// Input ids to ranks; an id >= nv sets *err and maps to rank 0 (the call then
+// fails before any feature is used).
+__global__ void k_ids_to_ranks(const uint32_t* __restrict__ ids, uint32_t n, uint32_t nv,
+                               const uint32_t* __restrict__ rank, uint32_t* __restrict__ out,
+                               uint32_t* __restrict__ err)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        out[i] = rank[ids[i]];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t v = ids[i];
+        if (v >= nv) {
+            atomicOr(err, 1u);
+            v = 0;
+        }
+        out[i] = rank[v];
+    }
 }
 
 // ---------------------------------------------------------------- BF16 inference
@@ -418,8 +427,24 @@ mce_status root_features(const Oriented& g, const uint32_t* roots_rank, uint32_t
 mce_status ids_to_ranks(const Oriented& g, const uint32_t* ids, uint32_t n, uint32_t* out, hipStream_t s)
 {
     if (!n) return MCE_OK;
-    k_ids_to_ranks<<<blocks_for(n, 256, 8192), 256, 0, s>>>(ids, n, g.rank.as<uint32_t>(), out);
+    if (g.n == 0) {
+        set_error("root id out of range (graph has no vertices)");
+        return MCE_ERR_INVALID_ARG;
+    }
+    DevBuf err;
+    mce_status st;
+    if ((st = err.alloc(4)) != MCE_OK) return st;
+    fill_u32(err.as<uint32_t>(), 0, 1, s);
+    k_ids_to_ranks<<<blocks_for(n, 256, 8192), 256, 0, s>>>(ids, n, g.n, g.rank.as<uint32_t>(), out,
+                                                            err.as<uint32_t>());
     MCE_HIP_TRY(hipGetLastError());
+    uint32_t herr = 0;
+    MCE_HIP_TRY(hipMemcpyAsync(&herr, err.p, 4, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    if (herr) {
+        set_error("root id out of range");
+        return MCE_ERR_INVALID_ARG;
+    }
     return MCE_OK;
 }
 

@@ -133,6 +133,9 @@ struct EnumConfig {
     uint32_t donate_min_p = 10;
     uint32_t donate_max_depth = 0;
     uint32_t donate_every = 1;
+    uint32_t task_log_min_us = 0;
+    uint64_t* task_log = nullptr;
+    uint64_t task_log_cap = 0;
     uint64_t timeout_ms = 600000;
     const uint32_t* root_order = nullptr;  // device, input ids
     uint64_t* root_count = nullptr;

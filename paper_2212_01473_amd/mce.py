@@ -38,10 +38,12 @@ F_STREAM = 0x10
 F_ROOT_STATS = 0x20
 F_REVERSE_ORDER = 0x40
 F_CUSTOM_ORDER = 0x80
+F_TASK_LOG = 0x100
 
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
               "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words",
-              "busy_ns", "max_task_ns", "xrow_tasks", "build_ns"]
+              "busy_ns", "max_task_ns", "xrow_tasks", "build_ns", "task_log", "donate_ns",
+              "pop_fails"]
 
 FULL = 0xFFFFFFFF
 
@@ -71,7 +73,8 @@ class Options(C.Structure):
                 ("stream", C.c_void_p), ("timeout_ms", C.c_uint64), ("root_order", C.c_void_p),
                 ("root_count", C.c_void_p), ("root_hash", C.c_void_p), ("root_nodes", C.c_void_p),
                 ("xrow_ratio", C.c_uint32), ("xrow_min_u", C.c_uint32), ("xrow_budget_words", C.c_uint64),
-                ("donate_every", C.c_uint32), ("reserved2", C.c_uint32)]
+                ("donate_every", C.c_uint32), ("task_log_min_us", C.c_uint32),
+                ("task_log", C.c_void_p), ("task_log_cap", C.c_uint64)]
 
 
 class TrainOptions(C.Structure):
@@ -266,18 +269,21 @@ def make_options(max_root_core: int = FULL, worker_list: bool = True, flags: int
                  model=None, split: bool = False, split_top: int = 0,
                  bitmap_max_p: int = 0, donate_min_p: int = 0, donate_max_depth: int = 0,
                  timeout_ms: int = 0, stream=None, root_order=None, root_stats=None, xrow_ratio: int = 0,
-                 xrow_budget_words: int = 0, xrow_min_u: int = 0, donate_every: int = 0) -> Options:
+                 xrow_budget_words: int = 0, xrow_min_u: int = 0, donate_every: int = 0,
+                 task_log=None, task_log_min_us: int = 0) -> Options:
     o = Options()
     o.donate_every = donate_every
     o.xrow_ratio = xrow_ratio
     o.xrow_min_u = xrow_min_u
     o.xrow_budget_words = xrow_budget_words
+    o.struct_size = C.sizeof(Options)
+    o.flags = flags | (F_WORKER_LIST if worker_list else 0) | F_STATS
     if model is not None:
         o.flags |= F_LEARNED_ORDER | (F_SPLIT if split else 0)
         o.model = C.c_void_p(model.data_ptr())
         o.split_top = split_top
-    o.struct_size = C.sizeof(Options)
-    o.flags = flags | (F_WORKER_LIST if worker_list else 0) | F_STATS
+    elif split:
+        raise ValueError("split needs a model")
     o.max_root_core = int(max_root_core) & 0xFFFFFFFF
     o.wg_per_cu = wg_per_cu
     o.bitmap_max_p = bitmap_max_p
@@ -288,6 +294,12 @@ def make_options(max_root_core: int = FULL, worker_list: bool = True, flags: int
     if root_order is not None:
         o.flags |= F_CUSTOM_ORDER
         o.root_order = C.c_void_p(root_order.data_ptr())
+    if task_log is not None:
+        # device int64 tensor [cap, 8]
+        o.flags |= F_TASK_LOG
+        o.task_log = C.c_void_p(task_log.data_ptr())
+        o.task_log_cap = int(task_log.shape[0])
+        o.task_log_min_us = task_log_min_us
     if root_stats is not None:
         cnt, hsh, nodes = root_stats
         o.flags |= F_ROOT_STATS

@@ -133,15 +133,23 @@ def test_split_every_root_keeps_results(gpu_lib):
     import torch
 
     rand = torch.from_numpy(_rand_model(5)).cuda()
-    # a huge positive output bias predicts every root as costly: all roots split
+    # zero output weights and a huge bias: every root is predicted equally costly
+    rand[mlp.oW4:mlp.ob4] = 0.0
     rand[mlp.ob4] = 30.0
     g = I.chung_lu_planted(n=3000, wmax=30, n_cliques=12, cmin=70, cmax=100, pool=3000, seed=5)
     exp = oracle.mce(g)
     with gpu_lib.load_graph(g) as dg:
+        plain = gpu_lib.enumerate_cliques(dg, timeout_ms=60000)
         r = gpu_lib.enumerate_cliques(dg, model=rand, split=True, timeout_ms=60000)
     assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
-    # every queued root was split into 64 groups of level-1 branches
-    assert r.stats["roots"] % 64 == 0 and r.stats["roots"] >= 64
+    # equal predictions: the target task is 1/(4 * workgroups) of the total, so
+    # every root becomes the same ceil(4 * workgroups / roots) groups (float
+    # rounding of the quotient may add one when it is an integer)
+    n_roots = plain.stats["roots"]
+    assert r.stats["roots"] % n_roots == 0
+    groups = -(-4 * plain.stats["workgroups"] // n_roots)
+    assert r.stats["roots"] // n_roots in (min(groups, 64), min(groups + 1, 64))
+    assert r.stats["roots"] > n_roots
 
 
 def test_trained_model_ranks_held_out_roots(gpu_lib):

@@ -153,6 +153,36 @@ def test_custom_order(gpu_lib):
     check(gpu_lib, g, root_order=perm)
 
 
+def test_custom_order_rejects_non_permutations(gpu_lib):
+    import torch
+
+    g = I.rmat(10, 8, 0.57, 0.19, 0.19, 0.05, 8)
+    bad_range = np.arange(g.n, dtype=np.int32)
+    bad_range[5] = g.n
+    dup = np.arange(g.n, dtype=np.int32)
+    dup[7] = 3
+    with gpu_lib.load_graph(g) as dg:
+        for arr, msg in ((bad_range, "id >= n"), (dup, "not a permutation")):
+            with pytest.raises(gpu_lib.MCEError) as e:
+                gpu_lib.enumerate_cliques(dg, root_order=torch.from_numpy(arr).cuda())
+            assert e.value.status == gpu_lib.MCE_ERR_INVALID_ARG and msg in str(e.value)
+        # the handle still works after the rejected calls
+        exp = oracle.mce(g)
+        r = gpu_lib.enumerate_cliques(dg)
+        assert (r.count, r.hash) == (exp.count, exp.hash)
+
+
+def test_root_features_reject_bad_ids(gpu_lib):
+    import torch
+
+    g = I.rmat(10, 8, 0.57, 0.19, 0.19, 0.05, 8)
+    with gpu_lib.load_graph(g) as dg:
+        ids = torch.tensor([0, 1, g.n], dtype=torch.int32, device="cuda")
+        with pytest.raises(gpu_lib.MCEError) as e:
+            gpu_lib.root_features(dg, ids)
+        assert e.value.status == gpu_lib.MCE_ERR_INVALID_ARG
+
+
 # ---------------------------------------------------------------- peel arrays
 
 @pytest.mark.parametrize("make", [lambda: I.workload("er1000"),

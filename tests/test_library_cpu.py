@@ -40,7 +40,8 @@ int main(void) {
   printf("mce_result %zu\n", sizeof(mce_result));
   printf("mce_graph_info %zu\n", sizeof(mce_graph_info));
   F(mce_options, model); F(mce_options, stream); F(mce_options, timeout_ms); F(mce_options, root_nodes);
-  F(mce_options, xrow_min_u); F(mce_options, xrow_budget_words);
+  F(mce_options, xrow_min_u); F(mce_options, xrow_budget_words); F(mce_options, task_log);
+  F(mce_options, task_log_cap);
   F(mce_result, hist); F(mce_result, stream_vertices); F(mce_result, stats);
   F(mce_graph_info, n_isolated); F(mce_graph_info, n_graphs);
   return 0;
@@ -59,6 +60,8 @@ int main(void) {
     assert got["mce_options.root_nodes"] == mce.Options.root_nodes.offset
     assert got["mce_options.xrow_min_u"] == mce.Options.xrow_min_u.offset
     assert got["mce_options.xrow_budget_words"] == mce.Options.xrow_budget_words.offset
+    assert got["mce_options.task_log"] == mce.Options.task_log.offset
+    assert got["mce_options.task_log_cap"] == mce.Options.task_log_cap.offset
     assert got["mce_result.hist"] == mce.Result.hist.offset
     assert got["mce_result.stream_vertices"] == mce.Result.stream_vertices.offset
     assert got["mce_result.stats"] == mce.Result.stats.offset
@@ -104,3 +107,18 @@ def test_binding_fails_loudly_without_library(tmp_path):
             mce.load_library(str(tmp_path / "missing.so"))
     finally:
         mce._lib = saved
+
+
+def test_options_carry_learned_flags():
+    import torch
+
+    model = torch.zeros(mce.MODEL_FLOATS)
+    o = mce.make_options(model=model, split=True)
+    assert o.flags & mce.F_LEARNED_ORDER and o.flags & mce.F_SPLIT and o.flags & mce.F_WORKER_LIST
+    assert o.model == model.data_ptr()
+    o = mce.make_options(model=model)
+    assert o.flags & mce.F_LEARNED_ORDER and not o.flags & mce.F_SPLIT
+    o = mce.make_options()
+    assert not o.flags & (mce.F_LEARNED_ORDER | mce.F_SPLIT)
+    with pytest.raises(ValueError):
+        mce.make_options(split=True)
