@@ -41,7 +41,6 @@ namespace {
 constexpr uint32_t kFlagIdle = 0u, kFlagTask = 1u, kFlagTerm = 2u;
 constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
 constexpr int kHistLds = 256;
-constexpr int kDepth = 66;                 // register-mode stack levels (universe <= 64)
 constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
 struct Ctrl {
@@ -125,6 +124,10 @@ __device__ inline uint64_t rl64(uint64_t v, uint32_t l)
     return ((uint64_t)hi << 32) | lo;
 }
 __device__ inline uint32_t rl32(uint32_t v, uint32_t l) { return __builtin_amdgcn_readlane(v, l); }
+// Register stacks: lane d of a VGPR holds the value of DFS level d; a push
+// replaces lane l's value with the wave-uniform x.
+__device__ inline uint64_t wl64(uint64_t v, uint32_t l, uint64_t x) { return __lane_id() == l ? x : v; }
+__device__ inline uint32_t wl32(uint32_t v, uint32_t l, uint32_t x) { return __lane_id() == l ? x : v; }
 __device__ inline uint64_t shfl64(uint64_t v, uint32_t src)
 {
     uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, 64);
@@ -198,18 +201,19 @@ enum : int {
 // Fixed-size LDS of a workgroup (static offsets: no pointer registers).
 struct LdsFixed {
     uint64_t pw[64], xw[64];
-    uint64_t lP[kDepth], lXP[kDepth], lB[kDepth], lK[kDepth];  // list-mode stack
-    uint64_t fP[kDepth], fXP[kDepth], fXX[kDepth], fB[kDepth], fK[kDepth];  // folded-mode stack
-    uint64_t stat[S_COUNT + 4];  // + snapshots at task start: nodes, donations, build time
-    uint32_t lL[kDepth], lA[kDepth], fA[kDepth];
+    uint64_t lP[64], lXP[64], lB[64], lK[64];  // list executor stack while suspended (lane = level)
+    uint64_t stat[S_COUNT + 4];  // + snapshots at task start: (unused), donations, build time
+    uint32_t lL[64], lA[64], lR[64];
+    uint32_t frame[4];  // suspended executors: mid depth, mid split counter, list depth, list split counter
     uint32_t hist[kHistLds];
     uint32_t sidx[64], soff[64], sbeg[64], sxj[64];
 };
 __shared__ LdsFixed S;
 
+// LDS atomics without return: no wait on the search's critical path
 __device__ inline void stat_add(int k, uint64_t v)
 {
-    if (__lane_id() == 0) S.stat[k] += v;
+    if (__lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&S.stat[k]), (unsigned long long)v);
 }
 
 struct Wg {
@@ -241,6 +245,7 @@ struct Wg {
     uint32_t cur_gid;
     uint32_t hmax;
     uint64_t task_t0;
+    uint64_t nodes, nodes_t0;  // search-tree nodes (all tasks; at the current task's start)
     uint64_t don_t0;  // start of the current donation attempt
     uint32_t probes;  // per lane
     uint32_t wl_tick, wl_seen, poll;
@@ -365,7 +370,7 @@ __device__ void report(const Params& p, Wg& w, uint32_t rsize, uint64_t ks)
     w.hmax = max(w.hmax, rsize);
     const uint32_t lane = lane_id();
     if (lane == 0) {
-        if (rsize < (uint32_t)kHistLds) S.hist[rsize] += 1;
+        if (rsize < (uint32_t)kHistLds) atomicAdd(&S.hist[rsize], 1u);
         else atomicAdd(&p.ghist[(uint64_t)w.cur_gid * p.hist_len + min(rsize, p.hist_len - 1)], 1ull);
     }
     if (p.flags & MCE_F_STREAM) {
@@ -487,20 +492,76 @@ __device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, 
     stat_add(S_DONATE, uni64(now_ticks()) - w.don_t0);
 }
 
+// ---------------------------------------------------------------- executors
+// Three executors share one dispatcher (run_task), so each is instantiated
+// once.  The mid executor (universe > 64 vertices) and the list executor
+// (universe <= 64, X_X as an index list) hand a child whose P u X_P has at
+// most 64 vertices to a smaller executor: they push their current level, as
+// for a descent, keep a small frame in LDS and return; the dispatcher runs the
+// smaller executor and resumes them, which pops that level.  Only the
+// running executor's state is live in registers.
+
+// A node over a universe of m <= 64 vertices (lane k holds vertex k), passed
+// from one executor to the next.
+struct SmallJob {
+    uint32_t m, L, rs;
+    uint32_t su, oidx, xj;  // per lane: rank, index in the task universe, X_X entry of lane (< L)
+    uint64_t skey, rowP;    // per lane: key, adjacency over the small universe
+    uint64_t P, XP, ks;
+    bool anc;
+};
+
+enum : uint32_t { kDone = 0, kYieldFold = 1, kYieldList = 2 };
+enum : uint32_t { kExDone = 0, kExFold = 1, kExList = 2, kExMid = 3 };
+
 // ---------------------------------------------------------------- folded executor
-// P-universe of m <= 64 vertices (lane k: rank su, key skey, rowP over the
-// P-universe, rowX over the folded X set); folded X set of up to 64 vertices
-// (lane j: rank xrank, xrowP = its adjacency over the P-universe).
-__device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
-                           uint64_t rowP, uint64_t rowX, uint64_t xrowP, uint32_t xrank, uint64_t P, uint64_t XP,
-                           uint64_t XX, uint64_t ks, uint32_t rs, bool anc)
+// Universe of m <= 64 vertices (lane k: rank su, key skey, rowP over the
+// universe, rowX over the folded X set); folded X set of up to 64 vertices
+// (lane j: rank xrank, xrowP = its adjacency over the universe).  X_X (L <= 64
+// entries, lane j holds entry xj) is folded from the X rows first.
+__device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root, const SmallJob& j)
 {
     const uint32_t lane = lane_id();
+    const uint32_t m = j.m, L = j.L;
     const bool valid = lane < m;
-    uint32_t depth = 0;
+    const bool vx = lane < L;
+    const uint32_t su = j.su;
+    const uint64_t skey = j.skey, rowP = j.rowP;
+    const uint32_t xrank = vx ? w.xr[j.xj] : 0u;
+    uint64_t xrowP = 0;
+    if (L) {
+        if (w.W == 1) {
+            // the small universe is the task universe itself (oidx = lane)
+            xrowP = vx ? w.xrows[j.xj] : 0ull;
+        } else {
+            // o_k ascend with k: load each X-row word once
+            const uint64_t* xrow = w.xrows + (uint64_t)j.xj * w.W;
+            uint32_t k = 0;
+            while (k < m) {
+                uint32_t q = rl32(j.oidx, k) >> 6;
+                uint64_t word = vx ? xrow[q] : 0ull;
+                for (; k < m; ++k) {
+                    uint32_t ok = rl32(j.oidx, k);
+                    if ((ok >> 6) != q) break;
+                    xrowP |= ((word >> (ok & 63)) & 1ull) << k;
+                }
+            }
+        }
+    }
+    uint64_t rowX = 0;
+    for (uint32_t t = 0; t < L; ++t) {
+        uint64_t wt = rl64(xrowP, t);
+        if ((wt >> lane) & 1ull) rowX |= 1ull << t;
+    }
+    uint64_t P = j.P, XP = j.XP, XX = low_mask(L), ks = j.ks;
+    uint32_t rs = j.rs;
+    bool anc = j.anc;
+    uint32_t depth = 0;  // < m <= 64: the stack fits one lane per level
     uint64_t B;
+    uint64_t sP = 0, sXP = 0, sXX = 0, sB = 0, sK = 0;
+    uint32_t sA = 0;
 enter : {
-    stat_add(S_NODES, 1);
+    ++w.nodes;
     uint64_t cp = P | XP;
     uint32_t key = 0;
     if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
@@ -514,12 +575,12 @@ enter : {
         if (B == 0) {
             if (depth == 0) return;
             --depth;
-            P = S.fP[depth];
-            XP = S.fXP[depth];
-            XX = S.fXX[depth];
-            B = S.fB[depth];
-            ks = S.fK[depth];
-            anc = S.fA[depth] != 0;
+            P = rl64(sP, depth);
+            XP = rl64(sXP, depth);
+            XX = rl64(sXX, depth);
+            B = rl64(sB, depth);
+            ks = rl64(sK, depth);
+            anc = rl32(sA, depth) != 0;
             --rs;
             continue;
         }
@@ -535,7 +596,7 @@ enter : {
         uint32_t vb = rl32(su, bb);
         uint64_t ksc = ks + rl64(skey, bb);
         if (Pc == 0) {
-            stat_add(S_NODES, 1);
+            ++w.nodes;
             if ((XPc | XXc) == 0) {
                 if (p.flags & MCE_F_STREAM) {
                     if (lane == 0) w.R[rs] = vb;
@@ -557,15 +618,13 @@ enter : {
                 continue;
             }
         }
-        if (lane == 0) {
-            S.fP[depth] = P;
-            S.fXP[depth] = XP;
-            S.fXX[depth] = XX;
-            S.fB[depth] = B;
-            S.fK[depth] = ks;
-            S.fA[depth] = anc ? 1u : 0u;
-            w.R[rs] = vb;
-        }
+        sP = wl64(sP, depth, P);
+        sXP = wl64(sXP, depth, XP);
+        sXX = wl64(sXX, depth, XX);
+        sB = wl64(sB, depth, B);
+        sK = wl64(sK, depth, ks);
+        sA = wl32(sA, depth, anc ? 1u : 0u);
+        if (lane == 0) w.R[rs] = vb;
         anc = anc || (B != 0);
         ++depth;
         ++rs;
@@ -577,57 +636,55 @@ enter : {
     }
 }
 
-// Fold X_X (xx[0, L), L <= 64) into registers and run the folded executor.
-// oidx: lane k's index in the task universe (X rows are over that universe).
-__device__ __forceinline__ void fold_and_run(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
-                             uint32_t oidx, uint64_t rowP, uint64_t P, uint64_t XP, uint32_t L, uint32_t xj,
-                             uint64_t ks, uint32_t rs, bool anc)
-{
-    const uint32_t lane = lane_id();
-    const bool vx = lane < L;
-    const uint32_t xrank = vx ? w.xr[xj] : 0u;
-    uint64_t xrowP = 0;
-    if (L) {
-        if (w.W == 1) {
-            // the small universe is the task universe itself (oidx = lane)
-            xrowP = vx ? w.xrows[xj] : 0ull;
-        } else {
-            // o_k ascend with k: load each X-row word once
-            const uint64_t* xrow = w.xrows + (uint64_t)xj * w.W;
-            uint32_t k = 0;
-            while (k < m) {
-                uint32_t q = rl32(oidx, k) >> 6;
-                uint64_t word = vx ? xrow[q] : 0ull;
-                for (; k < m; ++k) {
-                    uint32_t ok = rl32(oidx, k);
-                    if ((ok >> 6) != q) break;
-                    xrowP |= ((word >> (ok & 63)) & 1ull) << k;
-                }
-            }
-        }
-    }
-    uint64_t rowX = 0;
-    for (uint32_t j = 0; j < L; ++j) {
-        uint64_t wj = rl64(xrowP, j);
-        if ((wj >> lane) & 1ull) rowX |= 1ull << j;
-    }
-    run_folded(p, w, root, m, su, skey, rowP, rowX, xrowP, xrank, P, XP, low_mask(L), ks, rs, anc);
-}
-
 // ---------------------------------------------------------------- list executor
-// P-universe of m <= 64 vertices in registers; X_X stays the index list.
-// (c, C): at depth 0 descend only into branches t with t % C == c.
-__device__ __forceinline__ void run_list(const Params& p, Wg& w, uint32_t root, uint32_t m, uint32_t su, uint64_t skey,
-                         uint32_t oidx, uint64_t rowP, uint64_t P, uint64_t XP, uint32_t L, uint64_t ks,
-                         uint32_t rs, bool anc, uint32_t c, uint32_t C)
+// Universe of m <= 64 vertices in registers (the job's per-lane fields, which
+// stay untouched while a folded child runs); X_X stays the index list.
+// (c, C): at depth 0 descend only into branches t with t % C == c.  Returns
+// kYieldFold with j updated to a child for the folded executor, or kDone.
+__device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t root, bool resume, SmallJob& j,
+                                             uint32_t c, uint32_t C)
 {
     const uint32_t lane = lane_id();
+    const uint32_t m = j.m;
     const bool valid = lane < m;
     const bool can_fold = w.have_xrows;
-    uint32_t depth = 0, t0 = 0;
-    uint64_t B;
+    const uint32_t su = j.su, oidx = j.oidx;
+    const uint64_t skey = j.skey, rowP = j.rowP;
+    uint32_t depth, t0, rs, L;
+    uint64_t P, XP, ks, B;
+    bool anc;
+    // register stack (lane d = level d < m <= 64); spilled to LDS while a
+    // folded child runs
+    uint64_t sP, sXP, sB, sK;
+    uint32_t sL, sA, sR;
+    bool pop_first = resume;  // resuming: the suspended level is popped first
+    if (resume) {
+        depth = S.frame[2];
+        t0 = S.frame[3];
+        rs = L = 0;
+        P = XP = ks = B = 0;
+        anc = false;
+        sP = S.lP[lane];
+        sXP = S.lXP[lane];
+        sB = S.lB[lane];
+        sK = S.lK[lane];
+        sL = S.lL[lane];
+        sA = S.lA[lane];
+        sR = S.lR[lane];
+        goto loop;
+    }
+    sP = sXP = sB = sK = 0;
+    sL = sA = sR = 0;
+    depth = 0;
+    t0 = 0;
+    rs = j.rs;
+    L = j.L;
+    P = j.P;
+    XP = j.XP;
+    ks = j.ks;
+    anc = j.anc;
 enter : {
-    stat_add(S_NODES, 1);
+    ++w.nodes;
     uint64_t cp = P | XP;
     uint32_t key = 0;
     if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
@@ -635,20 +692,22 @@ enter : {
     uint32_t piv = 255u - (best & 255u);
     B = P & ~rl64(rowP, piv);
 }
+loop:
     while (true) {
-        if (B == 0) {
-            if (depth == 0) return;
+        if (pop_first || B == 0) {
+            if (depth == 0) return kDone;
+            pop_first = false;
             --depth;
-            P = S.lP[depth];
-            XP = S.lXP[depth];
-            B = S.lB[depth];
-            ks = S.lK[depth];
-            L = S.lL[depth];
-            anc = S.lA[depth] != 0;
-            --rs;
+            P = rl64(sP, depth);
+            XP = rl64(sXP, depth);
+            B = rl64(sB, depth);
+            ks = rl64(sK, depth);
+            L = rl32(sL, depth);
+            anc = rl32(sA, depth) != 0;
+            rs = rl32(sR, depth);
             continue;
         }
-        if ((++w.poll & 1023u) == 0 && check_deadline(p, w)) return;
+        if ((++w.poll & 1023u) == 0 && check_deadline(p, w)) return kDone;
         uint32_t bb = (uint32_t)__builtin_ctzll(B);
         B &= B - 1;
         uint64_t rp = rl64(rowP, bb);
@@ -663,7 +722,7 @@ enter : {
         uint32_t bidx = rl32(oidx, bb);
         uint64_t ksc = ks + rl64(skey, bb);
         if (Pc == 0) {
-            stat_add(S_NODES, 1);
+            ++w.nodes;
             if (XPc == 0 && !xx_any(p, w, L, bidx, vb)) {
                 if (p.flags & MCE_F_STREAM) {
                     if (lane == 0) w.R[rs] = vb;
@@ -687,23 +746,40 @@ enter : {
             }
         }
         if (lane == 0) w.R[rs] = vb;
-        if (Lc <= 64 && (can_fold || Lc == 0)) {
-            wave_mem_sync();
-            const uint32_t xj = lane < Lc ? w.xx[lane] : 0u;
-            fold_and_run(p, w, root, m, su, skey, oidx, rowP, Pc, XPc, Lc, xj, ksc, rs + 1, anc || (B != 0));
-            if (w.abort) return;
-            continue;
-        }
-        if (lane == 0) {
-            S.lP[depth] = P;
-            S.lXP[depth] = XP;
-            S.lB[depth] = B;
-            S.lK[depth] = ks;
-            S.lL[depth] = L;
-            S.lA[depth] = anc ? 1u : 0u;
-        }
-        anc = anc || (B != 0);
+        sP = wl64(sP, depth, P);
+        sXP = wl64(sXP, depth, XP);
+        sB = wl64(sB, depth, B);
+        sK = wl64(sK, depth, ks);
+        sL = wl32(sL, depth, L);
+        sA = wl32(sA, depth, anc ? 1u : 0u);
+        sR = wl32(sR, depth, rs);
+        const bool canc = anc || (B != 0);
         ++depth;
+        if (Lc <= 64 && (can_fold || Lc == 0)) {
+            // suspend: the folded child runs next, then this level is popped
+            wave_mem_sync();
+            j.xj = lane < Lc ? w.xx[lane] : 0u;
+            j.P = Pc;
+            j.XP = XPc;
+            j.L = Lc;
+            j.ks = ksc;
+            j.rs = rs + 1;
+            j.anc = canc;
+            S.lP[lane] = sP;
+            S.lXP[lane] = sXP;
+            S.lB[lane] = sB;
+            S.lK[lane] = sK;
+            S.lL[lane] = sL;
+            S.lA[lane] = sA;
+            S.lR[lane] = sR;
+            if (lane == 0) {
+                S.frame[2] = depth;
+                S.frame[3] = t0;
+            }
+            wave_mem_sync();
+            return kYieldFold;
+        }
+        anc = canc;
         ++rs;
         P = Pc;
         XP = XPc;
@@ -735,71 +811,16 @@ __device__ __forceinline__ uint32_t xx_members(Wg& w, uint64_t XX, bool to_list)
     return (!to_list && lane < base) ? S.sxj[lane] : 0u;
 }
 
-// Re-index a node whose P u X_P has at most 64 vertices into registers and run
-// it with the folded or the list executor.
-__device__ __forceinline__ void compact_and_run(const Params& p, Wg& w, uint32_t root, const uint64_t* rows, uint32_t ws,
-                                uint64_t Pc, uint64_t XPc, uint32_t L, uint64_t XXc, uint64_t ks, uint32_t rs,
-                                bool anc)
-{
-    const uint32_t lane = lane_id();
-    const uint32_t W = w.W;
-    uint64_t cand = lane < W ? (Pc | XPc) : 0ull;
-    uint32_t cnt = (uint32_t)__popcll(cand);
-    uint32_t pre = wave_excl_scan(cnt);
-    uint32_t m = wave_sum(cnt);
-    uint64_t cc = cand;
-    uint32_t t = pre;
-    while (cc) {
-        uint32_t bit = (uint32_t)__builtin_ctzll(cc);
-        cc &= cc - 1;
-        S.sidx[t++] = lane * 64 + bit;
-    }
-    wave_mem_sync();
-    const bool valid = lane < m;
-    const uint32_t o = valid ? S.sidx[lane] : 0u;
-    const uint32_t su = valid ? w.uarr[o] : 0u;
-    const uint64_t skey = valid ? w.ukey[o] : 0ull;
-    // local row of vertex k: bit k2 set iff o_k and o_k2 are adjacent; the
-    // sorted o_k2 visit each source word once, so each word is loaded once
-    uint64_t row = 0;
-    const uint64_t* ro = rows + (uint64_t)o * ws;
-    {
-        uint32_t k2 = 0;
-        while (k2 < m) {
-            uint32_t q = S.sidx[k2] >> 6;
-            uint64_t word = valid ? ro[q] : 0ull;
-            for (; k2 < m; ++k2) {
-                uint32_t o2 = S.sidx[k2];
-                if ((o2 >> 6) != q) break;
-                row |= ((word >> (o2 & 63)) & 1ull) << k2;
-            }
-        }
-    }
-    uint64_t pword = shfl64(Pc, o >> 6);
-    uint64_t xword = shfl64(XPc, o >> 6);
-    uint64_t Ps = __ballot(valid && ((pword >> (o & 63)) & 1ull));
-    uint64_t XPs = __ballot(valid && ((xword >> (o & 63)) & 1ull));
-    wave_mem_sync();
-    if (w.have_xrows) {
-        // X_X is a bitmap over the task's X list: fold its members, or list them
-        const uint32_t xj = xx_members(w, XXc, L > 64);
-        if (L <= 64) fold_and_run(p, w, root, m, su, skey, o, row, Ps, XPs, L, xj, ks, rs, anc);
-        else run_list(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc, 0, 1);
-    } else if (L == 0) {
-        fold_and_run(p, w, root, m, su, skey, o, row, Ps, XPs, 0, 0, ks, rs, anc);
-    } else {
-        run_list(p, w, root, m, su, skey, o, row, Ps, XPs, L, ks, rs, anc, 0, 1);
-    }
-}
-
-// Mid executor: universe of up to 4096 vertices, one 64-bit word per lane
-// (W words).  The pivot maximises |P n N(u)| over u in P u X_P (Section
-// III-E).  X_X is either a bitmap over the task's X list (lanes hold its Wx
-// words; a child's X_X is one AND with the X column of the branch vertex) or,
-// when the X columns were not built, the partitioned index list of Section
-// III-E.  The DFS stack lives in this workgroup's HBM scratch.
-__device__ __forceinline__ void run_mid(const Params& p, Wg& w, uint32_t root, uint32_t nu, const uint64_t* rows, uint32_t ws,
-                        uint64_t P, uint64_t XP, uint32_t L, uint64_t ks, uint32_t rs, uint32_t c, uint32_t C)
+// Universe of up to 4096 vertices, one 64-bit word per lane (W words).  The
+// pivot maximises |P n N(u)| over u in P u X_P (Section III-E).  X_X is either
+// a bitmap over the task's X list (lanes hold its Wx words; a child's X_X is
+// one AND with the X column of the branch vertex) or, when the X columns were
+// not built, the partitioned index list of Section III-E.  The DFS stack lives
+// in this workgroup's HBM scratch.  A child whose P u X_P fits 64 vertices is
+// re-indexed into j and handed over (kYieldFold / kYieldList).
+__device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t root, uint32_t nu, const uint64_t* rows,
+                                            uint32_t ws, bool resume, SmallJob& j, uint32_t L0, uint32_t c,
+                                            uint32_t C)
 {
     const uint32_t lane = lane_id();
     const uint32_t W = w.W;
@@ -808,12 +829,30 @@ __device__ __forceinline__ void run_mid(const Params& p, Wg& w, uint32_t root, u
     const uint32_t gws = p.wg;
     const uint32_t lvl_words = 3 * gws + p.wgx;
     const uint32_t* U = w.uarr;
-    uint32_t depth = 0, t0 = 0;
-    uint64_t B = 0;
-    uint64_t XX = lane < Wx ? low_mask(L - lane * 64) : 0ull;
-    bool anc = false;
+    uint32_t depth, t0, rs, L;
+    uint64_t P, XP, XX, B, ks;
+    bool anc;
+    bool pop_first = resume;  // resuming: the suspended level is popped first
+    if (resume) {
+        depth = S.frame[0];
+        t0 = S.frame[1];
+        rs = L = 0;
+        P = XP = XX = B = ks = 0;
+        anc = false;
+        goto loop;
+    }
+    depth = 0;
+    t0 = 0;
+    rs = j.rs;
+    L = L0;
+    ks = j.ks;
+    anc = false;
+    P = lane < W ? S.pw[lane] : 0ull;
+    XP = lane < W ? S.xw[lane] : 0ull;
+    XX = lane < Wx ? low_mask(L - lane * 64) : 0ull;
+    B = 0;
 enter : {
-    stat_add(S_NODES, 1);
+    ++w.nodes;
     uint32_t best = 0;
     uint64_t cand = P | XP;
     for (uint32_t t = 0; t < W; ++t) {
@@ -831,10 +870,12 @@ enter : {
     uint32_t piv = 8191u - (best & 8191u);
     B = lane < W ? (P & ~rows[(uint64_t)piv * ws + lane]) : 0ull;
 }
+loop:
     while (true) {
-        uint64_t bm = __ballot(B != 0);
+        uint64_t bm = pop_first ? 0ull : __ballot(B != 0);
         if (bm == 0) {
-            if (depth == 0) return;
+            if (depth == 0) return kDone;
+            pop_first = false;
             --depth;
             const uint64_t* lvl = w.gstack + (uint64_t)depth * lvl_words;
             if (lane < W) {
@@ -843,14 +884,14 @@ enter : {
                 B = lvl[2 * gws + lane];
             }
             if (lane < Wx) XX = lvl[3 * gws + lane];
-            uint64_t meta = w.gmeta[2 * depth];
-            ks = w.gmeta[2 * depth + 1];
+            uint64_t meta = w.gmeta[3 * depth];
+            ks = w.gmeta[3 * depth + 1];
+            rs = (uint32_t)w.gmeta[3 * depth + 2];
             L = (uint32_t)meta;
             anc = (meta >> 32) != 0;
-            --rs;
             continue;
         }
-        if ((++w.poll & 255u) == 0 && check_deadline(p, w)) return;
+        if ((++w.poll & 255u) == 0 && check_deadline(p, w)) return kDone;
         uint32_t w0 = (uint32_t)__builtin_ctzll(bm);
         uint64_t word = rl64(B, w0);
         uint32_t bit = (uint32_t)__builtin_ctzll(word);
@@ -874,7 +915,7 @@ enter : {
         uint32_t nxc = wave_sum((uint32_t)__popcll(XPc));
         bool more_here = __ballot(B != 0) != 0;
         if (npc == 0) {
-            stat_add(S_NODES, 1);
+            ++w.nodes;
             bool xhit = xb ? __ballot(XXc != 0) != 0 : (nxc == 0 && xx_any(p, w, L, bb, vb));
             if (nxc == 0 && !xhit) {
                 if (p.flags & MCE_F_STREAM) {
@@ -919,13 +960,7 @@ enter : {
                 continue;
             }
         }
-        if (lane == 0) w.R[rs] = vb;
-        if (npc + nxc <= 64) {
-            wave_mem_sync();
-            compact_and_run(p, w, root, rows, ws, Pc, XPc, Lc, XXc, ksc, rs + 1, anc || more_here || depth > 0);
-            if (w.abort) return;
-            continue;
-        }
+        // push this level (also when the child is handed to a smaller executor)
         uint64_t* lvl = w.gstack + (uint64_t)depth * lvl_words;
         if (lane < W) {
             lvl[lane] = P;
@@ -934,10 +969,71 @@ enter : {
         }
         if (lane < Wx) lvl[3 * gws + lane] = XX;
         // every lane stores the same meta words, so each later reads its own store
-        w.gmeta[2 * depth] = ((uint64_t)(anc ? 1u : 0u) << 32) | L;
-        w.gmeta[2 * depth + 1] = ks;
-        anc = anc || more_here;
+        w.gmeta[3 * depth] = ((uint64_t)(anc ? 1u : 0u) << 32) | L;
+        w.gmeta[3 * depth + 1] = ks;
+        w.gmeta[3 * depth + 2] = rs;
+        if (lane == 0) w.R[rs] = vb;
+        const bool canc = anc || more_here || depth > 0;
         ++depth;
+        if (npc + nxc <= 64) {
+            // re-index the child's P u X_P (at most 64 vertices) into registers
+            uint64_t cand = lane < W ? (Pc | XPc) : 0ull;
+            uint32_t cnt = (uint32_t)__popcll(cand);
+            uint32_t pre = wave_excl_scan(cnt);
+            uint32_t msz = wave_sum(cnt);
+            uint64_t cc = cand;
+            uint32_t tt = pre;
+            while (cc) {
+                uint32_t bt = (uint32_t)__builtin_ctzll(cc);
+                cc &= cc - 1;
+                S.sidx[tt++] = lane * 64 + bt;
+            }
+            wave_mem_sync();
+            const bool valid = lane < msz;
+            const uint32_t o = valid ? S.sidx[lane] : 0u;
+            // local row of vertex k: bit k2 set iff o_k and o_k2 are adjacent; the
+            // sorted o_k2 visit each source word once, so each word is loaded once
+            uint64_t row = 0;
+            const uint64_t* ro = rows + (uint64_t)o * ws;
+            {
+                uint32_t k2 = 0;
+                while (k2 < msz) {
+                    uint32_t q = S.sidx[k2] >> 6;
+                    uint64_t wq = valid ? ro[q] : 0ull;
+                    for (; k2 < msz; ++k2) {
+                        uint32_t o2 = S.sidx[k2];
+                        if ((o2 >> 6) != q) break;
+                        row |= ((wq >> (o2 & 63)) & 1ull) << k2;
+                    }
+                }
+            }
+            uint64_t pword = shfl64(Pc, o >> 6);
+            uint64_t xword = shfl64(XPc, o >> 6);
+            j.m = msz;
+            j.su = valid ? U[o] : 0u;
+            j.skey = valid ? w.ukey[o] : 0ull;
+            j.oidx = o;
+            j.rowP = row;
+            j.P = __ballot(valid && ((pword >> (o & 63)) & 1ull));
+            j.XP = __ballot(valid && ((xword >> (o & 63)) & 1ull));
+            j.L = Lc;
+            j.ks = ksc;
+            j.rs = rs + 1;
+            j.anc = canc;
+            if (lane == 0) {
+                S.frame[0] = depth;
+                S.frame[1] = t0;
+            }
+            wave_mem_sync();
+            if (xb) {
+                // X_X is a bitmap over the task's X list: fold its members, or list them
+                j.xj = xx_members(w, XXc, Lc > 64);
+                return Lc <= 64 ? kYieldFold : kYieldList;
+            }
+            j.xj = 0;
+            return Lc == 0 ? kYieldFold : kYieldList;
+        }
+        anc = canc;
         ++rs;
         P = Pc;
         XP = XPc;
@@ -1019,11 +1115,11 @@ __device__ inline void begin_task(const Params& p, Wg& w, uint32_t root)
     if (__lane_id() == 0) {
         S.stat[S_CTASK] = 0;
         S.stat[S_HTASK] = 0;
-        S.stat[S_COUNT] = S.stat[S_NODES];  // snapshots at task start
         S.stat[S_COUNT + 1] = S.stat[S_DONATIONS];
         S.stat[S_COUNT + 2] = S.stat[S_BUILD];
     }
     w.task_t0 = uni64(now_ticks());
+    w.nodes_t0 = w.nodes;
 }
 
 __device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint32_t rs, uint32_t c,
@@ -1040,7 +1136,7 @@ __device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t roo
             uint32_t id = p.perm[root];
             atomicAdd(&p.root_count[id], (unsigned long long)S.stat[S_CTASK]);
             atomicAdd(&p.root_hash[id], (unsigned long long)S.stat[S_HTASK]);
-            atomicAdd(&p.root_nodes[id], (unsigned long long)(S.stat[S_NODES] - S.stat[S_COUNT]));
+            atomicAdd(&p.root_nodes[id], (unsigned long long)(w.nodes - w.nodes_t0));
         }
         if ((p.flags & MCE_F_TASK_LOG) && dt >= p.tlog_min_ticks) {
             uint32_t slot = atomicAdd(&p.ctrl->tlog_n, 1u);
@@ -1049,7 +1145,7 @@ __device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t roo
                 e[0] = p.perm[root];
                 e[1] = ((unsigned long long)rs << 32) | nu;
                 e[2] = ((unsigned long long)c << 48) | ((unsigned long long)C << 32) | L;
-                e[3] = S.stat[S_NODES] - S.stat[S_COUNT];
+                e[3] = w.nodes - w.nodes_t0;
                 e[4] = dt * 10;  // 100 MHz clock -> ns
                 e[5] = (S.stat[S_BUILD] - S.stat[S_COUNT + 2]) * 10;
                 e[6] = S.stat[S_DONATIONS] - S.stat[S_COUNT + 1];
@@ -1102,22 +1198,48 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
     wave_mem_sync();
     scan_lists(p, w, 0, nu, nu, rows, ws, nullptr, 0);
     stat_add(S_BUILD, now_ticks() - tb0);
+    // dispatcher: one instance of each executor; a suspended executor resumes
+    // when the one it handed a child to has finished
+    SmallJob j;
+    j.ks = ks;
+    j.rs = rs;
+    j.anc = false;
+    uint32_t ex;
+    bool mid_susp = false, list_susp = false;
+    uint32_t lc = c, lC = C;
     if (nu <= 64) {
         const bool valid = lane < nu;
-        uint32_t su = valid ? w.uarr[lane] : 0u;
-        uint64_t skey = valid ? w.ukey[lane] : 0ull;
-        uint64_t rowP = valid ? rows[lane] : 0ull;
-        uint64_t P = S.pw[0], XP = S.xw[0];
+        j.m = nu;
+        j.su = valid ? w.uarr[lane] : 0u;
+        j.skey = valid ? w.ukey[lane] : 0ull;
+        j.oidx = lane;
+        j.rowP = valid ? rows[lane] : 0ull;
+        j.P = S.pw[0];
+        j.XP = S.xw[0];
+        j.L = L;
+        j.xj = lane;  // xx[i] = i at the start of a task
         wave_mem_sync();
-        if (C == 1 && L <= 64 && (w.have_xrows || L == 0))
-            fold_and_run(p, w, root, nu, su, skey, lane, rowP, P, XP, L, lane, ks, rs, false);
-        else
-            run_list(p, w, root, nu, su, skey, lane, rowP, P, XP, L, ks, rs, false, c, C);
+        ex = (C == 1 && L <= 64 && (w.have_xrows || L == 0)) ? kExFold : kExList;
     } else {
-        uint64_t P = lane < W ? S.pw[lane] : 0ull;
-        uint64_t XP = lane < W ? S.xw[lane] : 0ull;
-        wave_mem_sync();
-        run_mid(p, w, root, nu, rows, ws, P, XP, L, ks, rs, c, C);
+        ex = kExMid;
+    }
+    while (ex != kExDone && !w.abort) {
+        if (ex == kExFold) {
+            run_folded(p, w, root, j);
+            ex = list_susp ? kExList : (mid_susp ? kExMid : kExDone);
+        } else if (ex == kExList) {
+            const uint32_t y = run_list(p, w, root, list_susp, j, lc, lC);
+            list_susp = y == kYieldFold;
+            ex = list_susp ? kExFold : (mid_susp ? kExMid : kExDone);
+        } else {
+            const uint32_t y = run_mid(p, w, root, nu, rows, ws, mid_susp, j, L, c, C);
+            mid_susp = y != kDone;
+            if (y == kYieldList) {
+                lc = 0;
+                lC = 1;
+            }
+            ex = y == kYieldFold ? kExFold : (y == kYieldList ? kExList : kExDone);
+        }
     }
 }
 
@@ -1304,6 +1426,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.cur_gid = 0;
     w.hmax = 0;
     w.task_t0 = 0;
+    w.nodes = w.nodes_t0 = 0;
     w.don_t0 = 0;
     w.probes = 0;
     w.wl_tick = w.wl_seen = w.poll = 0;
@@ -1332,7 +1455,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)S.stat[S_ROOTW]);
         atomicAdd(&p.acc[2 + MCE_STAT_BUSY_NS], (unsigned long long)S.stat[S_BUSY]);
         atomicMax(&p.acc[2 + MCE_STAT_MAX_TASK_NS], (unsigned long long)S.stat[S_MAXTASK]);
-        atomicAdd(&p.acc[2 + MCE_STAT_NODES], (unsigned long long)S.stat[S_NODES]);
+        atomicAdd(&p.acc[2 + MCE_STAT_NODES], (unsigned long long)w.nodes);
         atomicAdd(&p.acc[2 + MCE_STAT_DONATIONS], (unsigned long long)S.stat[S_DONATIONS]);
         atomicAdd(&p.acc[2 + MCE_STAT_TASKS], (unsigned long long)S.stat[S_TASKS]);
         atomicAdd(&p.acc[2 + MCE_STAT_XTESTS], (unsigned long long)S.stat[S_XTESTS]);
@@ -1530,7 +1653,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint64_t off_xrows = off; off = align_up(off + xrow_words * 8 + 8, 256);
     const uint64_t off_xcols = off; off = align_up(off + xcol_words * 8 + 8, 256);
     const uint64_t off_stack = off; off = align_up(off + (uint64_t)(ucap + 2) * (3 * wg_words + wgx_words) * 8, 256);
-    const uint64_t off_meta = off; off = align_up(off + (uint64_t)(ucap + 2) * 16, 256);
+    const uint64_t off_meta = off; off = align_up(off + (uint64_t)(ucap + 2) * 24, 256);
     const uint64_t stride = off;
     const uint64_t budget = 32ull << 30;
     if ((uint64_t)G * stride > budget) G = (uint32_t)std::max<uint64_t>(1, budget / stride);
