@@ -1,14 +1,29 @@
 """Benchmark: exact maximal clique enumeration on one MI355X.
 
-One step = the whole hot path over a graph already resident in HBM: device
+One step = the whole hot path over input already resident in HBM: device
 validation of the CSR, the synchronous-round peel and degeneracy order,
-orientation into later/earlier neighbour lists, the root queue, and the
-persistent enumeration kernel, ending with the results on the host
-(mce_load_csr with device pointers + mce_enumerate + mce_free).
+orientation into later/earlier neighbour lists, the root queue (for the
+learned form: root features, BF16 cost-model inference, ordering and split),
+and the persistent enumeration kernel, ending with the results on the host.
 
-Default workload: R-MAT scale 18, edge factor 16 (a=.57, b=.19, c=.19,
-d=.05, seed 2), enumerated in the core window c = 264 (every maximal clique
-whose smallest core number is at most 264).
+Workloads (seeded synthetic graphs shaped like the paper's inputs):
+  rmat18     R-MAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 2,
+             core window c = 264 (default)
+  rmat22     R-MAT scale 22, edge factor 32, same quadrants, seed 5, window c = 425
+  chunglu1m  Chung-Lu 1M vertices (exponent 2.1, max weight 5000) + 2000 planted
+             cliques of size U[20,60], seed 3, full enumeration
+  er1000     Erdos-Renyi G(1000, 0.02), seed 1, full enumeration
+  batch4096  4096 graphs (n log-uniform [50, 5000]; half Erdos-Renyi with average
+             degree U[5,40], half planted partition 8 blocks .3/.005), seed 4
+
+Forms:
+  plain      degeneracy-order root queue, worker list, default knobs
+  learned    roots ordered by the cost model (trained beforehand on scale-18
+             R-MAT graphs of other seeds, outside the timed region) and the
+             costliest split into groups of level-1 branches
+  batched    (batch4096) every graph in one launch, knobs autotuned beforehand
+             on a held-out batch (512 graphs, seed 104)
+  sequential (batch4096) one load + enumerate per graph
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -25,12 +40,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FULL = 0xFFFFFFFF
 WORKLOADS = {
-    "er1000": dict(c=0xFFFFFFFF, desc="Erdos-Renyi G(n=1000, p=0.02), seed 1, full enumeration"),
-    "rmat18": dict(c=264, desc="R-MAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 2, "
-                              "core window c=264"),
-    "chunglu1m": dict(c=0xFFFFFFFF, desc="Chung-Lu 1M vertices, exponent 2.1, max weight 5000, "
-                                         "2000 planted cliques U[20,60], seed 3, full enumeration"),
+    "er1000": dict(kind="graph", c=FULL, form="plain", compare="",
+                   desc="Erdos-Renyi G(n=1000, p=0.02), seed 1, full enumeration"),
+    "rmat18": dict(kind="graph", c=264, form="plain", compare="learned",
+                   desc="R-MAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 2, core window c=264"),
+    "chunglu1m": dict(kind="graph", c=FULL, form="plain", compare="",
+                      desc="Chung-Lu 1M vertices, exponent 2.1, max weight 5000, 2000 planted cliques U[20,60], "
+                           "seed 3, full enumeration"),
+    "rmat22": dict(kind="graph", c=425, form="learned", compare="plain",
+                   desc="R-MAT scale 22, edge factor 32, a=.57 b=.19 c=.19 d=.05, seed 5, core window c=425"),
+    "batch4096": dict(kind="batch", c=FULL, form="batched", compare="",
+                      desc="4096 graphs, n log-uniform [50,5000], half ER avg degree U[5,40], half planted "
+                           "partition (8 blocks, p_in .3, p_out .005), seed 4, full enumeration"),
 }
 
 
@@ -39,14 +62,14 @@ def log(*a):
 
 
 # Algorithmic HBM bytes of one enumeration launch, from the kernel's own counters:
-#   4 B per adjacency entry scanned to build bitmap rows (and 8 B of row pointers
-#     per universe vertex, folded into the 4 B/entry term's companion below),
-#   4 B per P/X id staged from the oriented CSR for a root, plus 4 B to write it,
-#   12 B per X_X adjacency test (the X_X id, and the two row pointers of x),
+#   4 B per adjacency entry scanned to build bitmap rows,
+#   8 B per P/X id staged from the oriented CSR for a root (read + write),
+#   12 B per X_X adjacency test on the index list (the id and two row pointers),
+#   8 B per X-column word read for a bitmap X_X,
 #   4 B per list entry probed by the binary searches of those tests.
 def algorithmic_bytes(stats) -> int:
     return (4 * stats["build_edges"] + 8 * stats["root_words"] + 12 * stats["xtests"]
-            + 4 * stats["probes"])
+            + 8 * stats["xcol_words"] + 4 * stats["probes"])
 
 
 def measured_traffic(workload: str, c: int):
@@ -65,7 +88,7 @@ def measured_traffic(workload: str, c: int):
     return None
 
 
-def cpu_baseline(g, c, frac_mod: int, budget_s: float):
+def cpu_baseline_graph(g, c, frac_mod: int):
     """The oracle as it stands, on a deterministic sample of roots (input ids
     v with v % frac_mod == 0), all host threads it is given."""
     import oracle
@@ -79,15 +102,34 @@ def cpu_baseline(g, c, frac_mod: int, budget_s: float):
                       f"{r.count} cliques in {dt:.2f} s", "seconds": round(dt, 3)}
 
 
+def cpu_baseline_batch(batch, every: int):
+    """The oracle on every `every`-th graph of the batch."""
+    import oracle
+
+    idx = list(range(0, len(batch), every))
+    t0 = time.perf_counter()
+    count, threads = 0, 1
+    for i in idx:
+        r = oracle.mce(batch.graph(i))
+        count += r.count
+        threads = r.threads
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "cliques/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"graphs with index % {every} == 0 ({len(idx)} of {len(batch)}); {count} cliques in "
+                      f"{dt:.2f} s", "seconds": round(dt, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=sorted(WORKLOADS))
+    ap.add_argument("--form", default=None, choices=["plain", "learned", "batched", "sequential"])
+    ap.add_argument("--compare", default=None,
+                    help="comma-separated forms also timed in this run, at equal results ('' for none)")
     ap.add_argument("--window", type=int, default=None, help="override the core window c")
     ap.add_argument("--no-worker-list", action="store_true")
-    ap.add_argument("--reverse", action="store_true", help="process roots in reverse degeneracy order")
     ap.add_argument("--bitmap-max-p", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--donate-min-p", type=int, default=0)
@@ -112,13 +154,12 @@ def main():
     torch.cuda.set_device(0)
     mce.load_library()
     spec = WORKLOADS[args.workload]
+    form = args.form or spec["form"]
+    compare = [f for f in (spec["compare"] if args.compare is None else args.compare).split(",") if f and f != form]
     c = spec["c"] if args.window is None else args.window
-    t0 = time.perf_counter()
-    g = I.workload(args.workload)
-    log(f"[bench] workload {args.workload}: n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
-    rp = torch.from_numpy(g.row_ptr.astype(np.int64)).to(torch.int32).cuda()
-    ci = torch.from_numpy(g.col_idx.astype(np.int64)).to(torch.int32).cuda()
-    torch.cuda.synchronize()
+    knobs = dict(worker_list=not args.no_worker_list, bitmap_max_p=args.bitmap_max_p, wg_per_cu=args.wg_per_cu,
+                 donate_min_p=args.donate_min_p, timeout_ms=600000)
+
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -127,70 +168,145 @@ def main():
         del src, dst
         log("[bench] calibration kernel: 1 GiB read + 1 GiB written")
 
-    flags = 0
-    if args.reverse:
-        flags |= mce.F_REVERSE_ORDER
-
-    def step():
-        dg = mce.load_csr(rp, ci, g.n)
-        info = dg.info()
-        r = mce.enumerate_cliques(dg, max_root_core=c, worker_list=not args.no_worker_list, flags=flags,
-                                  bitmap_max_p=args.bitmap_max_p, wg_per_cu=args.wg_per_cu,
-                                  donate_min_p=args.donate_min_p, timeout_ms=300000,
-                                  hist_len=info.degeneracy + 2)
-        dg.free()
-        return r, info
-
-    for i in range(args.warmup):
-        r, info = step()
-        log(f"[bench] warmup {i}: count={r.count} kernel={r.stats['kernel_ns'] / 1e6:.1f}ms")
-    torch.cuda.synchronize()
-    results = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        r, info = step()
-        results.append(r)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for i, r in enumerate(results):
-        log(f"[bench] step {i}: count={r.count} hash={r.hash:#018x} kernel={r.stats['kernel_ns'] / 1e6:.2f}ms "
-            f"nodes={r.stats['nodes']} donations={r.stats['donations']}")
-    counts = {(r.count, r.hash) for r in results}
-    assert len(counts) == 1, f"results differ between steps: {counts}"
-    r = results[-1]
-    ms = elapsed * 1e3 / args.steps
-    kern_ms = sum(x.stats["kernel_ns"] for x in results) / len(results) / 1e6
-    alg = algorithmic_bytes(r.stats)
+    steps = {}  # form -> callable returning (results, stats of the launch)
+    if spec["kind"] == "graph":
+        g = I.workload(args.workload)
+        log(f"[bench] workload {args.workload}: n={g.n} m={g.m} ready in {time.perf_counter() - t0:.1f}s")
+        rp = torch.from_numpy(g.row_ptr.astype(np.int64)).to(torch.int32).cuda()
+        ci = torch.from_numpy(g.col_idx.astype(np.int64)).to(torch.int32).cuda()
+        model = None
+        if "learned" in [form] + compare:
+            from paper_2212_01473_amd import learned
+
+            t1 = time.perf_counter()
+            model = learned.cached_model()
+            log(f"[bench] cost model ready in {time.perf_counter() - t1:.1f}s")
+
+        def graph_step(extra):
+            def step():
+                dg = mce.load_csr(rp, ci, g.n)
+                info = dg.info()
+                r = mce.enumerate_cliques(dg, max_root_core=c, hist_len=info.degeneracy + 2, **knobs, **extra)
+                dg.free()
+                return [r], r.stats, info
+            return step
+
+        steps["plain"] = graph_step({})
+        if model is not None:
+            steps["learned"] = graph_step(dict(model=model, split=True))
+        units = g.n
+    else:
+        batch = I.workload_batch(args.workload)
+        log(f"[bench] workload {args.workload}: {len(batch)} graphs, {int(batch.row_off[-1]) - len(batch)} "
+            f"vertices, {batch.col_idx_cat.size // 2} edges, ready in {time.perf_counter() - t0:.1f}s")
+        rp = torch.from_numpy(batch.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
+        ci = torch.from_numpy(batch.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
+        # knobs tuned on a held-out batch, outside the timed region
+        t1 = time.perf_counter()
+        tb = I.workload_batch("batch512_tune")
+        trp = torch.from_numpy(tb.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
+        tci = torch.from_numpy(tb.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
+        with mce.load_batch_device(trp, tci, tb.row_off, tb.col_off) as tg:
+            tuned, rep = mce.autotune(tg, **knobs)
+        log(f"[bench] autotuned on the held-out batch in {time.perf_counter() - t1:.1f}s: {rep}")
+        del trp, tci
+
+        def batched():
+            dg = mce.load_batch_device(rp, ci, batch.row_off, batch.col_off)
+            res = mce.enumerate_batch(dg, options=tuned)
+            dg.free()
+            return res, res[0].stats, None
+
+        def sequential():
+            res, stats = [], None
+            for i in range(len(batch)):
+                a, b = int(batch.row_off[i]), int(batch.row_off[i + 1])
+                cc, d = int(batch.col_off[i]), int(batch.col_off[i + 1])
+                dg = mce.load_csr(rp[a:b], ci[cc:d] if d > cc else ci[:1], b - a - 1)
+                r = mce.enumerate_cliques(dg, **knobs)
+                dg.free()
+                res.append(r)
+                stats = r.stats
+            return res, stats, None
+
+        steps["batched"] = batched
+        steps["sequential"] = sequential
+        units = len(batch)
+    for f in [form] + compare:
+        if f not in steps:
+            raise SystemExit(f"form {f} does not apply to workload {args.workload}")
+
+    def timed(f, nsteps, nwarm):
+        for i in range(nwarm):
+            res, st, _ = steps[f]()
+            log(f"[bench] {f} warmup {i}: count={sum(r.count for r in res)} kernel={st['kernel_ns'] / 1e6:.1f}ms")
+        torch.cuda.synchronize()
+        out = []
+        t0 = time.perf_counter()
+        for i in range(nsteps):
+            out.append(steps[f]())
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        keys = {tuple((r.count, r.hash) for r in res) for res, _, _ in out}
+        assert len(keys) == 1, f"{f}: results differ between steps"
+        return out, el / nsteps
+
+    runs, sec = timed(form, args.steps, args.warmup)
+    res, st, info = runs[-1]
+    key = tuple((r.count, r.hash, tuple(r.hist.tolist())) for r in res)
+    count = sum(r.count for r in res)
+    for i, (rr, s, _) in enumerate(runs):
+        log(f"[bench] {form} step {i}: count={sum(r.count for r in rr)} kernel={s['kernel_ns'] / 1e6:.2f}ms "
+            f"setup={s['setup_ns'] / 1e6:.2f}ms nodes={s['nodes']} donations={s['donations']}")
+    comp = {}
+    for f in compare:
+        cr, csec = timed(f, max(1, args.steps if f != "sequential" else 1), args.warmup if f != "sequential" else 0)
+        ckey = tuple((r.count, r.hash, tuple(r.hist.tolist())) for r in cr[-1][0])
+        assert ckey == key, f"form {f} changed the results"
+        comp[f] = {"ms_per_step": round(csec * 1e3, 3), "value": count / csec,
+                   "kernel_ms": round(cr[-1][1]["kernel_ns"] / 1e6, 3),
+                   "setup_ms": round(cr[-1][1]["setup_ns"] / 1e6, 3), "speedup_of_reported_form": round(csec / sec, 3)}
+        log(f"[bench] {f}: {csec * 1e3:.1f} ms/step (reported form {form}: {sec * 1e3:.1f})")
+
+    kern_ms = sum(s["kernel_ns"] for _, s, _ in runs) / len(runs) / 1e6
+    alg = algorithmic_bytes(st)
     achieved = alg / (kern_ms / 1e3) / 1e9
     peak = 8000.0
+    cfg = {"workload": spec["desc"] if args.window is None else f"{args.workload} c={c}", "form": form,
+           "count": count, "units": units}
+    if info is not None:
+        cfg.update({"n": int(info.n), "degeneracy": int(info.degeneracy), "max_degree": int(info.max_degree),
+                    "core_window": c if c != FULL else "full", "hash": f"{res[0].hash:#018x}",
+                    "max_clique": res[0].max_size})
+    cfg.update({"workgroups": st["workgroups"], "tree_nodes": st["nodes"], "donations": st["donations"],
+                "kernel_ms": round(kern_ms, 3), "setup_ms": round(st["setup_ns"] / 1e6, 3)})
     out = {
         "metric": "maximal cliques/sec (wall time per step in ms_per_step)",
-        "value": r.count / (ms / 1e3),
+        "value": count / sec,
         "unit": "cliques/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": sec * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32/u64 (exact integer)",
         "data": "synthetic (seeded generator)",
-        "config": {"workload": spec["desc"] if args.window is None else f"{args.workload} c={c}",
-                   "form": "plain worker list" if not args.no_worker_list else "plain, no worker list",
-                   "n": g.n, "edges": g.m, "degeneracy": int(info.degeneracy),
-                   "max_degree": int(info.max_degree), "core_window": c if c != 0xFFFFFFFF else "full",
-                   "count": r.count, "hash": f"{r.hash:#018x}", "max_clique": r.max_size,
-                   "workgroups": r.stats["workgroups"], "tree_nodes": r.stats["nodes"],
-                   "donations": r.stats["donations"]},
+        "config": cfg,
+        "compare": comp,
         "roofline": {"bound": "hbm", "kernel": "k_enumerate", "achieved": round(achieved, 2),
                      "peak": peak, "unit": "GB/s", "frac": round(achieved / peak, 5),
-                     "traffic": measured_traffic(args.workload, c),
+                     "traffic": measured_traffic(args.workload, c) if spec["kind"] == "graph" else None,
                      "algorithmic_bytes": alg, "avg_kernel_ms": round(kern_ms, 3)},
     }
     if args.cpu_baseline == "on":
-        log("[bench] timing the CPU oracle on a root sample")
-        out["cpu_baseline"] = cpu_baseline(g, c, args.cpu_sample_mod, 30.0)
+        log("[bench] timing the CPU oracle on a sample")
+        if spec["kind"] == "graph":
+            out["cpu_baseline"] = cpu_baseline_graph(g, c, args.cpu_sample_mod)
+        else:
+            out["cpu_baseline"] = cpu_baseline_batch(batch, 64)
     print(json.dumps(out), flush=True)
 
 

@@ -102,7 +102,9 @@ mce_status mce_load_csr(const uint32_t* row_ptr, const uint32_t* col_idx, uint32
  * length n_graphs + 1, host memory) give where graph i starts in each array,
  * so n_i = row_off[i+1] - row_off[i] - 1 and nnz_i = col_off[i+1] - col_off[i].
  * Every graph obeys the rules of mce_load_csr.  Vertex ids in results are
- * per-graph input ids.  Same flags, ownership and stream rules.
+ * per-graph input ids.  Same flags, ownership and stream rules; with
+ * MCE_LOAD_DEVICE_PTRS the two concatenated arrays are device pointers (the
+ * offsets stay in host memory) and the per-graph end checks run on the device.
  */
 mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_idx_cat,
                               const uint64_t* row_off, const uint64_t* col_off,
@@ -143,10 +145,16 @@ typedef struct {
     uint32_t max_root_core;     /* core window c; UINT32_MAX = full enumeration */
     uint32_t wg_per_cu;         /* persistent workgroups per compute unit; 0 = occupancy limit */
     uint32_t bitmap_max_p;      /* largest subtree universe whose bitmap rows live in LDS;
-                                   larger ones use HBM rows; 0 = default */
-    uint32_t donate_min_p;      /* donate a branch only if its |P| >= this; 0 = 10 (Section III-C) */
+                                   larger ones use HBM rows; 0 = 128 (smaller LDS per
+                                   workgroup, more resident workgroups) */
+    uint32_t donate_min_p;      /* donate a branch only if its |P| >= this; 0 = 32 (Section III-C
+                                   uses 10; a donated branch here is rebuilt from the CSR by
+                                   its receiver, so smaller ones cost more than they save) */
     uint32_t donate_max_depth;  /* donate only at depth <= this; 0 = unlimited */
-    uint32_t split_top;         /* MCE_F_SPLIT: number of costliest roots to split; 0 = auto */
+    uint32_t split_top;         /* MCE_F_SPLIT: the costliest roots by predicted rank, each split
+                                   into 64 groups if predicted at least 4x the mean cost;
+                                   0 = workgroups / 32.  Any root predicted above 1/(4 x
+                                   workgroups) of the total is split in proportion too. */
     const void* model;          /* MCE_F_LEARNED_ORDER: device pointer to mce_model weights */
     void* stream;               /* hipStream_t or NULL */
     uint64_t timeout_ms;        /* watchdog; 0 = 600000 */
@@ -192,7 +200,8 @@ enum {
     MCE_STAT_BUILD_NS = 17,    /* summed bitmap-construction time over workgroups (ns) */
     MCE_STAT_TASK_LOG = 18,    /* tasks that qualified for the task log (may exceed its capacity) */
     MCE_STAT_DONATE_NS = 19,   /* summed time spent offering branches to the worker list (ns) */
-    MCE_STAT_POP_FAILS = 20    /* offers that found no idle workgroup */
+    MCE_STAT_POP_FAILS = 20,   /* offers that found no idle workgroup */
+    MCE_STAT_XCOL_WORDS = 21   /* X-column words read for bitmap X_X children */
 };
 
 typedef struct {
@@ -278,6 +287,27 @@ mce_status mce_model_train(float* model, const float* feat, const float* target,
  * zero for mean/std) of the mean squared error, and the loss (host). */
 mce_status mce_model_loss_grad(const float* model, const float* feat, const float* target, uint32_t n,
                                float* grad, float* loss, void* stream);
+
+/*
+ * Autotuner for the performance knobs (none of them changes the result):
+ * coordinate descent over donate_min_p, bitmap_max_p, wg_per_cu,
+ * donate_max_depth and xrow_ratio, timing setup + kernel with device events on
+ * this handle (single graph or batch).  base: the options to start from
+ * (MCE_F_STREAM, MCE_F_ROOT_STATS and MCE_F_TASK_LOG are rejected); tuned:
+ * receives base with the best knob values.  Every trial must reproduce the
+ * base run's count, hash and histogram for every graph, else MCE_ERR_DEVICE.
+ * report may be NULL; its struct_size must be set when given.
+ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(mce_tune_report) */
+    uint32_t passes;      /* in: coordinate-descent passes; 0 = 1 */
+    uint32_t repeats;     /* in: timed runs per setting (the minimum counts); 0 = 1 */
+    uint32_t trials;      /* out: enumerations run */
+    double base_ms;       /* out: time with the base options */
+    double best_ms;       /* out: time with the tuned options */
+} mce_tune_report;
+
+mce_status mce_autotune(mce_graph* g, const mce_options* base, mce_options* tuned, mce_tune_report* report);
 
 /* Release a handle (NULL is a no-op). */
 void mce_free(mce_graph* g);

@@ -3,6 +3,7 @@
 // enumeration; every step of the computation runs in this library's kernels.
 #include "mce_internal.h"
 
+#include <algorithm>
 #include <memory>
 #include <string>
 #include <vector>
@@ -94,7 +95,7 @@ mce_status config_from(const mce_options* opt, EnumConfig& cfg)
     cfg.max_root_core = opt->max_root_core;
     cfg.wg_per_cu = opt->wg_per_cu;
     cfg.bitmap_max_p = opt->bitmap_max_p;
-    cfg.donate_min_p = opt->donate_min_p ? opt->donate_min_p : 10u;
+    cfg.donate_min_p = opt->donate_min_p ? opt->donate_min_p : kDefaultDonateMinP;
     cfg.donate_max_depth = opt->donate_max_depth;
     cfg.timeout_ms = opt->timeout_ms ? opt->timeout_ms : 600000ull;
     cfg.root_order = opt->root_order;
@@ -165,8 +166,7 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
     *out = nullptr;
     if (!row_ptr_cat || !row_off || !col_off) return fail(MCE_ERR_INVALID_ARG, "NULL batch array");
     if (n_graphs == 0) return fail(MCE_ERR_INVALID_ARG, "n_graphs is 0");
-    if (flags & MCE_LOAD_DEVICE_PTRS) return fail(MCE_ERR_INVALID_ARG, "batch loading takes host arrays");
-    if (flags & ~(MCE_LOAD_NO_VALIDATE)) return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
+    if (flags & ~(MCE_LOAD_DEVICE_PTRS | MCE_LOAD_NO_VALIDATE)) return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
     for (uint32_t i = 0; i < n_graphs; ++i) {
         if (row_off[i + 1] <= row_off[i] || col_off[i + 1] < col_off[i])
             return fail(MCE_ERR_INVALID_ARG, "batch offsets not increasing at graph " + std::to_string(i));
@@ -177,7 +177,8 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
     g->batch = true;
     g->graphs.emplace_back(new Oriented());
     mce_status st = preprocess_batch(row_ptr_cat, col_idx_cat, row_off, col_off, n_graphs,
-                                     (flags & MCE_LOAD_NO_VALIDATE) == 0, s, *g->graphs[0]);
+                                     (flags & MCE_LOAD_NO_VALIDATE) == 0, (flags & MCE_LOAD_DEVICE_PTRS) != 0, s,
+                                     *g->graphs[0]);
     if (st != MCE_OK) return st;
     *out = g.release();
     return MCE_OK;
@@ -337,3 +338,102 @@ const char* mce_last_error(void) { return get_error(); }
 const char* mce_version(void) { return "mce-mi355x 0.1 (gfx950)"; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+// Coordinate descent over the performance knobs: each knob in turn takes the
+// candidate value with the shortest measured time (setup + kernel, device
+// events) while the others stay fixed.  Every trial must reproduce the base
+// run's count, hash and histogram; candidates slower than 3x the best time so
+// far are cut off by the watchdog.
+mce_status mce_autotune(mce_graph* g, const mce_options* base, mce_options* tuned, mce_tune_report* report)
+{
+    set_error("");
+    if (!g || !base || !tuned) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    if (report && report->struct_size != sizeof(mce_tune_report))
+        return fail(MCE_ERR_INVALID_ARG, "mce_tune_report.struct_size must be sizeof(mce_tune_report)");
+    if (base->flags & (MCE_F_STREAM | MCE_F_ROOT_STATS | MCE_F_TASK_LOG))
+        return fail(MCE_ERR_INVALID_ARG, "autotune: stream, per-root statistics and task log are not tuned");
+    const uint32_t passes = report && report->passes ? report->passes : 1u;
+    const uint32_t repeats = report && report->repeats ? report->repeats : 1u;
+    const Oriented& o = *g->graphs[0];
+    hipStream_t s = reinterpret_cast<hipStream_t>(base->stream);
+
+    mce_options cur = *base;
+    uint32_t trials = 0;
+    EnumOutput ref;
+    bool have_ref = false;
+    // time of one option set (minimum over repeats); +inf if cut off
+    auto measure = [&](const mce_options& opt, double cutoff_ms, double* ms) -> mce_status {
+        EnumConfig cfg;
+        mce_status st = config_from(&opt, cfg);
+        if (st != MCE_OK) return st;
+        cfg.flags |= MCE_F_STATS;
+        if (cutoff_ms > 0) cfg.timeout_ms = std::max<uint64_t>(1000, (uint64_t)(3.0 * cutoff_ms) + 1);
+        double best = 1e300;
+        for (uint32_t r = 0; r < repeats; ++r) {
+            EnumOutput eo;
+            st = enumerate_graph(o, cfg, g->state, s, eo);
+            ++trials;
+            if (st == MCE_ERR_TIMEOUT) {
+                *ms = 1e300;
+                return MCE_OK;
+            }
+            if (st != MCE_OK) return st;
+            if (!have_ref) {
+                ref = eo;
+                have_ref = true;
+            } else {
+                for (size_t gi = 0; gi < ref.graphs.size(); ++gi) {
+                    const auto& a = ref.graphs[gi];
+                    const auto& b = eo.graphs[gi];
+                    if (a.count != b.count || a.hash != b.hash || a.hist != b.hist)
+                        return fail(MCE_ERR_DEVICE, "autotune: a knob setting changed the result of graph " +
+                                                        std::to_string(gi));
+                }
+            }
+            best = std::min(best, (eo.stats[MCE_STAT_KERNEL_NS] + eo.stats[MCE_STAT_SETUP_NS]) / 1e6);
+        }
+        *ms = best;
+        return MCE_OK;
+    };
+
+    double best_ms = 0;
+    mce_status st = measure(cur, 0, &best_ms);
+    if (st != MCE_OK) return st;
+    const double base_ms = best_ms;
+
+    struct Knob {
+        uint32_t mce_options::*field;
+        std::vector<uint32_t> values;
+    };
+    const std::vector<Knob> knobs = {
+        {&mce_options::donate_min_p, {12, 20, 32, 48}},
+        {&mce_options::bitmap_max_p, {64, 128, 256}},
+        {&mce_options::wg_per_cu, {0, 4, 2}},
+        {&mce_options::donate_max_depth, {0, 3}},
+        {&mce_options::xrow_ratio, {2, 8, 32}},
+    };
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+        for (const Knob& k : knobs) {
+            uint32_t keep = cur.*k.field;
+            for (uint32_t v : k.values) {
+                if (v == keep) continue;
+                mce_options cand = cur;
+                cand.*k.field = v;
+                double ms = 0;
+                if ((st = measure(cand, best_ms, &ms)) != MCE_OK) return st;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    cur.*k.field = v;
+                }
+            }
+        }
+    }
+    *tuned = cur;
+    if (report) {
+        report->trials = trials;
+        report->base_ms = base_ms;
+        report->best_ms = best_ms;
+    }
+    return MCE_OK;
+}

@@ -195,7 +195,7 @@ __device__ inline uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ul
 // Statistics counters kept in LDS (updated by lane 0) to spare scalar registers.
 enum : int {
     S_NODES = 0, S_DONATIONS, S_TASKS, S_XTESTS, S_EDGES, S_HBM, S_IDLE, S_ROOTW, S_XROW, S_BUSY, S_MAXTASK,
-    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_DONATE, S_POPFAIL, S_COUNT
+    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_DONATE, S_POPFAIL, S_XCOLW, S_COUNT
 };
 
 // Fixed-size LDS of a workgroup (static offsets: no pointer registers).
@@ -929,7 +929,7 @@ loop:
         uint32_t Lc;
         if (xb) {
             Lc = wave_sum((uint32_t)__popcll(XXc));
-            stat_add(S_XTESTS, Wx);
+            stat_add(S_XCOLW, Wx);
         } else {
             Lc = xx_partition(p, w, L, bb, vb);
         }
@@ -1466,6 +1466,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         atomicAdd(&p.acc[2 + MCE_STAT_BUILD_TICKS], (unsigned long long)S.stat[S_BUILD]);
         atomicAdd(&p.acc[2 + MCE_STAT_DONATE_NS], (unsigned long long)S.stat[S_DONATE]);
         atomicAdd(&p.acc[2 + MCE_STAT_POP_FAILS], (unsigned long long)S.stat[S_POPFAIL]);
+        atomicAdd(&p.acc[2 + MCE_STAT_XCOL_WORDS], (unsigned long long)S.stat[S_XCOLW]);
     }
 }
 
@@ -1613,7 +1614,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint32_t ws_g = wg_words | 1u;
 
     // LDS budget for bitmap rows (universes up to 64 always fit)
-    uint32_t lds_cap = cfg.bitmap_max_p ? cfg.bitmap_max_p : 256u;
+    uint32_t lds_cap = cfg.bitmap_max_p ? cfg.bitmap_max_p : kDefaultBitmapMaxP;
     lds_cap = std::max(64u, std::min(lds_cap, std::max(ucap, 64u)));
     const uint32_t ws_l = lds_cap <= 64 ? 1u : (((lds_cap + 63) / 64) | 1u);
     size_t lds_bytes = 0;                                      // dynamic part (static LdsFixed comes first)
@@ -1756,7 +1757,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.xcap = xcap;
     p.rcap = rcap;
     p.flags = cfg.flags;
-    p.donate_min_p = cfg.donate_min_p ? cfg.donate_min_p : 10u;
+    p.donate_min_p = cfg.donate_min_p ? cfg.donate_min_p : kDefaultDonateMinP;
     p.donate_max_depth = cfg.donate_max_depth;
     p.donate_every = cfg.donate_every ? cfg.donate_every : 1u;
     p.nwg = G;

@@ -36,8 +36,10 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 // Per root v (rank): log1p(degree), log1p(core), log1p(2-hop count = sum of
 // neighbour degrees), and the edge density of its later-neighbour set P
 // (edges inside P / C(|P|, 2); 0 when |P| < 2).  One wave per root; P is
-// staged in LDS (|P| <= 4095) and every later list of a P vertex is searched
-// in it.
+// staged in LDS (cap entries per wave, cap > the largest |P|); the later
+// lists of all P vertices are scanned as one concatenated sequence (lanes
+// take consecutive entries, so loads are independent) and each entry is
+// searched in P.
 constexpr int kFeatWaves = 4;
 constexpr int kFeatCap = 4096;
 
@@ -47,12 +49,13 @@ __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __
                                                              const uint32_t* __restrict__ ic,
                                                              const uint32_t* __restrict__ core_r,
                                                              const uint32_t* __restrict__ roots, uint32_t nr,
-                                                             float* __restrict__ feat)
+                                                             uint32_t cap, float* __restrict__ feat)
 {
-    __shared__ uint32_t buf[kFeatWaves][kFeatCap];
+    extern __shared__ uint32_t fbuf[];
+    __shared__ uint32_t soff[kFeatWaves][64], sbeg[kFeatWaves][64];
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x >> 6;
-    uint32_t* P = buf[wv];
+    uint32_t* P = fbuf + (size_t)wv * cap;
     for (size_t k = (size_t)blockIdx.x * kFeatWaves + wv; k < nr; k += (size_t)gridDim.x * kFeatWaves) {
         uint32_t v = roots[k];
         uint32_t pb = op[v], np = op[v + 1] - pb;
@@ -63,30 +66,54 @@ __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __
             uint32_t u = i < np ? oc[pb + i] : ic[xb + i - np];
             two += (uint64_t)(op[u + 1] - op[u]) + (ip[u + 1] - ip[u]);
         }
-        // density of P
+        // edges inside P: for each P vertex u (position a), its later
+        // neighbours found in P (they sit after a, since P is ascending)
         uint64_t tri = 0;
         if (np >= 2) {
             for (uint32_t i = lane; i < np; i += 64) P[i] = oc[pb + i];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
             const uint32_t pmax = P[np - 1];
-            for (uint32_t a = 0; a < np; ++a) {
-                uint32_t u = P[a];
-                uint32_t ub = op[u], ue = op[u + 1];
-                for (uint32_t e = ub + lane; e < ue; e += 64) {
-                    uint32_t x = oc[e];
+            for (uint32_t a0 = 0; a0 < np; a0 += 64) {
+                uint32_t a = a0 + lane, beg = 0, len = 0;
+                if (a < np) {
+                    uint32_t u = P[a];
+                    beg = op[u];
+                    len = op[u + 1] - beg;
+                }
+                // exclusive prefix of len over the wave
+                uint32_t off = len;
+                for (int d = 1; d < 64; d <<= 1) {
+                    uint32_t y = (uint32_t)__shfl_up((int)off, d, 64);
+                    if ((int)lane >= d) off += y;
+                }
+                uint32_t total = (uint32_t)__shfl((int)off, 63, 64);
+                off -= len;
+                soff[wv][lane] = off;
+                sbeg[wv][lane] = beg;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t nrows = min(64u, np - a0);
+                for (uint32_t f = lane; f < total; f += 64) {
+                    uint32_t lo = 0, hi = nrows;  // last row with soff <= f
+                    while (hi - lo > 1) {
+                        uint32_t mid = (lo + hi) >> 1;
+                        if (soff[wv][mid] <= f) lo = mid;
+                        else hi = mid;
+                    }
+                    uint32_t x = oc[sbeg[wv][lo] + (f - soff[wv][lo])];
                     if (x <= pmax) {
-                        uint32_t lo = a + 1, hi = np;
-                        while (lo < hi) {
-                            uint32_t mid = (lo + hi) >> 1;
-                            if (P[mid] < x) lo = mid + 1;
-                            else hi = mid;
+                        uint32_t l2 = a0 + lo + 1, h2 = np;
+                        while (l2 < h2) {
+                            uint32_t mid = (l2 + h2) >> 1;
+                            if (P[mid] < x) l2 = mid + 1;
+                            else h2 = mid;
                         }
-                        tri += lo < np && P[lo] == x;
+                        tri += l2 < np && P[l2] == x;
                     }
                 }
+                __builtin_amdgcn_wave_barrier();
             }
-            __builtin_amdgcn_wave_barrier();
         }
         for (int off = 32; off > 0; off >>= 1) {
             two += __shfl_xor(two, off, 64);
@@ -99,6 +126,7 @@ __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __
             f[2] = log1pf((float)two);
             f[3] = np >= 2 ? (float)((double)tri / (0.5 * (double)np * (double)(np - 1))) : 0.f;
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -371,18 +399,21 @@ __global__ void k_score_keys(const float* __restrict__ score, uint32_t n, uint32
     }
 }
 
-// Number of groups each queued root is split into: predicted nodes divided by
-// the target task size, capped; only the first split_top roots of the order.
-__global__ void k_split_counts(const float* __restrict__ score_sorted, uint32_t n, uint32_t split_top,
-                               float target, uint32_t* __restrict__ groups)
+// Number of groups each queued root (in descending predicted cost) is split
+// into.  The model ranks roots well but its scale is unreliable outside its
+// training range, so two rules combine: the first `top` roots get kMaxSplit
+// groups when predicted at least `floor_nodes`, and every root gets predicted
+// nodes / target groups, capped.
+constexpr uint32_t kMaxSplit = 64;
+
+__global__ void k_split_counts(const float* __restrict__ score_sorted, uint32_t n, uint32_t top,
+                               float floor_nodes, float target, uint32_t* __restrict__ groups)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        uint32_t c = 1;
-        if (i < split_top) {
-            float nodes = expm1f(fminf(fmaxf(score_sorted[i], 0.f), 40.f));
-            float g = ceilf(nodes / target);
-            c = (uint32_t)fminf(fmaxf(g, 1.f), 64.f);
-        }
+        float nodes = expm1f(fminf(fmaxf(score_sorted[i], 0.f), 40.f));
+        float g = fminf(fmaxf(ceilf(nodes / target), 1.f), (float)kMaxSplit);
+        uint32_t c = (uint32_t)g;
+        if (i < top && nodes >= floor_nodes) c = kMaxSplit;
         groups[i] = c;
     }
 }
@@ -417,9 +448,10 @@ mce_status root_features(const Oriented& g, const uint32_t* roots_rank, uint32_t
         set_error("first-level P too large for the feature kernel");
         return MCE_ERR_UNSUPPORTED;
     }
-    k_features<<<blocks_for(nr, kFeatWaves, 65536), 64 * kFeatWaves, 0, s>>>(
+    const uint32_t cap = (g.max_out + 4) & ~3u;  // > max |P|
+    k_features<<<blocks_for(nr, kFeatWaves, 65536), 64 * kFeatWaves, (size_t)kFeatWaves * cap * 4, s>>>(
         g.op.as<uint32_t>(), g.oc.as<uint32_t>(), g.ip.as<uint32_t>(), g.ic.as<uint32_t>(), g.core_r.as<uint32_t>(),
-        roots_rank, nr, feat);
+        roots_rank, nr, cap, feat);
     MCE_HIP_TRY(hipGetLastError());
     return MCE_OK;
 }
@@ -605,20 +637,22 @@ mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st
         MCE_HIP_TRY(hipStreamSynchronize(s));
         return MCE_OK;
     }
-    // split: total predicted nodes spread over `grid` workgroups, 4 tasks each
+    // split: the costliest roots by rank, and any root predicted above the
+    // target task size (total predicted nodes over 4 tasks per workgroup)
     std::vector<float> sc(nn);
     MCE_HIP_TRY(hipMemcpyAsync(sc.data(), q.score_sorted.p, nn * 4, hipMemcpyDeviceToHost, s));
     MCE_HIP_TRY(hipStreamSynchronize(s));
     double total = 0;
     for (float x : sc) total += std::expm1((double)std::min(std::max(x, 0.f), 40.f));
     float target = (float)std::max(64.0, total / (4.0 * std::max(grid, 1u)));
-    uint32_t top = cfg.split_top ? std::min(cfg.split_top, nroots) : nroots;
+    uint32_t top = cfg.split_top ? std::min(cfg.split_top, nroots) : std::max(1u, grid / 32);
+    float floor_nodes = (float)std::max(64.0, 4.0 * total / (double)nroots);
     if ((rc = q.groups.alloc((nn + 1) * 4)) != MCE_OK) return rc;
     if ((rc = q.pos.alloc((nn + 1) * 4)) != MCE_OK) return rc;
     if ((rc = q.scan_tmp.alloc(scan_tmp_words(nn + 1) * 8 + 64)) != MCE_OK) return rc;
     if ((rc = q.total.alloc(8)) != MCE_OK) return rc;
-    k_split_counts<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score_sorted.as<float>(), nroots, top, target,
-                                                             q.groups.as<uint32_t>());
+    k_split_counts<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score_sorted.as<float>(), nroots, top,
+                                                             floor_nodes, target, q.groups.as<uint32_t>());
     MCE_HIP_TRY(hipGetLastError());
     if ((rc = exclusive_scan_u32(q.groups.as<uint32_t>(), q.pos.as<uint32_t>(), nn, q.total.as<uint32_t>(),
                                  q.scan_tmp.as<uint64_t>(), s)) != MCE_OK)

@@ -121,16 +121,20 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
 
 // Build the union CSR of a batch on the device (host inputs) and preprocess it.
 mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, const uint64_t* row_off,
-                            const uint64_t* col_off, uint32_t n_graphs, bool validate, hipStream_t s,
+                            const uint64_t* col_off, uint32_t ng, bool validate, bool on_dev, hipStream_t s,
                             Oriented& g);
 
 // Enumeration (enumerate.hip) ----------------------------------------------------------
+// Default knobs (measured on gfx950; see the options in mce.h)
+constexpr uint32_t kDefaultDonateMinP = 32;
+constexpr uint32_t kDefaultBitmapMaxP = 128;
+
 struct EnumConfig {
     uint32_t flags = MCE_F_WORKER_LIST;
     uint32_t max_root_core = 0xFFFFFFFFu;
     uint32_t wg_per_cu = 0;
     uint32_t bitmap_max_p = 0;
-    uint32_t donate_min_p = 10;
+    uint32_t donate_min_p = kDefaultDonateMinP;
     uint32_t donate_max_depth = 0;
     uint32_t donate_every = 1;
     uint32_t task_log_min_us = 0;

@@ -13,6 +13,7 @@ namespace mce {
 namespace {
 
 constexpr uint32_t kUnset = 0xFFFFFFFFu;
+constexpr int kPeelSteps = 16;  // peel steps per graph launch
 
 unsigned blocks_for(size_t items, unsigned per_block, unsigned cap = 65536)
 {
@@ -90,11 +91,24 @@ __global__ void k_validate_cols(const uint32_t* __restrict__ rp, const uint32_t*
 }
 
 // ---- peel ----------------------------------------------------------------------
-struct PeelCtl {
-    uint32_t n_front;   // size of the frontier being built
-    uint32_t n_alive;   // size of the alive list being built
-    uint32_t min_deg;
-    uint32_t pad;
+// Synchronous-round peel (Section III-B), driven from device memory: every step
+// reads its counts from PeelState, so a fixed sequence of launches (captured
+// once in a hipGraph) runs any number of rounds; a step after the last round
+// does nothing.  One step: a new level when the frontier ran empty (minimum
+// remaining degree k, then every remaining vertex of degree <= k), then one
+// round of removals, then the bookkeeping.
+struct PeelState {
+    uint32_t k;            // current level
+    uint32_t r;            // round number of the current frontier
+    uint32_t n_alive;      // unselected vertices listed in alive[pa] (some may be removed since)
+    uint32_t n_alive_next; // entries written to alive[pa ^ 1] by the level selection
+    uint32_t n_cur;        // frontier size, in front[pf]
+    uint32_t n_next;       // next frontier being written to front[pf ^ 1]
+    uint32_t min_deg;      // minimum remaining degree (level selection)
+    uint32_t need_level;   // the frontier ran empty: select a new level first
+    uint32_t pa, pf;       // buffer parities
+    uint32_t done, err;
+    unsigned long long removed;
 };
 
 __global__ void k_peel_init(const uint32_t* __restrict__ rp, uint32_t n, uint32_t* __restrict__ deg,
@@ -121,28 +135,37 @@ __global__ void k_peel_init(const uint32_t* __restrict__ rp, uint32_t n, uint32_
     }
 }
 
-__global__ void k_level_min(const uint32_t* __restrict__ alive, uint32_t n_alive,
-                            const uint32_t* __restrict__ deg, const uint32_t* __restrict__ round,
-                            PeelCtl* ctl)
+struct PeelBufs {
+    uint32_t* alive[2];
+    uint32_t* front[2];
+};
+
+__global__ void k_pd_level_min(PeelBufs b, const uint32_t* __restrict__ deg, const uint32_t* __restrict__ round,
+                               PeelState* ps)
 {
+    if (ps->done || !ps->need_level) return;
+    const uint32_t n_alive = ps->n_alive;
+    const uint32_t* A = b.alive[ps->pa];
     uint32_t m = kUnset;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_alive;
          i += (size_t)gridDim.x * blockDim.x) {
-        uint32_t v = alive[i];
+        uint32_t v = A[i];
         if (round[v] == kUnset) m = min(m, deg[v]);
     }
     for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
-    if (lane_id() == 0 && m != kUnset) atomicMin(&ctl->min_deg, m);
+    if (lane_id() == 0 && m != kUnset) atomicMin(&ps->min_deg, m);
 }
 
-// Select the level's first frontier: every unremoved vertex of degree <= k.
-// Unselected unremoved vertices are compacted into alive_out.
-__global__ void k_level_select(const uint32_t* __restrict__ alive, uint32_t n_alive,
-                               const uint32_t* __restrict__ deg, uint32_t* __restrict__ round,
-                               uint32_t* __restrict__ core, uint32_t k, uint32_t r,
-                               uint32_t* __restrict__ front, uint32_t* __restrict__ alive_out,
-                               PeelCtl* ctl)
+// The level's first frontier: every remaining vertex of degree <= k (round r,
+// core k); the others are compacted into the other alive buffer.
+__global__ void k_pd_level_select(PeelBufs b, const uint32_t* __restrict__ deg, uint32_t* __restrict__ round,
+                                  uint32_t* __restrict__ core, PeelState* ps)
 {
+    if (ps->done || !ps->need_level) return;
+    const uint32_t n_alive = ps->n_alive, k = max(ps->k, ps->min_deg), r = ps->r;
+    const uint32_t* A = b.alive[ps->pa];
+    uint32_t* A2 = b.alive[ps->pa ^ 1u];
+    uint32_t* F = b.front[ps->pf];
     const uint32_t lane = lane_id();
     for (size_t base = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n_alive;
          base += (size_t)gridDim.x * blockDim.x) {
@@ -150,7 +173,7 @@ __global__ void k_level_select(const uint32_t* __restrict__ alive, uint32_t n_al
         uint32_t v = 0;
         bool sel = false, keep = false;
         if (i < n_alive) {
-            v = alive[i];
+            v = A[i];
             if (round[v] == kUnset) {
                 if (deg[v] <= k) sel = true;
                 else keep = true;
@@ -159,32 +182,37 @@ __global__ void k_level_select(const uint32_t* __restrict__ alive, uint32_t n_al
         uint64_t ms = __ballot(sel), mk = __ballot(keep);
         uint32_t bs = 0, bk = 0;
         if (lane == 0) {
-            if (ms) bs = atomicAdd(&ctl->n_front, (uint32_t)__popcll(ms));
-            if (mk) bk = atomicAdd(&ctl->n_alive, (uint32_t)__popcll(mk));
+            if (ms) bs = atomicAdd(&ps->n_cur, (uint32_t)__popcll(ms));
+            if (mk) bk = atomicAdd(&ps->n_alive_next, (uint32_t)__popcll(mk));
         }
         bs = __shfl(bs, 0);
         bk = __shfl(bk, 0);
         if (sel) {
             round[v] = r;
             core[v] = k;
-            front[bs + prefix_popc(ms)] = v;
+            F[bs + prefix_popc(ms)] = v;
         }
-        if (keep) alive_out[bk + prefix_popc(mk)] = v;
+        if (keep) A2[bk + prefix_popc(mk)] = v;
     }
 }
 
 // Remove the frontier: decrement remaining neighbours; a neighbour whose degree
 // falls from k+1 to k joins the next round.  One wave per frontier vertex.
-__global__ void k_peel_decrement(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
-                                 const uint32_t* __restrict__ front, uint32_t n_front,
-                                 uint32_t* __restrict__ deg, uint32_t* __restrict__ round,
-                                 uint32_t* __restrict__ core, uint32_t k, uint32_t r_next,
-                                 uint32_t* __restrict__ front_next, PeelCtl* ctl)
+__global__ void k_pd_decrement(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, PeelBufs b,
+                               uint32_t* __restrict__ deg, uint32_t* __restrict__ round, uint32_t* __restrict__ core,
+                               PeelState* ps)
 {
+    if (ps->done) return;
+    const uint32_t n_front = ps->n_cur;
+    if (n_front == 0) return;
+    const uint32_t k = ps->need_level ? max(ps->k, ps->min_deg) : ps->k;
+    const uint32_t r_next = ps->r + 1;
+    const uint32_t* F = b.front[ps->pf];
+    uint32_t* F2 = b.front[ps->pf ^ 1u];
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
     for (size_t f = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); f < n_front; f += waves) {
-        uint32_t v = front[f];
+        uint32_t v = F[f];
         uint32_t beg = rp[v], end = rp[v + 1];
         for (uint32_t e0 = beg; e0 < end; e0 += 64) {
             uint32_t e = e0 + lane;
@@ -202,11 +230,40 @@ __global__ void k_peel_decrement(const uint32_t* __restrict__ rp, const uint32_t
                 }
             }
             uint64_t m = __ballot(joined);
-            uint32_t b = 0;
-            if (lane == 0 && m) b = atomicAdd(&ctl->n_front, (uint32_t)__popcll(m));
-            b = __shfl(b, 0);
-            if (joined) front_next[b + prefix_popc(m)] = u;
+            uint32_t bo = 0;
+            if (lane == 0 && m) bo = atomicAdd(&ps->n_next, (uint32_t)__popcll(m));
+            bo = __shfl(bo, 0);
+            if (joined) F2[bo + prefix_popc(m)] = u;
         }
+    }
+}
+
+// Bookkeeping after a step (one thread): adopt the level, count the removed
+// frontier, advance the round, swap frontiers, and decide what comes next.
+__global__ void k_pd_advance(PeelState* ps, uint32_t n)
+{
+    if (threadIdx.x != 0 || ps->done) return;
+    if (ps->need_level) {
+        if (ps->min_deg == kUnset || ps->n_cur == 0) {
+            ps->err = 1;
+            ps->done = 1;
+            return;
+        }
+        ps->k = max(ps->k, ps->min_deg);
+        ps->pa ^= 1u;
+        ps->n_alive = ps->n_alive_next;
+        ps->n_alive_next = 0;
+        ps->need_level = 0;
+        ps->min_deg = kUnset;
+    }
+    ps->removed += ps->n_cur;
+    ps->r += 1;
+    ps->pf ^= 1u;
+    ps->n_cur = ps->n_next;
+    ps->n_next = 0;
+    if (ps->n_cur == 0) {
+        if (ps->removed >= n) ps->done = 1;
+        else ps->need_level = 1;
     }
 }
 
@@ -251,6 +308,18 @@ __global__ void k_graph_meta(const uint32_t* __restrict__ op, const uint32_t* __
     }
 }
 
+// Batch graph i must have row_ptr[0] == 0 and row_ptr[n_i] == nnz_i; the
+// smallest offending graph index goes to *err (initially all ones).
+__global__ void k_batch_ends(const uint32_t* __restrict__ rp_cat, const uint64_t* __restrict__ row_off,
+                             const uint64_t* __restrict__ col_off, uint32_t ng, unsigned long long* err)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ng; i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t first = row_off[i], last = row_off[i + 1] - 1;
+        if (rp_cat[first] != 0u || (uint64_t)rp_cat[last] != col_off[i + 1] - col_off[i])
+            atomicMin(err, (unsigned long long)i);
+    }
+}
+
 // Union CSR of a batch: row pointers shifted by each graph's first arc, column
 // ids by each graph's first vertex; a column outside its own graph is an error.
 __global__ void k_union_rows(const uint32_t* __restrict__ rp_cat, const uint64_t* __restrict__ row_off,
@@ -291,19 +360,24 @@ __global__ void k_orient_count(const uint32_t* __restrict__ rp, const uint32_t* 
 {
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    uint32_t max_out = 0, max_in = 0;  // this wave's, one atomic each at the end
     for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
         uint32_t rv = rank[v];
         uint32_t beg = rp[v], end = rp[v + 1];
         uint32_t cnt = 0;
         for (uint32_t e = beg + lane; e < end; e += 64) cnt += rank[ci[e]] > rv;
         for (int off = 32; off > 0; off >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, off);
+        uint32_t in = (end - beg) - cnt;
         if (lane == 0) {
-            uint32_t in = (end - beg) - cnt;
             outdeg[rv] = cnt;
             indeg[rv] = in;
-            atomicMax(&maxes[0], cnt);
-            atomicMax(&maxes[1], in);
         }
+        max_out = max(max_out, cnt);
+        max_in = max(max_in, in);
+    }
+    if (lane == 0 && (max_out | max_in)) {
+        atomicMax(&maxes[0], max_out);
+        atomicMax(&maxes[1], max_in);
     }
 }
 
@@ -417,7 +491,7 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     }
 
     // ---- peel
-    DevBuf deg, alive_a, alive_b, front_a, front_b, ctlb;
+    DevBuf deg, alive_a, alive_b, front_a, front_b, psb;
     size_t nn = n ? n : 1;
     if ((st = deg.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = alive_a.alloc(nn * 4)) != MCE_OK) return st;
@@ -426,14 +500,20 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     if ((st = front_b.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = g.core.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = g.round.alloc(nn * 4)) != MCE_OK) return st;
-    if ((st = ctlb.alloc(sizeof(PeelCtl))) != MCE_OK) return st;
-    PeelCtl* ctl = ctlb.as<PeelCtl>();
+    if ((st = psb.alloc(sizeof(PeelState))) != MCE_OK) return st;
+    PeelState* ps = psb.as<PeelState>();
     uint32_t* dcore = g.core.as<uint32_t>();
     uint32_t* dround = g.round.as<uint32_t>();
 
     {
         uint64_t z[4] = {0, 0, 0, 0};
         MCE_HIP_TRY(hipMemcpyAsync(dmisc, z, 32, hipMemcpyHostToDevice, s));
+        PeelState p0{};
+        p0.n_alive = n;
+        p0.min_deg = kUnset;
+        p0.need_level = n ? 1u : 0u;
+        p0.done = n ? 0u : 1u;
+        MCE_HIP_TRY(hipMemcpyAsync(ps, &p0, sizeof(p0), hipMemcpyHostToDevice, s));
     }
     if (n) {
         k_peel_init<<<blocks_for(n, 256, 4096), 256, 0, s>>>(rp, n, deg.as<uint32_t>(), dround,
@@ -445,51 +525,59 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     g.max_degree = (uint32_t)hmisc[0];
     g.n_isolated = hmisc[1];
 
-    uint32_t* A = alive_a.as<uint32_t>();
-    uint32_t* A2 = alive_b.as<uint32_t>();
-    uint32_t* F = front_a.as<uint32_t>();
-    uint32_t* F2 = front_b.as<uint32_t>();
-    uint32_t nA = n, k = 0, r = 0;
-    uint64_t removed = 0;
-    uint32_t degen = 0;
-    while (removed < n) {
-        PeelCtl c0 = {0, 0, kUnset, 0};
-        MCE_HIP_TRY(hipMemcpyAsync(ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
-        k_level_min<<<blocks_for(nA, 256, 4096), 256, 0, s>>>(A, nA, deg.as<uint32_t>(), dround, ctl);
-        MCE_HIP_TRY(hipGetLastError());
-        PeelCtl c1;
-        MCE_HIP_TRY(hipMemcpyAsync(&c1, ctl, sizeof(c1), hipMemcpyDeviceToHost, s));
-        MCE_HIP_TRY(hipStreamSynchronize(s));
-        if (c1.min_deg == kUnset) {
+    PeelState hs{};
+    if (n) {
+        // kPeelSteps steps captured once, replayed until the peel is done
+        PeelBufs pb;
+        pb.alive[0] = alive_a.as<uint32_t>();
+        pb.alive[1] = alive_b.as<uint32_t>();
+        pb.front[0] = front_a.as<uint32_t>();
+        pb.front[1] = front_b.as<uint32_t>();
+        const unsigned gsel = blocks_for(n, 256, 1024), gdec = blocks_for(n, 4, 2048);
+        hipStream_t cs = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        auto cleanup = [&]() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (cs) (void)hipStreamDestroy(cs);
+        };
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int i = 0; i < kPeelSteps; ++i) {
+                k_pd_level_min<<<gsel, 256, 0, cs>>>(pb, deg.as<uint32_t>(), dround, ps);
+                k_pd_level_select<<<gsel, 256, 0, cs>>>(pb, deg.as<uint32_t>(), dround, dcore, ps);
+                k_pd_decrement<<<gdec, 256, 0, cs>>>(rp, ci, pb, deg.as<uint32_t>(), dround, dcore, ps);
+                k_pd_advance<<<1, 64, 0, cs>>>(ps, n);
+            }
+            hipError_t e2 = hipStreamEndCapture(cs, &graph);
+            e = e2 != hipSuccess ? e2 : hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            cleanup();
+            set_error(std::string("peel graph capture: ") + hipGetErrorString(e));
+            return MCE_ERR_DEVICE;
+        }
+        while (true) {
+            e = hipGraphLaunch(exec, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(&hs, ps, sizeof(hs), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess || hs.done) break;
+        }
+        cleanup();
+        if (e != hipSuccess) {
+            set_error(std::string("peel: ") + hipGetErrorString(e));
+            return MCE_ERR_DEVICE;
+        }
+        if (hs.err) {
             set_error("internal: peel found no remaining vertex");
             return MCE_ERR_DEVICE;
         }
-        k = std::max(k, c1.min_deg);
-        degen = k;
-        k_level_select<<<blocks_for(nA, 256, 4096), 256, 0, s>>>(A, nA, deg.as<uint32_t>(), dround, dcore,
-                                                                  k, r, F, A2, ctl);
-        MCE_HIP_TRY(hipGetLastError());
-        MCE_HIP_TRY(hipMemcpyAsync(&c1, ctl, sizeof(c1), hipMemcpyDeviceToHost, s));
-        MCE_HIP_TRY(hipStreamSynchronize(s));
-        uint32_t nF = c1.n_front;
-        std::swap(A, A2);
-        nA = c1.n_alive;
-        while (true) {
-            removed += nF;
-            uint32_t zero = 0;
-            MCE_HIP_TRY(hipMemcpyAsync(&ctl->n_front, &zero, 4, hipMemcpyHostToDevice, s));
-            k_peel_decrement<<<blocks_for(nF, 4, 16384), 256, 0, s>>>(rp, ci, F, nF, deg.as<uint32_t>(), dround,
-                                                                      dcore, k, r + 1, F2, ctl);
-            MCE_HIP_TRY(hipGetLastError());
-            uint32_t nF2 = 0;
-            MCE_HIP_TRY(hipMemcpyAsync(&nF2, &ctl->n_front, 4, hipMemcpyDeviceToHost, s));
-            MCE_HIP_TRY(hipStreamSynchronize(s));
-            r++;
-            if (nF2 == 0) break;
-            std::swap(F, F2);
-            nF = nF2;
-        }
     }
+    const uint32_t r = hs.r;
+    const uint32_t degen = hs.k;
     g.rounds = r;
     g.degeneracy = degen;
     alive_a.release();
@@ -625,7 +713,8 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
 }
 
 mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, const uint64_t* row_off,
-                            const uint64_t* col_off, uint32_t ng, bool validate, hipStream_t s, Oriented& g)
+                            const uint64_t* col_off, uint32_t ng, bool validate, bool on_dev, hipStream_t s,
+                            Oriented& g)
 {
     mce_status st;
     std::vector<uint32_t> voff(ng + 1), nloc(ng);
@@ -634,7 +723,7 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
         uint64_t ni = row_off[i + 1] - row_off[i] - 1;
         voff[i] = (uint32_t)N;
         nloc[i] = (uint32_t)ni;
-        if (validate) {
+        if (validate && !on_dev) {
             uint64_t nnzi = col_off[i + 1] - col_off[i];
             if (rp_cat[row_off[i]] != 0 || (uint64_t)rp_cat[row_off[i] + ni] != nnzi) {
                 set_error("invalid graph " + std::to_string(i) + ": row_ptr[0] != 0 or row_ptr[n] != nnz");
@@ -653,8 +742,10 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
         std::fill(gid_in.begin() + voff[i], gid_in.begin() + voff[i + 1], i);
     DevBuf d_rp, d_ci, d_roff, d_coff, d_voff, d_nloc, d_gid, urp, uci, err;
     size_t rp_words = row_off[ng] - row_off[0];
-    if ((st = d_rp.alloc(rp_words * 4)) != MCE_OK) return st;
-    if ((st = d_ci.alloc((NNZ ? NNZ : 1) * 4)) != MCE_OK) return st;
+    if (!on_dev) {
+        if ((st = d_rp.alloc(rp_words * 4)) != MCE_OK) return st;
+        if ((st = d_ci.alloc((NNZ ? NNZ : 1) * 4)) != MCE_OK) return st;
+    }
     if ((st = d_roff.alloc((size_t)(ng + 1) * 8)) != MCE_OK) return st;
     if ((st = d_coff.alloc((size_t)(ng + 1) * 8)) != MCE_OK) return st;
     if ((st = d_voff.alloc((size_t)(ng + 1) * 4)) != MCE_OK) return st;
@@ -668,8 +759,12 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
         roff[i] = row_off[i] - row_off[0];
         coff[i] = col_off[i] - col_off[0];
     }
-    MCE_HIP_TRY(hipMemcpyAsync(d_rp.p, rp_cat + row_off[0], rp_words * 4, hipMemcpyHostToDevice, s));
-    if (NNZ) MCE_HIP_TRY(hipMemcpyAsync(d_ci.p, ci_cat + col_off[0], NNZ * 4, hipMemcpyHostToDevice, s));
+    const uint32_t* src_rp = on_dev ? rp_cat + row_off[0] : d_rp.as<uint32_t>();
+    const uint32_t* src_ci = on_dev ? (NNZ ? ci_cat + col_off[0] : nullptr) : d_ci.as<uint32_t>();
+    if (!on_dev) {
+        MCE_HIP_TRY(hipMemcpyAsync(d_rp.p, rp_cat + row_off[0], rp_words * 4, hipMemcpyHostToDevice, s));
+        if (NNZ) MCE_HIP_TRY(hipMemcpyAsync(d_ci.p, ci_cat + col_off[0], NNZ * 4, hipMemcpyHostToDevice, s));
+    }
     MCE_HIP_TRY(hipMemcpyAsync(d_roff.p, roff.data(), (ng + 1) * 8, hipMemcpyHostToDevice, s));
     MCE_HIP_TRY(hipMemcpyAsync(d_coff.p, coff.data(), (ng + 1) * 8, hipMemcpyHostToDevice, s));
     MCE_HIP_TRY(hipMemcpyAsync(d_voff.p, voff.data(), (ng + 1) * 4, hipMemcpyHostToDevice, s));
@@ -679,8 +774,21 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
     MCE_HIP_TRY(hipMemcpyAsync(err.p, &einit, 8, hipMemcpyHostToDevice, s));
     uint32_t nnz32 = (uint32_t)NNZ;
     MCE_HIP_TRY(hipMemcpyAsync(urp.as<uint32_t>() + N, &nnz32, 4, hipMemcpyHostToDevice, s));
+    if (validate && on_dev) {
+        // per graph: row_ptr[0] == 0 and row_ptr[n] == nnz, checked where the arrays live
+        k_batch_ends<<<blocks_for(ng, 256, 4096), 256, 0, s>>>(src_rp, d_roff.as<uint64_t>(), d_coff.as<uint64_t>(),
+                                                               ng, err.as<unsigned long long>());
+        MCE_HIP_TRY(hipGetLastError());
+        uint64_t berr = 0;
+        MCE_HIP_TRY(hipMemcpyAsync(&berr, err.p, 8, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        if (berr != ~0ull) {
+            set_error("invalid graph " + std::to_string((uint32_t)berr) + ": row_ptr[0] != 0 or row_ptr[n] != nnz");
+            return MCE_ERR_INVALID_GRAPH;
+        }
+    }
     if (N) {
-        k_union_rows<<<blocks_for(N, 256, 8192), 256, 0, s>>>(d_rp.as<uint32_t>(), d_roff.as<uint64_t>(),
+        k_union_rows<<<blocks_for(N, 256, 8192), 256, 0, s>>>(src_rp, d_roff.as<uint64_t>(),
                                                               d_coff.as<uint64_t>(), d_voff.as<uint32_t>(),
                                                               d_gid.as<uint32_t>(), (uint32_t)N, urp.as<uint32_t>());
         MCE_HIP_TRY(hipGetLastError());
@@ -700,7 +808,7 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
                 return MCE_ERR_INVALID_GRAPH;
             }
         }
-        k_union_cols<<<blocks_for(N, 4, 16384), 256, 0, s>>>(d_ci.as<uint32_t>(), urp.as<uint32_t>(),
+        k_union_cols<<<blocks_for(N, 4, 16384), 256, 0, s>>>(src_ci, urp.as<uint32_t>(),
                                                              d_gid.as<uint32_t>(), d_voff.as<uint32_t>(),
                                                              d_nloc.as<uint32_t>(), (uint32_t)N, uci.as<uint32_t>(),
                                                              err.as<unsigned long long>());

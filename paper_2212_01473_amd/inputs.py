@@ -422,3 +422,45 @@ def workload(name: str) -> CSRGraph:
     if name == "rmat22":
         return _cached(name, lambda: rmat(22, 32, 0.57, 0.19, 0.19, 0.05, 5))
     raise KeyError(name)
+
+
+@dataclass
+class Batch:
+    """Concatenated CSRs of a batch (the layout of concat_batch)."""
+
+    row_ptr_cat: np.ndarray
+    col_idx_cat: np.ndarray
+    row_off: np.ndarray
+    col_off: np.ndarray
+
+    def __len__(self) -> int:
+        return len(self.row_off) - 1
+
+    def graph(self, i: int) -> CSRGraph:
+        a, b = int(self.row_off[i]), int(self.row_off[i + 1])
+        c, d = int(self.col_off[i]), int(self.col_off[i + 1])
+        return CSRGraph(n=b - a - 1, row_ptr=self.row_ptr_cat[a:b], col_idx=self.col_idx_cat[c:d])
+
+
+def workload_batch(name: str, count: int = 4096, seed: int = 4) -> Batch:
+    """Batched workloads, cached like the single graphs: "batch4096" (seed 4)
+    and its held-out tuning batch "batch512_tune" (seed 104, 512 graphs)."""
+    if name == "batch4096":
+        count, seed = 4096, 4
+    elif name == "batch512_tune":
+        count, seed = 512, 104
+    else:
+        raise KeyError(name)
+    path = os.path.join(cache_dir(), name + ".npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        return Batch(z["rp"], z["ci"], z["row_off"], z["col_off"])
+    rp, ci, row_off, col_off = concat_batch(batch_graphs(count, seed))
+    try:
+        os.makedirs(cache_dir(), exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}.npz"
+        np.savez(tmp, rp=rp, ci=ci, row_off=row_off, col_off=col_off)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return Batch(rp, ci, row_off, col_off)

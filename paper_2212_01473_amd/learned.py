@@ -81,11 +81,13 @@ def train(feat, label, epochs: int = 400, lr: float = 3e-3, seed: int = 0):
 
 
 TRAIN_GRAPHS = [
-    # (scale, edge factor, seed, window) -- R-MAT graphs with the workloads'
-    # quadrant probabilities; the windows stop below each graph's densest shell
-    (16, 16, 6, 150),
-    (17, 16, 7, 180),
-    (16, 32, 8, 200),
+    # (scale, edge factor, seed, window as a fraction of the degeneracy):
+    # R-MAT graphs with the workloads' quadrant probabilities and seeds other
+    # than those of the measured workloads; the windows stop below each graph's
+    # densest shell, where one plain run takes a few seconds at most
+    (18, 16, 6, 0.7),
+    (18, 32, 7, 0.7),
+    (18, 16, 8, 0.7),
 ]
 
 
@@ -93,8 +95,10 @@ def default_training_set(graphs=TRAIN_GRAPHS):
     import torch
 
     feats, labels = [], []
-    for scale, ef, seed, c in graphs:
+    for scale, ef, seed, frac in graphs:
         g = I.rmat(scale, ef, 0.57, 0.19, 0.19, 0.05, seed)
+        with mce.load_graph(g) as dg:
+            c = int(frac * dg.info().degeneracy)
         f, l = collect(g, c)
         feats.append(f)
         labels.append(l)
@@ -117,7 +121,7 @@ def load(path: str):
 
 def cached_model(path: str | None = None, epochs: int = 400):
     """Load the trained model, training (and storing) it first when absent."""
-    path = path or os.path.join(I.cache_dir(), "mce_cost_model.npy")
+    path = path or os.path.join(I.cache_dir(), "mce_cost_model_r18.npy")
     if os.path.exists(path):
         return load(path)
     feat, label = default_training_set()

@@ -43,13 +43,13 @@ F_TASK_LOG = 0x100
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
               "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words",
               "busy_ns", "max_task_ns", "xrow_tasks", "build_ns", "task_log", "donate_ns",
-              "pop_fails"]
+              "pop_fails", "xcol_words"]
 
 FULL = 0xFFFFFFFF
 
 EXPORTED = ["mce_load_csr", "mce_load_csr_batch", "mce_graph_get_info", "mce_graph_copy_order", "mce_enumerate",
             "mce_enumerate_batch", "mce_free", "mce_status_string", "mce_last_error", "mce_version",
-            "mce_root_features", "mce_model_predict", "mce_model_train", "mce_model_loss_grad"]
+            "mce_root_features", "mce_model_predict", "mce_model_train", "mce_model_loss_grad", "mce_autotune"]
 
 MODEL_FLOATS = 8713
 
@@ -89,6 +89,11 @@ class Result(C.Structure):
                 ("stream_offsets", C.c_void_p), ("stream_ocap", C.c_uint64),
                 ("stream_vertices_written", C.c_uint64), ("stream_cliques_written", C.c_uint64),
                 ("stats", C.c_uint64 * 24)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("passes", C.c_uint32), ("repeats", C.c_uint32),
+                ("trials", C.c_uint32), ("base_ms", C.c_double), ("best_ms", C.c_double)]
 
 
 def load_library(path: str | None = None):
@@ -133,6 +138,8 @@ def load_library(path: str | None = None):
     lib.mce_model_loss_grad.restype = C.c_int
     lib.mce_model_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                         C.POINTER(C.c_float), C.c_void_p]
+    lib.mce_autotune.restype = C.c_int
+    lib.mce_autotune.argtypes = [C.c_void_p, C.POINTER(Options), C.POINTER(Options), C.POINTER(TuneReport)]
     _lib = lib
     return lib
 
@@ -250,6 +257,7 @@ def load_graph(g, validate: bool = True) -> Graph:
 
 
 def load_batch(graphs, validate: bool = True) -> Graph:
+    """mce_load_csr_batch from host arrays (a list of CSRGraph)."""
     from .inputs import concat_batch
 
     lib = load_library()
@@ -261,6 +269,23 @@ def load_batch(graphs, validate: bool = True) -> Graph:
     st = lib.mce_load_csr_batch(C.c_void_p(rp.ctypes.data), C.c_void_p(ci.ctypes.data),
                                 C.c_void_p(row_off.ctypes.data), C.c_void_p(col_off.ctypes.data),
                                 len(graphs), flags, _torch_stream(), C.byref(h))
+    _check(st, "mce_load_csr_batch")
+    return Graph(h)
+
+
+def load_batch_device(rp_cat, ci_cat, row_off, col_off, validate: bool = True) -> Graph:
+    """mce_load_csr_batch with MCE_LOAD_DEVICE_PTRS: rp_cat / ci_cat are device
+    int32 tensors (concatenated CSRs), row_off / col_off host uint64 arrays."""
+    lib = load_library()
+    row_off = np.ascontiguousarray(row_off, dtype=np.uint64)
+    col_off = np.ascontiguousarray(col_off, dtype=np.uint64)
+    if not (_is_device_tensor(rp_cat) and _is_device_tensor(ci_cat)):
+        raise TypeError("rp_cat and ci_cat must be device tensors")
+    h = C.c_void_p()
+    flags = MCE_LOAD_DEVICE_PTRS | (0 if validate else MCE_LOAD_NO_VALIDATE)
+    st = lib.mce_load_csr_batch(C.c_void_p(rp_cat.data_ptr()), C.c_void_p(ci_cat.data_ptr()),
+                                C.c_void_p(row_off.ctypes.data), C.c_void_p(col_off.ctypes.data),
+                                len(row_off) - 1, flags, _torch_stream(), C.byref(h))
     _check(st, "mce_load_csr_batch")
     return Graph(h)
 
@@ -355,6 +380,21 @@ def enumerate_batch(g: Graph, options: Options | None = None, **kw):
     st = lib.mce_enumerate_batch(g.handle, C.byref(opt), results, ng)
     _check(st, "mce_enumerate_batch")
     return [_to_result(results[i], hists[i], st) for i in range(ng)]
+
+
+def autotune(g: Graph, passes: int = 1, repeats: int = 1, options: Options | None = None, **kw):
+    """mce_autotune on a single-graph or batch handle: (tuned Options, report dict)."""
+    lib = load_library()
+    base = options if options is not None else make_options(**kw)
+    tuned = Options()
+    rep = TuneReport()
+    rep.struct_size = C.sizeof(TuneReport)
+    rep.passes = passes
+    rep.repeats = repeats
+    _check(lib.mce_autotune(g.handle, C.byref(base), C.byref(tuned), C.byref(rep)), "mce_autotune")
+    knobs = {k: int(getattr(tuned, k)) for k in ("donate_min_p", "bitmap_max_p", "wg_per_cu", "donate_max_depth",
+                                                  "xrow_ratio")}
+    return tuned, dict(trials=int(rep.trials), base_ms=float(rep.base_ms), best_ms=float(rep.best_ms), **knobs)
 
 
 def version() -> str:

@@ -122,11 +122,17 @@ def test_learned_order_keeps_results(gpu_lib, split):
                   0xFFFFFFFF)):
         exp = oracle.mce(g, max_root_core=c)
         with gpu_lib.load_graph(g) as dg:
+            plain_roots = gpu_lib.enumerate_cliques(dg, max_root_core=c).stats["roots"]
             for m in (model, rand):
                 r = gpu_lib.enumerate_cliques(dg, max_root_core=c, model=m, split=split, timeout_ms=60000)
                 assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
                 if split:
                     assert r.stats["tasks"] >= r.stats["roots"]
+                    if m is model:
+                        # the costliest roots by rank are split into 64 groups each
+                        assert r.stats["roots"] >= plain_roots + 63
+                else:
+                    assert r.stats["roots"] == plain_roots
 
 
 def test_split_every_root_keeps_results(gpu_lib):

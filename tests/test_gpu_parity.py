@@ -131,6 +131,7 @@ def test_chung_lu_planted_small(gpu_lib):
     dict(bitmap_max_p=64),
     dict(bitmap_max_p=64, donate_min_p=2, wg_per_cu=2),
     dict(flags=0x40),  # reverse degeneracy order
+    dict(donate_min_p=10, bitmap_max_p=256),  # the donation size of Section III-C
 ])
 def test_knobs_invariant(gpu_lib, kw):
     g = I.chung_lu_planted(n=8000, wmax=400, n_cliques=30, cmin=15, cmax=45, pool=300, seed=11)
@@ -346,3 +347,54 @@ def test_no_x_rows_variant(gpu_lib):
     # X rows disabled: every X_X test goes to the original graph
     check(gpu_lib, I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 62), xrow_budget_words=1)
     check(gpu_lib, _dense(2), xrow_budget_words=1)
+
+
+def _device_batch(graphs):
+    import torch
+
+    rp, ci, row_off, col_off = I.concat_batch(graphs)
+    drp = torch.from_numpy(rp.astype(np.int64)).to(torch.int32).cuda()
+    dci = torch.from_numpy((ci if ci.size else np.zeros(1, np.uint32)).astype(np.int64)).to(torch.int32).cuda()
+    return drp, dci, row_off, col_off
+
+
+def test_batch_device_pointers_match_host_load(gpu_lib):
+    graphs = I.batch_graphs(count=40, seed=105, nmin=20, nmax=300)
+    graphs.insert(5, I.empty_graph(3))
+    drp, dci, row_off, col_off = _device_batch(graphs)
+    with gpu_lib.load_batch_device(drp, dci, row_off, col_off) as dg:
+        res = gpu_lib.enumerate_batch(dg)
+    for i, (g, r) in enumerate(zip(graphs, res)):
+        exp = oracle_result(g)
+        assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist)), i
+
+
+def test_batch_device_pointers_reject_bad_row_ptr(gpu_lib):
+    graphs = [I.erdos_renyi(40, 0.2, s) for s in range(4)]
+    drp, dci, row_off, col_off = _device_batch(graphs)
+    # graph 2's last row pointer no longer equals its nnz
+    drp[int(row_off[3]) - 1] -= 1
+    with pytest.raises(gpu_lib.MCEError) as e:
+        gpu_lib.load_batch_device(drp, dci, row_off, col_off)
+    assert e.value.status == gpu_lib.MCE_ERR_INVALID_GRAPH and "graph 2" in str(e.value)
+
+
+def test_autotune_keeps_results(gpu_lib):
+    g = I.chung_lu_planted(n=6000, wmax=300, n_cliques=25, cmin=15, cmax=40, pool=300, seed=21)
+    exp = oracle.mce(g)
+    with gpu_lib.load_graph(g) as dg:
+        opts, rep = gpu_lib.autotune(dg)
+        assert rep["trials"] >= 1 + 3 + 2 + 2 + 1 + 2 and 0 < rep["best_ms"] <= rep["base_ms"]
+        r = gpu_lib.enumerate_cliques(dg, options=opts)
+    assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
+
+
+def test_autotune_on_batch(gpu_lib):
+    graphs = I.batch_graphs(count=24, seed=106, nmin=30, nmax=300)
+    with gpu_lib.load_batch(graphs) as dg:
+        opts, rep = gpu_lib.autotune(dg)
+        res = gpu_lib.enumerate_batch(dg, options=opts)
+    assert rep["best_ms"] <= rep["base_ms"]
+    for i, (g, r) in enumerate(zip(graphs, res)):
+        exp = oracle_result(g)
+        assert (r.count, r.hash) == (exp.count, exp.hash), i

@@ -39,6 +39,7 @@ int main(void) {
   printf("mce_options %zu\n", sizeof(mce_options));
   printf("mce_result %zu\n", sizeof(mce_result));
   printf("mce_graph_info %zu\n", sizeof(mce_graph_info));
+  printf("mce_tune_report %zu\n", sizeof(mce_tune_report));
   F(mce_options, model); F(mce_options, stream); F(mce_options, timeout_ms); F(mce_options, root_nodes);
   F(mce_options, xrow_min_u); F(mce_options, xrow_budget_words); F(mce_options, task_log);
   F(mce_options, task_log_cap);
@@ -54,6 +55,7 @@ int main(void) {
     assert got["mce_options"] == C.sizeof(mce.Options)
     assert got["mce_result"] == C.sizeof(mce.Result)
     assert got["mce_graph_info"] == C.sizeof(mce.GraphInfo)
+    assert got["mce_tune_report"] == C.sizeof(mce.TuneReport)
     assert got["mce_options.model"] == mce.Options.model.offset
     assert got["mce_options.stream"] == mce.Options.stream.offset
     assert got["mce_options.timeout_ms"] == mce.Options.timeout_ms.offset
@@ -96,6 +98,8 @@ def test_argument_errors_without_device():
     assert lib.mce_graph_get_info(None, 0, C.byref(gi)) == mce.MCE_ERR_INVALID_ARG
     assert lib.mce_graph_copy_order(None, 0, None, None, None) == mce.MCE_ERR_INVALID_ARG
     assert lib.mce_enumerate_batch(None, None, C.byref(r), 1) == mce.MCE_ERR_INVALID_ARG
+    o = mce.Options()
+    assert lib.mce_autotune(None, C.byref(o), C.byref(o), None) == mce.MCE_ERR_INVALID_ARG
     lib.mce_free(None)
 
 
