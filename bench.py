@@ -23,6 +23,7 @@ Forms:
              costliest split into groups of level-1 branches
   batched    (batch4096) every graph in one launch, knobs autotuned beforehand
              on a held-out batch (512 graphs, seed 104)
+  batched_learned  the batched form with the learned order and split
   sequential (batch4096) one load + enumerate per graph
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -125,7 +126,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=sorted(WORKLOADS))
-    ap.add_argument("--form", default=None, choices=["plain", "learned", "batched", "sequential"])
+    ap.add_argument("--form", default=None, choices=["plain", "learned", "batched", "batched_learned", "sequential"])
     ap.add_argument("--compare", default=None,
                     help="comma-separated forms also timed in this run, at equal results ('' for none)")
     ap.add_argument("--window", type=int, default=None, help="override the core window c")
@@ -218,6 +219,21 @@ def main():
             dg.free()
             return res, res[0].stats, None
 
+        bmodel = None
+        if "batched_learned" in [form] + compare:
+            from paper_2212_01473_amd import learned
+
+            bmodel = learned.cached_model()
+
+        def batched_learned():
+            dg = mce.load_batch_device(rp, ci, batch.row_off, batch.col_off)
+            opt = mce.make_options(**knobs, model=bmodel, split=True)
+            for k in ("donate_min_p", "bitmap_max_p", "wg_per_cu", "donate_max_depth", "xrow_ratio"):
+                setattr(opt, k, getattr(tuned, k))
+            res = mce.enumerate_batch(dg, options=opt)
+            dg.free()
+            return res, res[0].stats, None
+
         def sequential():
             res, stats = [], None
             for i in range(len(batch)):
@@ -231,6 +247,7 @@ def main():
             return res, stats, None
 
         steps["batched"] = batched
+        steps["batched_learned"] = batched_learned
         steps["sequential"] = sequential
         units = len(batch)
     for f in [form] + compare:

@@ -155,38 +155,100 @@ __device__ inline uint16_t to_bf16(float f)
 }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Weights and activations rounded to BF16, sums accumulated in FP32.
+__device__ inline float bf16r(float f) { return from_bf16(to_bf16(f)); }
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline bf16x4 pack_bf16(float a, float b, float c, float d)
+{
+    bf16x4 v;
+    v[0] = (short)to_bf16(a);
+    v[1] = (short)to_bf16(b);
+    v[2] = (short)to_bf16(c);
+    v[3] = (short)to_bf16(d);
+    return v;
+}
+
+// Weights, biases and activations rounded to BF16, sums accumulated in FP32.
+// The 64x64 layers run on the matrix cores (v_mfma_f32_16x16x16_bf16) in
+// transposed form, Z^T = W . H^T: lane l = 16q + c holds, for sample c of a
+// 16-sample tile, units 16t + 4q + i (i < 4) of each 16-unit block t -- the B
+// operand of the next layer as produced by the previous one.  The 4-input
+// first layer and the 1-output last layer run on the vector ALUs.
 __global__ void __launch_bounds__(256) k_mlp_infer_bf16(const float* __restrict__ model,
                                                         const float* __restrict__ feat, uint32_t n,
                                                         float* __restrict__ out)
 {
-    __shared__ uint16_t w[kModel];
-    __shared__ float norm[2 * kIn];
-    for (int i = threadIdx.x; i < kModel; i += blockDim.x) w[i] = to_bf16(model[i]);
-    if (threadIdx.x < 2 * kIn) norm[threadIdx.x] = model[oMean + threadIdx.x];
-    __syncthreads();
-    for (size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t q = lane >> 4, c = lane & 15u;
+    // A fragments of W2 and W3 (rows 16t + c, columns 16kk + 4q .. +3), resident
+    bf16x4 w2f[4][4], w3f[4][4];
+    float b2r[16], b3r[16], w4r[16], w1r[16][kIn], b1r[16];
+    for (int t = 0; t < 4; ++t) {
+        const int row = 16 * t + (int)c;
+        for (int kk = 0; kk < 4; ++kk) {
+            const float* r2 = model + oW2 + row * kH + 16 * kk + 4 * (int)q;
+            const float* r3 = model + oW3 + row * kH + 16 * kk + 4 * (int)q;
+            w2f[t][kk] = pack_bf16(r2[0], r2[1], r2[2], r2[3]);
+            w3f[t][kk] = pack_bf16(r3[0], r3[1], r3[2], r3[3]);
+        }
+        for (int i = 0; i < 4; ++i) {
+            const int j = 16 * t + 4 * (int)q + i;  // unit held in slot 4t + i
+            b1r[4 * t + i] = bf16r(model[ob1 + j]);
+            b2r[4 * t + i] = bf16r(model[ob2 + j]);
+            b3r[4 * t + i] = bf16r(model[ob3 + j]);
+            w4r[4 * t + i] = bf16r(model[oW4 + j]);
+            for (int f = 0; f < kIn; ++f) w1r[4 * t + i][f] = bf16r(model[oW1 + j * kIn + f]);
+        }
+    }
+    float mean[kIn], sd[kIn];
+    for (int f = 0; f < kIn; ++f) {
+        mean[f] = model[oMean + f];
+        sd[f] = model[oStd + f];
+    }
+    const float b4 = bf16r(model[ob4]);
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    const size_t ntiles = ((size_t)n + 15) / 16;
+    for (size_t tile = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); tile < ntiles; tile += waves) {
+        const size_t s = tile * 16 + c;
+        const bool valid = s < n;
         float a0[kIn];
-        for (int i = 0; i < kIn; ++i)
-            a0[i] = from_bf16(to_bf16((feat[s * kIn + i] - norm[i]) / norm[kIn + i]));
-        float h1[kH], h2[kH];
-        for (int j = 0; j < kH; ++j) {
-            float acc = from_bf16(w[ob1 + j]);
-            for (int i = 0; i < kIn; ++i) acc += from_bf16(w[oW1 + j * kIn + i]) * a0[i];
-            h1[j] = from_bf16(to_bf16(fmaxf(acc, 0.f)));
+        for (int f = 0; f < kIn; ++f) a0[f] = valid ? bf16r((feat[s * kIn + f] - mean[f]) / sd[f]) : 0.f;
+        // layer 1 on the VALUs, straight into the B-operand layout
+        bf16x4 h[4];
+        for (int t = 0; t < 4; ++t) {
+            float v[4];
+            for (int i = 0; i < 4; ++i) {
+                float acc = b1r[4 * t + i];
+                for (int f = 0; f < kIn; ++f) acc += w1r[4 * t + i][f] * a0[f];
+                v[i] = fmaxf(acc, 0.f);
+            }
+            h[t] = pack_bf16(v[0], v[1], v[2], v[3]);
         }
-        for (int j = 0; j < kH; ++j) {
-            float acc = from_bf16(w[ob2 + j]);
-            for (int k = 0; k < kH; ++k) acc += from_bf16(w[oW2 + j * kH + k]) * h1[k];
-            h2[j] = from_bf16(to_bf16(fmaxf(acc, 0.f)));
+        // layers 2 and 3 on the matrix cores
+        for (int layer = 0; layer < 2; ++layer) {
+            f32x4 z[4];
+            for (int t = 0; t < 4; ++t) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int kk = 0; kk < 4; ++kk)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(layer == 0 ? w2f[t][kk] : w3f[t][kk], h[kk],
+                                                                    acc, 0, 0, 0);
+                z[t] = acc;
+            }
+            for (int t = 0; t < 4; ++t) {
+                const float* bias = layer == 0 ? b2r : b3r;
+                h[t] = pack_bf16(fmaxf(z[t][0] + bias[4 * t], 0.f), fmaxf(z[t][1] + bias[4 * t + 1], 0.f),
+                                 fmaxf(z[t][2] + bias[4 * t + 2], 0.f), fmaxf(z[t][3] + bias[4 * t + 3], 0.f));
+            }
         }
-        float y = from_bf16(w[ob4]);
-        for (int j = 0; j < kH; ++j) {
-            float acc = from_bf16(w[ob3 + j]);
-            for (int k = 0; k < kH; ++k) acc += from_bf16(w[oW3 + j * kH + k]) * h2[k];
-            y += from_bf16(w[oW4 + j]) * from_bf16(to_bf16(fmaxf(acc, 0.f)));
-        }
-        out[s] = y;
+        // layer 4: this lane's 16 units, then the four lanes of the sample
+        float y = 0.f;
+        for (int t = 0; t < 4; ++t)
+            for (int i = 0; i < 4; ++i) y += w4r[4 * t + i] * from_bf16((uint16_t)h[t][i]);
+        y += __shfl_xor(y, 16, 64);
+        y += __shfl_xor(y, 32, 64);
+        if (q == 0 && valid) out[s] = y + b4;
     }
 }
 
@@ -399,6 +461,35 @@ __global__ void k_score_keys(const float* __restrict__ score, uint32_t n, uint32
     }
 }
 
+// Total predicted tree nodes, sum of expm1(score): per-block partial sums over
+// a fixed grid, then one block adds them in order (deterministic).
+constexpr int kSumBlocks = 256;
+
+__global__ void __launch_bounds__(256) k_pred_partial(const float* __restrict__ score, uint32_t n,
+                                                      double* __restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        acc += (double)expm1f(fminf(fmaxf(score[i], 0.f), 40.f));
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_pred_total(const double* __restrict__ part, int nparts, double* __restrict__ total)
+{
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < nparts; ++i) s += part[i];
+        *total = s;
+    }
+}
+
 // Number of groups each queued root (in descending predicted cost) is split
 // into.  The model ranks roots well but its scale is unreliable outside its
 // training range, so two rules combine: the first `top` roots get kMaxSplit
@@ -483,7 +574,7 @@ mce_status ids_to_ranks(const Oriented& g, const uint32_t* ids, uint32_t n, uint
 mce_status model_predict(const float* model, const float* feat, uint32_t n, float* out, hipStream_t s)
 {
     if (!n) return MCE_OK;
-    k_mlp_infer_bf16<<<blocks_for(n, 256, 4096), 256, 0, s>>>(model, feat, n, out);
+    k_mlp_infer_bf16<<<blocks_for((n + 15) / 16, 4, 4096), 256, 0, s>>>(model, feat, n, out);
     MCE_HIP_TRY(hipGetLastError());
     return MCE_OK;
 }
@@ -639,11 +730,13 @@ mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st
     }
     // split: the costliest roots by rank, and any root predicted above the
     // target task size (total predicted nodes over 4 tasks per workgroup)
-    std::vector<float> sc(nn);
-    MCE_HIP_TRY(hipMemcpyAsync(sc.data(), q.score_sorted.p, nn * 4, hipMemcpyDeviceToHost, s));
-    MCE_HIP_TRY(hipStreamSynchronize(s));
+    if ((rc = q.psum.alloc((kSumBlocks + 1) * 8)) != MCE_OK) return rc;
+    k_pred_partial<<<kSumBlocks, 256, 0, s>>>(q.score_sorted.as<float>(), nroots, q.psum.as<double>());
+    k_pred_total<<<1, 64, 0, s>>>(q.psum.as<double>(), kSumBlocks, q.psum.as<double>() + kSumBlocks);
+    MCE_HIP_TRY(hipGetLastError());
     double total = 0;
-    for (float x : sc) total += std::expm1((double)std::min(std::max(x, 0.f), 40.f));
+    MCE_HIP_TRY(hipMemcpyAsync(&total, q.psum.as<double>() + kSumBlocks, 8, hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
     float target = (float)std::max(64.0, total / (4.0 * std::max(grid, 1u)));
     uint32_t top = cfg.split_top ? std::min(cfg.split_top, nroots) : std::max(1u, grid / 32);
     float floor_nodes = (float)std::max(64.0, 4.0 * total / (double)nroots);

@@ -179,7 +179,7 @@ struct EnumOutput {
 
 // Work queue built from the learned model.
 struct LearnedQueue {
-    DevBuf feat, score, keys, sorted, roots, score_sorted, groups, pos, scan_tmp, total, sroots, ssplits;
+    DevBuf feat, score, keys, sorted, roots, score_sorted, groups, pos, scan_tmp, total, sroots, ssplits, psum;
     const uint32_t* qroots = nullptr;
     const uint32_t* qsplits = nullptr;
     uint32_t n = 0, len = 0;
