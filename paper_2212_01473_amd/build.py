@@ -2,7 +2,9 @@
 from __future__ import annotations
 
 import glob
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -22,7 +24,24 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
+    # per-kernel register / scratch / occupancy report (parsed into RESOURCES)
+    "-Rpass-analysis=kernel-resource-usage",
 ]
+
+RESOURCES = os.path.join(HERE, "_build", "kernel_resources.json")
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|"
+                     r"SGPRs Spill|VGPRs Spill|LDS Size \[bytes/block\]):\s+(\S+)")
+
+
+def parse_resources(text: str) -> dict:
+    """Kernel name -> resource figures from the compiler's resource remarks."""
+    out, cur = {}, None
+    for key, val in _REMARK.findall(text):
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None:
+            cur[key.split(" [")[0].lower().replace(" ", "_")] = int(val) if val.isdigit() else val
+    return out
 
 
 def sources():
@@ -45,10 +64,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         if len([p for _, p in procs if p.poll() is None]) >= jobs:
             procs[0][1].wait()
     failed = []
+    resources = {}
     for src, p in procs:
         out, _ = p.communicate()
         text = out.decode(errors="replace")
-        text = "\n".join(ln for ln in text.splitlines() if "packed-fp32-ops" not in ln or "error" in ln)
+        resources.update(parse_resources(text))
+        text = "\n".join(ln for ln in text.splitlines()
+                         if ("packed-fp32-ops" not in ln and "remark" not in ln and not ln.startswith(" ")) or "error" in ln)
         if p.returncode != 0:
             failed.append((src, text))
         elif verbose and text.strip():
@@ -57,6 +79,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         for src, text in failed:
             sys.stderr.write(f"---- {src}\n{text}\n")
         raise RuntimeError("hipcc failed for " + ", ".join(os.path.basename(s) for s, _ in failed))
+    with open(RESOURCES, "w") as f:
+        json.dump(resources, f, indent=1, sort_keys=True)
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.check_call(cmd)

@@ -1472,10 +1472,12 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
 
 // ---------------------------------------------------------------- root queue
 // flag[i] = 1 if the i-th root in processing order is in the window and has P != {}.
+// A queued root's P (at most its core number of later neighbours) must fit
+// the launch's universe capacity ucap; a violation sets *err.
 __global__ void k_root_flags(const uint32_t* __restrict__ op, const uint32_t* __restrict__ core_r, uint32_t n,
                              uint32_t c, uint32_t mode, const uint32_t* __restrict__ custom,
-                             const uint32_t* __restrict__ rank, uint32_t* __restrict__ cand,
-                             uint32_t* __restrict__ flag)
+                             const uint32_t* __restrict__ rank, uint32_t ucap, uint32_t* __restrict__ cand,
+                             uint32_t* __restrict__ flag, uint32_t* __restrict__ err)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         uint32_t r;
@@ -1483,7 +1485,10 @@ __global__ void k_root_flags(const uint32_t* __restrict__ op, const uint32_t* __
         else if (mode == 2) r = rank[custom[i]];
         else r = (uint32_t)i;
         cand[i] = r;
-        flag[i] = (core_r[r] <= c && op[r + 1] > op[r]) ? 1u : 0u;
+        const uint32_t np = op[r + 1] - op[r];
+        const bool in = core_r[r] <= c && np > 0;
+        if (in && np > ucap) atomicOr(err, 1u);
+        flag[i] = in ? 1u : 0u;
     }
 }
 
@@ -1537,6 +1542,15 @@ unsigned blocks_for(size_t items, unsigned per_block, unsigned cap = 65536)
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Largest task universe of a launch.  In the synchronous-peel order a vertex
+// has at most core(v) later neighbours, and every task universe lies inside
+// its root's P, so a core window c bounds every universe by min(max
+// out-degree, c); the root queue checks each root against it.
+uint32_t universe_cap(const Oriented& g, const EnumConfig& cfg)
+{
+    return std::max(std::min(g.max_out, cfg.max_root_core), 1u);
+}
+
 }  // namespace
 
 mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s,
@@ -1577,10 +1591,12 @@ mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState&
     }
     if (n) {
         uint32_t* dtotal = st.small.as<uint32_t>();
+        fill_u32(dtotal + 1, 0, 1, s);
         k_root_flags<<<blocks_for(n, 256, 8192), 256, 0, s>>>(g.op.as<uint32_t>(), g.core_r.as<uint32_t>(), n,
                                                               cfg.max_root_core, mode, cfg.root_order,
-                                                              g.rank.as<uint32_t>(), st.tmp_a.as<uint32_t>(),
-                                                              st.tmp_c.as<uint32_t>());
+                                                              g.rank.as<uint32_t>(), universe_cap(g, cfg),
+                                                              st.tmp_a.as<uint32_t>(), st.tmp_c.as<uint32_t>(),
+                                                              dtotal + 1);
         MCE_HIP_TRY(hipGetLastError());
         if ((rc = exclusive_scan_u32(st.tmp_c.as<uint32_t>(), st.tmp_b.as<uint32_t>(), n, dtotal,
                                      st.scan_tmp.as<uint64_t>(), s)) != MCE_OK)
@@ -1588,8 +1604,14 @@ mce_status build_root_queue(const Oriented& g, const EnumConfig& cfg, EnumState&
         k_root_compact<<<blocks_for(n, 256, 8192), 256, 0, s>>>(st.tmp_a.as<uint32_t>(), st.tmp_c.as<uint32_t>(),
                                                                 st.tmp_b.as<uint32_t>(), n, st.roots.as<uint32_t>());
         MCE_HIP_TRY(hipGetLastError());
-        MCE_HIP_TRY(hipMemcpyAsync(&nroots, dtotal, 4, hipMemcpyDeviceToHost, s));
+        uint32_t hv[2] = {0, 0};
+        MCE_HIP_TRY(hipMemcpyAsync(hv, dtotal, 8, hipMemcpyDeviceToHost, s));
         MCE_HIP_TRY(hipStreamSynchronize(s));
+        nroots = hv[0];
+        if (hv[1]) {
+            set_error("internal: a root's later-neighbour list exceeds the universe capacity");
+            return MCE_ERR_DEVICE;
+        }
     }
     *nroots_out = nroots;
     return MCE_OK;
@@ -1601,7 +1623,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     mce_status rc;
     const uint32_t n = g.n;
     const uint32_t ng = std::max<uint32_t>(g.ngraphs, 1u);
-    const uint32_t ucap = std::max(g.max_out, 1u);
+    // per-workgroup LDS and scratch sized by the largest universe of this window
+    const uint32_t ucap = universe_cap(g, cfg);
     if (ucap > kMaxUniverse) {
         set_error("first-level P larger than " + std::to_string(kMaxUniverse) + " vertices is not supported");
         return MCE_ERR_UNSUPPORTED;
@@ -1686,11 +1709,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     uint32_t nroots = 0;
     const uint32_t* roots = nullptr;
     const uint32_t* splits = nullptr;
-    if (cfg.queue_roots) {
-        roots = cfg.queue_roots;
-        splits = cfg.queue_splits;
-        nroots = cfg.queue_len;
-    } else if (cfg.flags & MCE_F_LEARNED_ORDER) {
+    if (cfg.flags & MCE_F_LEARNED_ORDER) {
         if (!cfg.model) {
             set_error("MCE_F_LEARNED_ORDER without a model");
             return MCE_ERR_INVALID_ARG;

@@ -155,9 +155,6 @@ struct EnumConfig {
     const void* model = nullptr;             // MLP weights (device) for MCE_F_LEARNED_ORDER
     uint32_t split_top = 0;
     // explicit work queue (learned order / split); otherwise built from the window
-    const uint32_t* queue_roots = nullptr;
-    const uint32_t* queue_splits = nullptr;
-    uint32_t queue_len = 0;
 };
 
 struct EnumOutput {

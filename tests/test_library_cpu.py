@@ -126,3 +126,23 @@ def test_options_carry_learned_flags():
     assert not o.flags & (mce.F_LEARNED_ORDER | mce.F_SPLIT)
     with pytest.raises(ValueError):
         mce.make_options(split=True)
+
+
+def test_enumeration_kernel_resources():
+    """The build records each kernel's resources from the compiler; the DFS
+    kernel must keep 3 wavefronts per SIMD and use no scratch (a silent
+    register-allocation change costs a third of the resident workgroups)."""
+    import json
+
+    from paper_2212_01473_amd import build
+
+    if not os.path.exists(build.RESOURCES):
+        pytest.skip("library not built in this tree")
+    res = json.load(open(build.RESOURCES))
+    k = [v for name, v in res.items() if "k_enumerate" in name]
+    assert len(k) == 1
+    assert k[0]["occupancy"] >= 3 and k[0]["scratchsize"] == 0 and k[0]["vgprs_spill"] == 0, k[0]
+    for kernel in ("k_mlp_infer_bf16", "k_features", "k_pd_decrement", "scan"):
+        for name, v in res.items():
+            if kernel in name:
+                assert v["scratchsize"] == 0, name

@@ -381,3 +381,21 @@ def test_given_order_changes_attribution_not_results(seed):
     x = oracle.mce(g, order=sorder, root_mask=mask)
     y = oracle.mce(g, order=sorder, root_mask=1 - mask)
     assert x.count + y.count == b.count and (x.hash + y.hash) % 2**64 == b.hash
+
+
+@pytest.mark.parametrize("make", [lambda: I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 3),
+                                  lambda: I.chung_lu_planted(n=3000, wmax=200, n_cliques=10, cmin=10, cmax=30,
+                                                             pool=200, seed=4),
+                                  lambda: I.erdos_renyi(300, 0.1, 5), lambda: I.moon_moser(4)])
+def test_sync_order_later_neighbours_at_most_core(make):
+    """In the synchronous-peel order a vertex has at most core(v) later
+    neighbours: its remaining degree when its round starts is <= its level,
+    and every later neighbour is still present then."""
+    g = make()
+    order, rank = oracle.sync_order(g)
+    core, _, _ = oracle.sync_peel(g)
+    deg = g.degrees()
+    src = np.repeat(np.arange(g.n), deg)
+    later = rank[g.col_idx.astype(np.int64)] > rank[src]
+    outdeg = np.bincount(src[later], minlength=g.n)
+    assert (outdeg <= core).all()
