@@ -1518,16 +1518,39 @@ __global__ void k_perm_check(const uint32_t* __restrict__ seen, uint32_t n, uint
 }
 
 // Isolated vertices are maximal cliques of size 1 (Algorithm 3 with P = X = {}).
+// One graph: counts and hashes are summed across the wave first (one atomic per
+// wave); a batch adds per vertex into its own graph's accumulators.
 __global__ void k_isolated(const uint32_t* __restrict__ op, const uint32_t* __restrict__ ip,
                            const uint64_t* __restrict__ vkey, const uint32_t* __restrict__ gid, uint32_t n,
                            unsigned long long* gacc, unsigned long long* ghist, uint32_t hist_len)
 {
-    for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (size_t)gridDim.x * blockDim.x) {
-        if (op[r + 1] == op[r] && ip[r + 1] == ip[r]) {
-            uint32_t g = gid ? gid[r] : 0u;
-            atomicAdd(&gacc[2 * g], 1ull);
-            atomicAdd(&gacc[2 * g + 1], (unsigned long long)fmix64(vkey[r] + kGamma));
-            atomicAdd(&ghist[(uint64_t)g * hist_len + 1], 1ull);
+    const uint32_t lane = lane_id();
+    unsigned long long cnt = 0, hsh = 0;
+    for (size_t base = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n;
+         base += (size_t)gridDim.x * blockDim.x) {
+        const size_t r = base + lane;
+        if (r < n && op[r + 1] == op[r] && ip[r + 1] == ip[r]) {
+            const unsigned long long h = fmix64(vkey[r] + kGamma);
+            if (gid) {
+                const uint32_t g = gid[r];
+                atomicAdd(&gacc[2 * g], 1ull);
+                atomicAdd(&gacc[2 * g + 1], h);
+                atomicAdd(&ghist[(uint64_t)g * hist_len + 1], 1ull);
+            } else {
+                cnt += 1;
+                hsh += h;
+            }
+        }
+    }
+    if (!gid) {
+        for (int off = 32; off > 0; off >>= 1) {
+            cnt += __shfl_xor(cnt, off, 64);
+            hsh += __shfl_xor(hsh, off, 64);
+        }
+        if (lane == 0 && cnt) {
+            atomicAdd(&gacc[0], cnt);
+            atomicAdd(&gacc[1], hsh);
+            atomicAdd(&ghist[1], cnt);
         }
     }
 }
