@@ -204,7 +204,8 @@ struct LdsFixed {
     uint64_t lP[64], lXP[64], lB[64], lK[64];  // list executor stack while suspended (lane = level)
     uint64_t stat[S_COUNT + 4];  // + snapshots at task start: (unused), donations, build time
     uint32_t lL[64], lA[64], lR[64];
-    uint32_t frame[4];  // suspended executors: mid depth, mid split counter, list depth, list split counter
+    uint32_t frame[6];  // suspended executors: mid depth, mid split counter, list depth, list split
+                        // counter, list R offset
     uint32_t hist[kHistLds];
     uint32_t sidx[64], soff[64], sbeg[64], sxj[64];
 };
@@ -555,23 +556,30 @@ __device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root
     }
     uint64_t P = j.P, XP = j.XP, XX = low_mask(L), ks = j.ks;
     uint32_t rs = j.rs;
+    const uint32_t rs0 = j.rs;  // rs = rs0 + depth throughout
     bool anc = j.anc;
     uint32_t depth = 0;  // < m <= 64: the stack fits one lane per level
-    uint64_t B;
+    uint64_t B = 0;
     uint64_t sP = 0, sXP = 0, sXX = 0, sB = 0, sK = 0;
     uint32_t sA = 0;
-enter : {
-    ++w.nodes;
-    uint64_t cp = P | XP;
-    uint32_t key = 0;
-    if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
-    if ((XX >> lane) & 1ull) key = max(key, ((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane));
-    uint32_t best = wave_max(key);
-    uint32_t idx = 255u - (best & 255u);
-    uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
-    B = P & ~rowpiv;
-}
+    // R[rs0 + d] for d < depth lives in lane d of sV; it is written to w.R only
+    // when a donation or the clique stream needs it (no store per descent)
+    uint32_t sV = 0;
+    // one natural loop: a node's pivot step runs at the top of the iteration after a descent
+    bool at_node = true;
     while (true) {
+        if (at_node) {
+            at_node = false;
+            ++w.nodes;
+            uint64_t cp = P | XP;
+            uint32_t key = 0;
+            if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
+            if ((XX >> lane) & 1ull) key = max(key, ((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane));
+            uint32_t best = wave_max(key);
+            uint32_t idx = 255u - (best & 255u);
+            uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
+            B = P & ~rowpiv;
+        }
         if (B == 0) {
             if (depth == 0) return;
             --depth;
@@ -599,6 +607,7 @@ enter : {
             ++w.nodes;
             if ((XPc | XXc) == 0) {
                 if (p.flags & MCE_F_STREAM) {
+                    if (lane < depth) w.R[rs0 + lane] = sV;
                     if (lane == 0) w.R[rs] = vb;
                     wave_mem_sync();
                 }
@@ -614,6 +623,8 @@ enter : {
                 if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
                 if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
                 if ((XXc >> lane) & 1ull) d.xr[prefix_popc(XXc)] = xrank;
+                if (lane < depth) w.R[rs0 + lane] = sV;
+                wave_mem_sync();
                 publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), (uint32_t)__popcll(XXc));
                 continue;
             }
@@ -624,7 +635,7 @@ enter : {
         sB = wl64(sB, depth, B);
         sK = wl64(sK, depth, ks);
         sA = wl32(sA, depth, anc ? 1u : 0u);
-        if (lane == 0) w.R[rs] = vb;
+        sV = wl32(sV, depth, vb);
         anc = anc || (B != 0);
         ++depth;
         ++rs;
@@ -632,7 +643,7 @@ enter : {
         XP = XPc;
         XX = XXc;
         ks = ksc;
-        goto enter;
+        at_node = true;
     }
 }
 
@@ -654,10 +665,13 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
     uint64_t P, XP, ks, B;
     bool anc;
     // register stack (lane d = level d < m <= 64); spilled to LDS while a
-    // folded child runs
+    // folded child runs.  R[rs0 + d] for d < depth lives in lane d of sV and is
+    // written to w.R only for a donation, the clique stream or a suspension.
     uint64_t sP, sXP, sB, sK;
-    uint32_t sL, sA, sR;
-    bool pop_first = resume;  // resuming: the suspended level is popped first
+    uint32_t sL, sA, sR, sV, rs0;
+    // one natural loop: a node's pivot step runs at the top of the iteration
+    // after a descent; resuming pops the suspended level first
+    bool pop_first = resume, at_node = !resume;
     if (resume) {
         depth = S.frame[2];
         t0 = S.frame[3];
@@ -671,29 +685,33 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
         sL = S.lL[lane];
         sA = S.lA[lane];
         sR = S.lR[lane];
-        goto loop;
+        rs0 = S.frame[4];
+        sV = lane < depth ? w.R[rs0 + lane] : 0u;
+    } else {
+        sP = sXP = sB = sK = 0;
+        sL = sA = sR = sV = 0;
+        rs0 = j.rs;
+        depth = 0;
+        t0 = 0;
+        rs = j.rs;
+        L = j.L;
+        P = j.P;
+        XP = j.XP;
+        ks = j.ks;
+        anc = j.anc;
+        B = 0;
     }
-    sP = sXP = sB = sK = 0;
-    sL = sA = sR = 0;
-    depth = 0;
-    t0 = 0;
-    rs = j.rs;
-    L = j.L;
-    P = j.P;
-    XP = j.XP;
-    ks = j.ks;
-    anc = j.anc;
-enter : {
-    ++w.nodes;
-    uint64_t cp = P | XP;
-    uint32_t key = 0;
-    if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
-    uint32_t best = wave_max(key);
-    uint32_t piv = 255u - (best & 255u);
-    B = P & ~rl64(rowP, piv);
-}
-loop:
     while (true) {
+        if (at_node) {
+            at_node = false;
+            ++w.nodes;
+            uint64_t cp = P | XP;
+            uint32_t key = 0;
+            if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
+            uint32_t best = wave_max(key);
+            uint32_t piv = 255u - (best & 255u);
+            B = P & ~rl64(rowP, piv);
+        }
         if (pop_first || B == 0) {
             if (depth == 0) return kDone;
             pop_first = false;
@@ -725,6 +743,7 @@ loop:
             ++w.nodes;
             if (XPc == 0 && !xx_any(p, w, L, bidx, vb)) {
                 if (p.flags & MCE_F_STREAM) {
+                    if (lane < depth) w.R[rs0 + lane] = sV;
                     if (lane == 0) w.R[rs] = vb;
                     wave_mem_sync();
                 }
@@ -741,11 +760,13 @@ loop:
                 if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
                 if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
                 for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                if (lane < depth) w.R[rs0 + lane] = sV;
+                wave_mem_sync();
                 publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), Lc);
                 continue;
             }
         }
-        if (lane == 0) w.R[rs] = vb;
+        sV = wl32(sV, depth, vb);
         sP = wl64(sP, depth, P);
         sXP = wl64(sXP, depth, XP);
         sB = wl64(sB, depth, B);
@@ -772,9 +793,12 @@ loop:
             S.lL[lane] = sL;
             S.lA[lane] = sA;
             S.lR[lane] = sR;
+            // the folded child reads R[0, rs + 1) from memory when it donates
+            if (lane < depth) w.R[rs0 + lane] = sV;
             if (lane == 0) {
                 S.frame[2] = depth;
                 S.frame[3] = t0;
+                S.frame[4] = rs0;
             }
             wave_mem_sync();
             return kYieldFold;
@@ -785,7 +809,7 @@ loop:
         XP = XPc;
         L = Lc;
         ks = ksc;
-        goto enter;
+        at_node = true;
     }
 }
 
@@ -832,46 +856,48 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
     uint32_t depth, t0, rs, L;
     uint64_t P, XP, XX, B, ks;
     bool anc;
-    bool pop_first = resume;  // resuming: the suspended level is popped first
+    // one natural loop: a node's pivot step runs at the top of the iteration
+    // after a descent; resuming pops the suspended level first
+    bool pop_first = resume, at_node = !resume;
     if (resume) {
         depth = S.frame[0];
         t0 = S.frame[1];
         rs = L = 0;
         P = XP = XX = B = ks = 0;
         anc = false;
-        goto loop;
+    } else {
+        depth = 0;
+        t0 = 0;
+        rs = j.rs;
+        L = L0;
+        ks = j.ks;
+        anc = false;
+        P = lane < W ? S.pw[lane] : 0ull;
+        XP = lane < W ? S.xw[lane] : 0ull;
+        XX = lane < Wx ? low_mask(L - lane * 64) : 0ull;
+        B = 0;
     }
-    depth = 0;
-    t0 = 0;
-    rs = j.rs;
-    L = L0;
-    ks = j.ks;
-    anc = false;
-    P = lane < W ? S.pw[lane] : 0ull;
-    XP = lane < W ? S.xw[lane] : 0ull;
-    XX = lane < Wx ? low_mask(L - lane * 64) : 0ull;
-    B = 0;
-enter : {
-    ++w.nodes;
-    uint32_t best = 0;
-    uint64_t cand = P | XP;
-    for (uint32_t t = 0; t < W; ++t) {
-        uint64_t cw = rl64(cand, t);
-        if (cw == 0) continue;
-        uint32_t i = t * 64 + lane;
-        if ((cw >> lane) & 1ull) {
-            uint32_t sc = 0;
-            const uint64_t* ri = rows + (uint64_t)i * ws;
-            for (uint32_t q = 0; q < W; ++q) sc += (uint32_t)__popcll(rl64(P, q) & ri[q]);
-            best = max(best, (sc << 13) | (8191u - i));
-        }
-    }
-    best = wave_max(best);
-    uint32_t piv = 8191u - (best & 8191u);
-    B = lane < W ? (P & ~rows[(uint64_t)piv * ws + lane]) : 0ull;
-}
-loop:
     while (true) {
+        if (at_node) {
+            at_node = false;
+            ++w.nodes;
+            uint32_t best = 0;
+            uint64_t cand = P | XP;
+            for (uint32_t t = 0; t < W; ++t) {
+                uint64_t cw = rl64(cand, t);
+                if (cw == 0) continue;
+                uint32_t i = t * 64 + lane;
+                if ((cw >> lane) & 1ull) {
+                    uint32_t sc = 0;
+                    const uint64_t* ri = rows + (uint64_t)i * ws;
+                    for (uint32_t q = 0; q < W; ++q) sc += (uint32_t)__popcll(rl64(P, q) & ri[q]);
+                    best = max(best, (sc << 13) | (8191u - i));
+                }
+            }
+            best = wave_max(best);
+            uint32_t piv = 8191u - (best & 8191u);
+            B = lane < W ? (P & ~rows[(uint64_t)piv * ws + lane]) : 0ull;
+        }
         uint64_t bm = pop_first ? 0ull : __ballot(B != 0);
         if (bm == 0) {
             if (depth == 0) return kDone;
@@ -1040,7 +1066,7 @@ loop:
         XX = XXc;
         L = Lc;
         ks = ksc;
-        goto enter;
+        at_node = true;
     }
 }
 
@@ -1519,10 +1545,20 @@ __global__ void k_perm_check(const uint32_t* __restrict__ seen, uint32_t n, uint
 
 // Isolated vertices are maximal cliques of size 1 (Algorithm 3 with P = X = {}).
 // One graph: counts and hashes are summed across the wave first (one atomic per
-// wave); a batch adds per vertex into its own graph's accumulators.
+// wave); a batch adds per vertex into its own graph's accumulators.  With the
+// clique stream on (single graph), each is also written to the stream.
+struct IsoStream {
+    Ctrl* ctrl;
+    const uint32_t* perm;
+    uint32_t* verts;
+    uint64_t vcap;
+    unsigned long long* offs;
+    uint64_t ocap;
+};
+
 __global__ void k_isolated(const uint32_t* __restrict__ op, const uint32_t* __restrict__ ip,
                            const uint64_t* __restrict__ vkey, const uint32_t* __restrict__ gid, uint32_t n,
-                           unsigned long long* gacc, unsigned long long* ghist, uint32_t hist_len)
+                           unsigned long long* gacc, unsigned long long* ghist, uint32_t hist_len, IsoStream st)
 {
     const uint32_t lane = lane_id();
     unsigned long long cnt = 0, hsh = 0;
@@ -1539,6 +1575,14 @@ __global__ void k_isolated(const uint32_t* __restrict__ op, const uint32_t* __re
             } else {
                 cnt += 1;
                 hsh += h;
+            }
+            if (st.verts) {
+                unsigned long long c = atomicAdd(&st.ctrl->stream_c, 1ull);
+                unsigned long long v = atomicAdd(&st.ctrl->stream_v, 1ull);
+                const bool fits = v + 1 <= st.vcap;
+                if (fits) st.verts[v] = st.perm[r];
+                if (c < st.ocap) st.offs[c] = fits ? ((v << 16) | 1ull) : ~0ull;
+                if (!fits || c >= st.ocap) st.ctrl->stream_trunc = 1;
             }
         }
     }
@@ -1745,11 +1789,20 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
         if ((rc = build_root_queue(g, cfg, st, s, &nroots)) != MCE_OK) return rc;
         roots = st.roots.as<uint32_t>();
     }
+    IsoStream iso{};
+    if ((cfg.flags & MCE_F_STREAM) && cfg.stream_vertices && cfg.stream_offsets && g.ngraphs <= 1) {
+        iso.ctrl = reinterpret_cast<Ctrl*>(st.ctrl.p);
+        iso.perm = g.perm.as<uint32_t>();
+        iso.verts = cfg.stream_vertices;
+        iso.vcap = cfg.stream_vcap;
+        iso.offs = reinterpret_cast<unsigned long long*>(cfg.stream_offsets);
+        iso.ocap = cfg.stream_ocap;
+    }
     if (n) {
         k_isolated<<<blocks_for(n, 256, 4096), 256, 0, s>>>(
             g.op.as<uint32_t>(), g.ip.as<uint32_t>(), g.vkey.as<uint64_t>(),
             g.ngraphs > 1 ? g.gid.as<uint32_t>() : nullptr, n, reinterpret_cast<unsigned long long*>(st.gacc.p),
-            reinterpret_cast<unsigned long long*>(st.hist.p), hist_len);
+            reinterpret_cast<unsigned long long*>(st.hist.p), hist_len, iso);
         MCE_HIP_TRY(hipGetLastError());
     }
     MCE_HIP_TRY(hipEventRecord(e1, s));

@@ -231,16 +231,31 @@ def test_root_stats_match_oracle_on_sampled_roots(gpu_lib):
     assert int(cnt.sum()) + int((g.degrees() == 0).sum()) == r.count
 
 
-def test_stream_matches_oracle_cliques(gpu_lib):
+@pytest.mark.parametrize("case", ["er", "donated", "split"])
+def test_stream_matches_oracle_cliques(gpu_lib, case):
+    """The clique stream writes R from every executor: small universes, and
+    (planted cliques of 70-100 vertices, forced donations, split roots) the mid,
+    list and folded executors with R handed across donations and suspensions."""
     import torch
 
-    g = I.erdos_renyi(120, 0.3, 77)
+    kw = {}
+    if case == "er":
+        g = I.erdos_renyi(120, 0.3, 77)
+    else:
+        g = _dense(2)
+        kw = dict(donate_min_p=2, wg_per_cu=1)
+        if case == "split":
+            from paper_2212_01473_amd import learned
+
+            kw.update(model=torch.from_numpy(learned.init_model(3)).cuda(), split=True, split_top=64)
     exp = oracle.mce(g, collect=True)
-    verts = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")
+    verts = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
     offs = torch.zeros(1 << 14, dtype=torch.int64, device="cuda")
     with gpu_lib.load_graph(g) as dg:
-        r = gpu_lib.enumerate_cliques(dg, stream_buffers=(verts, offs))
+        r = gpu_lib.enumerate_cliques(dg, stream_buffers=(verts, offs), **kw)
     assert r.status == 0
+    if case == "donated":
+        assert r.stats["donations"] > 0
     v = verts.cpu().numpy().view(np.uint32)
     o = offs.cpu().numpy().view(np.uint64)[: r.stream_cliques]
     got = sorted(tuple(sorted(int(x) for x in v[int(e >> 16): int(e >> 16) + int(e & 0xFFFF)])) for e in o)
