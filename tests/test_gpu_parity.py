@@ -286,10 +286,14 @@ def _bad_graphs():
     oob = ci.copy(); oob[0] = 99
     dup = ci.copy(); dup[1] = dup[0]
     badrp = rp.copy(); badrp[2] = badrp[3] + 1
-    return [(rp, asym), (rp, unsorted), (rp, selfloop), (rp, oob), (rp, dup), (badrp, ci)]
+    # path 0-1-2 plus the arc 2 -> 0 alone: every arc v -> u with v < u has its
+    # reverse, only a v > u arc lacks one (found by the arc counts)
+    down_rp = np.array([0, 1, 3, 5], dtype=np.uint32)
+    down_ci = np.array([1, 0, 2, 0, 1], dtype=np.uint32)
+    return [(rp, asym), (rp, unsorted), (rp, selfloop), (rp, oob), (rp, dup), (badrp, ci), (down_rp, down_ci)]
 
 
-@pytest.mark.parametrize("i", range(6))
+@pytest.mark.parametrize("i", range(7))
 def test_invalid_graphs_rejected(gpu_lib, i):
     rp, ci = _bad_graphs()[i]
     with pytest.raises(gpu_lib.MCEError) as e:
