@@ -91,16 +91,24 @@ def measured_traffic(workload: str, c: int):
 
 def cpu_baseline_graph(g, c, frac_mod: int):
     """The oracle as it stands, on a deterministic sample of roots (input ids
-    v with v % frac_mod == 0), all host threads it is given."""
+    v with v % frac_mod == 0) with all host threads it is given, and on a
+    sample 16 times smaller with one thread."""
     import oracle
 
     mask = (np.arange(g.n) % frac_mod == 0).astype(np.uint8)
     t0 = time.perf_counter()
     r = oracle.mce(g, max_root_core=c, root_mask=mask)
     dt = time.perf_counter() - t0
+    mask1 = (np.arange(g.n) % (16 * frac_mod) == 0).astype(np.uint8)
+    t1 = time.perf_counter()
+    r1 = oracle.mce(g, max_root_core=c, root_mask=mask1, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": r.count / dt, "unit": "cliques/s", "cores": int(r.threads), "kind": "oracle",
             "sample": f"roots with input id % {frac_mod} == 0 ({int(mask.sum())} of {g.n}); "
-                      f"{r.count} cliques in {dt:.2f} s", "seconds": round(dt, 3)}
+                      f"{r.count} cliques in {dt:.2f} s", "seconds": round(dt, 3),
+            "single_thread": {"value": r1.count / dt1, "cores": 1,
+                              "sample": f"roots with input id % {16 * frac_mod} == 0; {r1.count} cliques in "
+                                        f"{dt1:.2f} s"}}
 
 
 def cpu_baseline_batch(batch, every: int):
@@ -135,7 +143,7 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--donate-min-p", type=int, default=0)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
-    ap.add_argument("--cpu-sample-mod", type=int, default=8)
+    ap.add_argument("--cpu-sample-mod", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch one elementwise kernel that reads and writes 1 GiB each, as the "
                          "reference for scaling hardware byte counters")

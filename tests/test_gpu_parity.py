@@ -417,3 +417,18 @@ def test_autotune_on_batch(gpu_lib):
     for i, (g, r) in enumerate(zip(graphs, res)):
         exp = oracle_result(g)
         assert (r.count, r.hash) == (exp.count, exp.hash), i
+
+
+def test_batch_with_empty_and_vertexless_graphs(gpu_lib):
+    """Members with no vertices or no edges sit between ordinary graphs; each
+    member's results stay its own (host and device loaders)."""
+    graphs = [I.empty_graph(0), I.complete_graph(5), I.empty_graph(4), I.empty_graph(0),
+              I.erdos_renyi(60, 0.2, 9), I.empty_graph(0)]
+    drp, dci, row_off, col_off = _device_batch(graphs)
+    for load in (lambda: gpu_lib.load_batch(graphs), lambda: gpu_lib.load_batch_device(drp, dci, row_off, col_off)):
+        with load() as dg:
+            res = gpu_lib.enumerate_batch(dg)
+            assert [dg.info(i).n for i in range(len(graphs))] == [g.n for g in graphs]
+        for i, (g, r) in enumerate(zip(graphs, res)):
+            exp = oracle_result(g)
+            assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist)), i
