@@ -250,6 +250,7 @@ struct Wg {
     uint64_t don_t0;  // start of the current donation attempt
     uint32_t probes;  // per lane
     uint32_t wl_tick, wl_seen, poll;
+    uint32_t don_min;  // smallest |P| of a branch offered to the worker list (~0: no worker list)
     uint64_t deadline;
     uint32_t me;
     bool abort;
@@ -458,8 +459,10 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
 __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child, bool more_here, bool anc,
                                        uint32_t depth)
 {
-    if (!(p.flags & MCE_F_WORKER_LIST)) return false;
-    if (np_child < p.donate_min_p || !more_here || !anc) return false;
+    // w.don_min: donate_min_p, or ~0 without the worker list; almost every
+    // branch stops at this one compare
+    if (__builtin_expect(np_child < w.don_min, 1)) return false;
+    if (!more_here || !anc) return false;
     if (p.donate_max_depth && depth > p.donate_max_depth) return false;
     if (p.donate_every > 1 && (++w.wl_tick % p.donate_every) != 0) return false;
     uint32_t prev = w.wl_seen;
@@ -1456,6 +1459,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.don_t0 = 0;
     w.probes = 0;
     w.wl_tick = w.wl_seen = w.poll = 0;
+    w.don_min = (p.flags & MCE_F_WORKER_LIST) ? p.donate_min_p : 0xFFFFFFFFu;
     w.me = me;
     w.abort = false;
     w.W = 1;
