@@ -29,8 +29,8 @@
 //          except its LDS stack, and X_X vertices are pivot candidates.
 //
 // Work distribution (Section III-C): phase 1 pops (root, split) entries from
-// a shared counter; phase 2 is the worker list: idle workgroups wait in an
-// MPMC ring, busy ones hand branches to them.  Results accumulate per graph
+// a shared counter; phase 2 is the worker list: idle workgroups set their bit
+// in a bitmap, busy ones claim a set bit and hand the branch to its owner.  Results accumulate per graph
 // (several graphs are enumerated as one disjoint union in batched mode).
 #include "mce_internal.h"
 
@@ -45,8 +45,6 @@ constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
 struct Ctrl {
     unsigned long long packed;     // started << 32 | idle
-    unsigned long long ring_head;
-    unsigned long long ring_tail;
     unsigned long long stream_v;
     unsigned long long stream_c;
     unsigned int root_cursor;
@@ -88,8 +86,8 @@ struct Params {
     uint64_t xcol_budget;      // words of X columns per workgroup
     uint32_t xrow_ratio;       // build X rows when |X| <= ratio * max(|U|, 64)
     uint32_t xrow_min_u;       // ... and |U| >= xrow_min_u
-    uint32_t* ring;
-    uint32_t ring_mask;
+    unsigned long long* idle_bits;  // bit g: workgroup g waits for a branch
+    uint32_t idle_words;
     uint32_t* wflags;
     uint32_t ucap, lds_cap, wg, wgx, xcap, rcap;  // wg / wgx: words per stack level of P and X_X
     uint32_t flags;
@@ -249,7 +247,7 @@ struct Wg {
     uint64_t nodes, nodes_t0;  // search-tree nodes (all tasks; at the current task's start)
     uint64_t don_t0;  // start of the current donation attempt
     uint32_t probes;  // per lane
-    uint32_t wl_tick, wl_seen, poll;
+    uint32_t wl_tick, wl_seen, poll, pops;
     uint32_t don_min;  // smallest |P| of a branch offered to the worker list (~0: no worker list)
     uint64_t deadline;
     uint32_t me;
@@ -416,36 +414,61 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
     return w;
 }
 
-// Pop an idle workgroup id (or kEmptySlot).  The ring only carries ids, so all
-// accesses are relaxed; the task is published with release/acquire on the
-// receiver's flag.
+// Claim an idle workgroup (or kEmptySlot).  All 64 lanes read one word of the
+// idle bitmap each, starting at a word that rotates per attempt; lane 0 then
+// clears a set bit of a non-empty word with one fetch-and, which either wins
+// that bit or returns the word's current value for the next try.  Donors start
+// at different words and bits, so claims rarely collide.  The bitmap carries
+// no task data: all accesses are relaxed; the task is published with
+// release/acquire on the receiver's flag.
 __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
 {
-    uint32_t r = kEmptySlot;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = p.idle_words;
     w.don_t0 = uni64(now_ticks());
-    if (lane_id() == 0) {
-        unsigned long long h = __hip_atomic_load(&p.ctrl->ring_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long t = __hip_atomic_load(&p.ctrl->ring_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (h < t && __hip_atomic_compare_exchange_strong(&p.ctrl->ring_head, &h, h + 1, __ATOMIC_RELAXED,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            uint32_t* slot = &p.ring[h & p.ring_mask];
-            uint32_t v;
-            // the pusher has claimed this slot and stores its id imminently
-            while ((v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == kEmptySlot) {
-                if (now_ticks() > w.deadline) break;
-                __builtin_amdgcn_s_sleep(1);
+    const uint32_t q0 = (w.me + 7u * w.pops++) % nw;
+    const uint32_t s = w.me & 63u;
+    uint32_t r = kEmptySlot;
+    uint32_t tried = 0;
+    for (uint32_t base = 0; base < nw && r == kEmptySlot && tried < 4; base += 64) {
+        const uint32_t k = base + lane;
+        uint32_t q = q0 + k;
+        if (q >= nw) q -= nw;
+        uint64_t b = 0;
+        if (k < nw) b = __hip_atomic_load(&p.idle_bits[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t nz = __ballot(b != 0);
+        while (nz != 0 && r == kEmptySlot && tried < 4) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(nz);
+            nz &= nz - 1;
+            ++tried;
+            uint64_t bw = rl64(b, l);
+            const uint32_t qw = rl32(q, l);
+            uint32_t got = kEmptySlot;
+            if (lane == 0) {
+                for (int t = 0; t < 3 && bw != 0; ++t) {
+                    const uint64_t rot = s ? ((bw >> s) | (bw << (64u - s))) : bw;
+                    const uint32_t i = ((uint32_t)__builtin_ctzll(rot) + s) & 63u;
+                    const uint64_t m = 1ull << i;
+                    const uint64_t old = __hip_atomic_fetch_and(&p.idle_bits[qw], ~m, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                    if (old & m) {
+                        got = qw * 64u + i;
+                        break;
+                    }
+                    bw = old & ~m;
+                }
+                if (got != kEmptySlot) {
+                    __hip_atomic_fetch_add(&p.ctrl->waiting, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // the receiver stops counting as idle before it is handed work
+                    __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
-            if (v != kEmptySlot) {
-                __hip_atomic_store(slot, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&p.ctrl->waiting, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // the receiver stops counting as idle before it is handed work
-                __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            r = v;
+            r = uni(got);
         }
     }
-    r = uni(r);
     if (r == kEmptySlot) {
+        // skip the next offer: other donors emptied the bitmap first
+        w.wl_seen = 0;
         stat_add(S_POPFAIL, 1);
         stat_add(S_DONATE, uni64(now_ticks()) - w.don_t0);
     }
@@ -1384,15 +1407,10 @@ __device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, 
         uint32_t idle = (uint32_t)old + 1, started = (uint32_t)(old >> 32);
         terminate = idle == started;
         if (!terminate) {
-            unsigned long long tl =
-                __hip_atomic_fetch_add(&p.ctrl->ring_tail, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t* slot = &p.ring[tl & p.ring_mask];
-            while (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kEmptySlot) {
-                if (now_ticks() > w.deadline) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
+            // count first, so the hint never drops below the claimable bits
             __hip_atomic_fetch_add(&p.ctrl->waiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(slot, me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&p.idle_bits[me >> 6], 1ull << (me & 63u), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     terminate = uni(terminate);
@@ -1458,7 +1476,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.nodes = w.nodes_t0 = 0;
     w.don_t0 = 0;
     w.probes = 0;
-    w.wl_tick = w.wl_seen = w.poll = 0;
+    w.wl_tick = w.wl_seen = w.poll = w.pops = 0;
     w.don_min = (p.flags & MCE_F_WORKER_LIST) ? p.donate_min_p : 0xFFFFFFFFu;
     w.me = me;
     w.abort = false;
@@ -1758,9 +1776,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     if ((rc = st.acc.alloc(32 * 8)) != MCE_OK) return rc;
     if ((rc = st.gacc.alloc((size_t)ng * 16)) != MCE_OK) return rc;
     if ((rc = st.hist.alloc((size_t)ng * hist_len * 8)) != MCE_OK) return rc;
-    uint32_t ring_cap = 1;
-    while (ring_cap < 2 * G) ring_cap <<= 1;
-    if ((rc = st.ring.alloc((size_t)ring_cap * 4)) != MCE_OK) return rc;
+    const uint32_t idle_words = (G + 63) / 64;
+    if ((rc = st.idle.alloc((size_t)idle_words * 8)) != MCE_OK) return rc;
     if ((rc = st.flags.alloc((size_t)G * 4)) != MCE_OK) return rc;
 
     hipEvent_t e0, e1, e2;
@@ -1774,7 +1791,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     fill_u64(st.acc.as<uint64_t>(), 0, 32, s);
     fill_u64(st.gacc.as<uint64_t>(), 0, (size_t)ng * 2, s);
     fill_u64(st.hist.as<uint64_t>(), 0, (size_t)ng * hist_len, s);
-    fill_u32(st.ring.as<uint32_t>(), kEmptySlot, ring_cap, s);
+    fill_u64(st.idle.as<uint64_t>(), 0, idle_words, s);
     fill_u32(st.flags.as<uint32_t>(), kFlagIdle, G, s);
 
     uint32_t nroots = 0;
@@ -1846,8 +1863,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.xcol_budget = xcol_words;
     p.xrow_ratio = cfg.xrow_ratio;
     p.xrow_min_u = cfg.xrow_min_u;
-    p.ring = st.ring.as<uint32_t>();
-    p.ring_mask = ring_cap - 1;
+    p.idle_bits = st.idle.as<unsigned long long>();
+    p.idle_words = idle_words;
     p.wflags = st.flags.as<uint32_t>();
     p.ucap = ucap;
     p.lds_cap = lds_cap;

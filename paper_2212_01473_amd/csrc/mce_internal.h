@@ -185,7 +185,7 @@ struct LearnedQueue {
 // One graph's enumeration state kept across calls (scratch sized to the graph).
 struct EnumState {
     LearnedQueue lq;
-    DevBuf roots, ctrl, acc, gacc, hist, scratch, ring, flags, small;
+    DevBuf roots, ctrl, acc, gacc, hist, scratch, idle, flags, small;
     DevBuf tmp_a, tmp_b, tmp_c, scan_tmp;
     size_t scratch_stride = 0;
     uint32_t grid = 0;
