@@ -147,7 +147,7 @@ typedef struct {
     uint32_t bitmap_max_p;      /* largest subtree universe whose bitmap rows live in LDS;
                                    larger ones use HBM rows; 0 = 128 (smaller LDS per
                                    workgroup, more resident workgroups) */
-    uint32_t donate_min_p;      /* donate a branch only if its |P| >= this; 0 = 32 (Section III-C
+    uint32_t donate_min_p;      /* donate a branch only if its |P| >= this; 0 = 24 (Section III-C
                                    uses 10; a donated branch here is rebuilt from the CSR by
                                    its receiver, so smaller ones cost more than they save) */
     uint32_t donate_max_depth;  /* donate only at depth <= this; 0 = unlimited */

@@ -407,7 +407,7 @@ mce_status mce_autotune(mce_graph* g, const mce_options* base, mce_options* tune
         std::vector<uint32_t> values;
     };
     const std::vector<Knob> knobs = {
-        {&mce_options::donate_min_p, {12, 20, 32, 48}},
+        {&mce_options::donate_min_p, {16, 20, 24, 32}},
         {&mce_options::bitmap_max_p, {64, 128, 256}},
         {&mce_options::wg_per_cu, {0, 4, 2}},
         {&mce_options::donate_max_depth, {0, 3}},

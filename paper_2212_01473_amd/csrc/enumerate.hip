@@ -43,16 +43,19 @@ constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
 constexpr int kHistLds = 256;
 constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
+// The counters that every workgroup updates with device-scope atomics each sit
+// in a 256-byte block of their own, so they do not contend for one line.
+constexpr uint32_t kIdleStride = 32;  // idle bitmap: one 64-bit word per 256 bytes
+
 struct Ctrl {
-    unsigned long long packed;     // started << 32 | idle
-    unsigned long long stream_v;
+    alignas(256) unsigned long long packed;  // started << 32 | idle
+    alignas(256) unsigned int waiting;       // workgroups currently in the worker list
+    alignas(256) unsigned int root_cursor;
+    alignas(256) unsigned long long stream_v;
     unsigned long long stream_c;
-    unsigned int root_cursor;
-    unsigned int err;              // 1 = timeout
+    unsigned int err;              // 1 = timeout, 4 = inconsistent mailbox
     unsigned int stream_trunc;
-    unsigned int waiting;          // workgroups currently in the worker list
     unsigned int tlog_n;           // tasks that qualified for the task log
-    unsigned int pad[3];
 };
 
 struct MboxHdr {
@@ -86,10 +89,11 @@ struct Params {
     uint64_t xcol_budget;      // words of X columns per workgroup
     uint32_t xrow_ratio;       // build X rows when |X| <= ratio * max(|U|, 64)
     uint32_t xrow_min_u;       // ... and |U| >= xrow_min_u
-    unsigned long long* idle_bits;  // bit g: workgroup g waits for a branch
+    unsigned long long* idle_bits;  // bit g % 64 of word (g / 64) * kIdleStride: workgroup g waits
     uint32_t idle_words;
     uint32_t* wflags;
     uint32_t ucap, lds_cap, wg, wgx, xcap, rcap;  // wg / wgx: words per stack level of P and X_X
+    uint32_t nv;               // vertices (ranks are < nv)
     uint32_t flags;
     uint32_t donate_min_p, donate_max_depth, donate_every;
     uint32_t nwg;
@@ -435,7 +439,7 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
         uint32_t q = q0 + k;
         if (q >= nw) q -= nw;
         uint64_t b = 0;
-        if (k < nw) b = __hip_atomic_load(&p.idle_bits[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k < nw) b = __hip_atomic_load(&p.idle_bits[q * kIdleStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t nz = __ballot(b != 0);
         while (nz != 0 && r == kEmptySlot && tried < 4) {
             const uint32_t l = (uint32_t)__builtin_ctzll(nz);
@@ -449,7 +453,7 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
                     const uint64_t rot = s ? ((bw >> s) | (bw << (64u - s))) : bw;
                     const uint32_t i = ((uint32_t)__builtin_ctzll(rot) + s) & 63u;
                     const uint64_t m = 1ull << i;
-                    const uint64_t old = __hip_atomic_fetch_and(&p.idle_bits[qw], ~m, __ATOMIC_RELAXED,
+                    const uint64_t old = __hip_atomic_fetch_and(&p.idle_bits[qw * kIdleStride], ~m, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
                     if (old & m) {
                         got = qw * 64u + i;
@@ -1330,13 +1334,15 @@ __device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t 
     return t;
 }
 
-// A task received through the worker list; its lists are in this workgroup's mailbox.
-__device__ __forceinline__ TaskArgs setup_received(const Params& p, Wg& w)
+// A task received through the worker list; its lists are in this workgroup's
+// mailbox.  Returns false when the mailbox is not a task this kernel could have
+// written (a size beyond its capacity, a rank >= n): nothing is read through
+// such values.
+__device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs& t)
 {
     const uint32_t lane = lane_id();
     MboxHdr h = *w.mbox;
     uint32_t np = uni(h.np), nxp = uni(h.nxp);
-    TaskArgs t;
     t.root = uni(h.root);
     t.L = uni(h.nxx);
     t.rs = uni(h.rsize);
@@ -1344,6 +1350,15 @@ __device__ __forceinline__ TaskArgs setup_received(const Params& p, Wg& w)
     t.c = 0;
     t.C = 1;
     t.nu = np + nxp;
+    if (t.root >= p.nv || np > p.ucap || nxp > p.ucap || t.nu > p.ucap || t.L > p.xcap || t.rs == 0 ||
+        t.rs + 2 > p.rcap)
+        return false;
+    bool bad = false;
+    for (uint32_t i = lane; i < t.L; i += 64) bad |= w.xr[i] >= p.nv;
+    for (uint32_t i = lane; i < t.rs; i += 64) bad |= w.R[i] >= p.nv;
+    for (uint32_t i = lane; i < np; i += 64) bad |= w.mP[i] >= p.nv;
+    for (uint32_t i = lane; i < nxp; i += 64) bad |= w.mXP[i] >= p.nv;
+    if (__ballot(bad) != 0) return false;
     uint32_t W = (t.nu + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
         S.pw[q] = 0;
@@ -1376,7 +1391,7 @@ __device__ __forceinline__ TaskArgs setup_received(const Params& p, Wg& w)
         atomicOr((unsigned long long*)&S.xw[pos >> 6], 1ull << (pos & 63));
     }
     wave_mem_sync();
-    return t;
+    return true;
 }
 
 // Next unit of work: a (root, split) entry of the queue in phase 1, a donated
@@ -1409,7 +1424,7 @@ __device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, 
         if (!terminate) {
             // count first, so the hint never drops below the claimable bits
             __hip_atomic_fetch_add(&p.ctrl->waiting, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_or(&p.idle_bits[me >> 6], 1ull << (me & 63u), __ATOMIC_RELAXED,
+            __hip_atomic_fetch_or(&p.idle_bits[(me >> 6) * kIdleStride], 1ull << (me & 63u), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -1440,8 +1455,13 @@ __device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, 
     }
     if (f == kFlagTerm) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    t = setup_received(p, w);
-    return true;
+    if (setup_received(p, w, t)) return true;
+    // inconsistent mailbox: report it and stop every workgroup
+    if (lane == 0) atomicOr(&p.ctrl->err, 4u);
+    for (uint32_t g = lane; g < p.nwg; g += 64)
+        __hip_atomic_store(&p.wflags[g], kFlagTerm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    w.abort = true;
+    return false;
 }
 
 __global__ void __launch_bounds__(64) k_enumerate(Params p)
@@ -1777,7 +1797,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     if ((rc = st.gacc.alloc((size_t)ng * 16)) != MCE_OK) return rc;
     if ((rc = st.hist.alloc((size_t)ng * hist_len * 8)) != MCE_OK) return rc;
     const uint32_t idle_words = (G + 63) / 64;
-    if ((rc = st.idle.alloc((size_t)idle_words * 8)) != MCE_OK) return rc;
+    if ((rc = st.idle.alloc((size_t)idle_words * kIdleStride * 8)) != MCE_OK) return rc;
     if ((rc = st.flags.alloc((size_t)G * 4)) != MCE_OK) return rc;
 
     hipEvent_t e0, e1, e2;
@@ -1791,7 +1811,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     fill_u64(st.acc.as<uint64_t>(), 0, 32, s);
     fill_u64(st.gacc.as<uint64_t>(), 0, (size_t)ng * 2, s);
     fill_u64(st.hist.as<uint64_t>(), 0, (size_t)ng * hist_len, s);
-    fill_u64(st.idle.as<uint64_t>(), 0, idle_words, s);
+    fill_u64(st.idle.as<uint64_t>(), 0, (size_t)idle_words * kIdleStride, s);
     fill_u32(st.flags.as<uint32_t>(), kFlagIdle, G, s);
 
     uint32_t nroots = 0;
@@ -1867,6 +1887,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.idle_words = idle_words;
     p.wflags = st.flags.as<uint32_t>();
     p.ucap = ucap;
+    p.nv = n;
     p.lds_cap = lds_cap;
     p.wg = wg_words;
     p.wgx = wgx_words;
@@ -1951,8 +1972,13 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     out.stream_v = ctrl.stream_v;
     out.stream_truncated = ctrl.stream_trunc != 0;
     out.timed_out = (ctrl.err & 1u) != 0;
+    const bool mailbox_err = (ctrl.err & 4u) != 0;
     st.grid = G;
     st.lds_cap = lds_cap;
+    if (mailbox_err) {
+        set_error("a worker-list mailbox held sizes or ranks out of range; results are invalid");
+        return MCE_ERR_DEVICE;
+    }
     if (out.timed_out) {
         set_error("enumeration exceeded its timeout; results are invalid");
         return MCE_ERR_TIMEOUT;

@@ -126,7 +126,7 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
 
 // Enumeration (enumerate.hip) ----------------------------------------------------------
 // Default knobs (measured on gfx950; see the options in mce.h)
-constexpr uint32_t kDefaultDonateMinP = 32;
+constexpr uint32_t kDefaultDonateMinP = 24;
 constexpr uint32_t kDefaultBitmapMaxP = 128;
 
 struct EnumConfig {
