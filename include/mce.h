@@ -201,7 +201,8 @@ enum {
     MCE_STAT_TASK_LOG = 18,    /* tasks that qualified for the task log (may exceed its capacity) */
     MCE_STAT_DONATE_NS = 19,   /* summed time spent offering branches to the worker list (ns) */
     MCE_STAT_POP_FAILS = 20,   /* offers that found no idle workgroup */
-    MCE_STAT_XCOL_WORDS = 21   /* X-column words read for bitmap X_X children */
+    MCE_STAT_XCOL_WORDS = 21,  /* X-column words read for bitmap X_X children */
+    MCE_STAT_FOLD_DONATIONS = 22 /* donations sent as register frames (no rebuild by the receiver) */
 };
 
 typedef struct {

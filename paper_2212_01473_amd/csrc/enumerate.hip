@@ -62,8 +62,18 @@ struct MboxHdr {
     uint32_t root;     // root rank (graph and per-root attribution)
     uint32_t rsize;    // |R|
     uint64_t keysum;   // sum of keys of R (mod 2^64)
-    uint32_t np, nxp, nxx, pad;
+    uint32_t np, nxp, nxx;
+    uint32_t kind;     // kMboxLists or kMboxFold
 };
+
+// A donated branch travels either as lists (P, X_P, X_X ranks; the receiver
+// builds the bitmaps from the CSR) or, when its universe and X_X each fit 64
+// vertices, as a fold frame: the donor's register rows, so the receiver runs
+// the folded executor without any construction.  Frame words: P, X_P, then
+// per lane rowP[64], skey[64], X row[64]; then ranks su[64], X rank[64].
+constexpr uint32_t kMboxLists = 0, kMboxFold = 1;
+constexpr uint32_t kFrRow = 2, kFrKey = 66, kFrXRow = 130, kFrU32 = 194;
+constexpr uint64_t kFrameBytes = kFrU32 * 8 + 128 * 4;
 
 struct Params {
     const uint32_t* op;
@@ -83,6 +93,7 @@ struct Params {
     uint32_t hist_len;
     uint8_t* scratch;
     uint64_t stride;
+    uint64_t off_fr;
     uint64_t off_P, off_XP, off_R, off_xr, off_xx, off_flag, off_hpos, off_spos, off_rows, off_xrows, off_xcols, off_stack,
         off_meta;
     uint64_t xrow_budget;      // words of X rows per workgroup
@@ -197,7 +208,7 @@ __device__ inline uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ul
 // Statistics counters kept in LDS (updated by lane 0) to spare scalar registers.
 enum : int {
     S_NODES = 0, S_DONATIONS, S_TASKS, S_XTESTS, S_EDGES, S_HBM, S_IDLE, S_ROOTW, S_XROW, S_BUSY, S_MAXTASK,
-    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_DONATE, S_POPFAIL, S_XCOLW, S_COUNT
+    S_CTASK, S_HTASK, S_PENDING, S_BUILD, S_DONATE, S_POPFAIL, S_XCOLW, S_FOLDDON, S_COUNT
 };
 
 // Fixed-size LDS of a workgroup (static offsets: no pointer registers).
@@ -225,6 +236,7 @@ struct Wg {
     uint32_t* mP;      // mailbox P ranks
     uint32_t* mXP;     // mailbox X_P ranks
     uint32_t* R;       // ranks of R
+    uint64_t* fr;      // mailbox fold frame
     uint32_t* xr;      // the task's initial X_X ranks (mailbox target)
     uint32_t* xx;      // X_X as indices into xr, partitioned in place
     uint64_t* xflag;
@@ -414,6 +426,7 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
     w.mP = reinterpret_cast<uint32_t*>(base + p.off_P);
     w.mXP = reinterpret_cast<uint32_t*>(base + p.off_XP);
     w.R = reinterpret_cast<uint32_t*>(base + p.off_R);
+    w.fr = reinterpret_cast<uint64_t*>(base + p.off_fr);
     w.xr = reinterpret_cast<uint32_t*>(base + p.off_xr);
     return w;
 }
@@ -500,7 +513,7 @@ __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child
 // Finish a donation to r: R (this workgroup's R[0, rs) plus vb), header, one
 // release fence, then the flag.  P, X_P and X_X were written by the caller.
 __device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
-                             uint64_t ks, uint32_t np, uint32_t nxp, uint32_t nxx)
+                             uint64_t ks, uint32_t np, uint32_t nxp, uint32_t nxx, uint32_t kind)
 {
     const uint32_t lane = lane_id();
     Wg d = wg_view(p, r);
@@ -514,12 +527,13 @@ __device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, 
         h.np = np;
         h.nxp = nxp;
         h.nxx = nxx;
-        h.pad = 0;
+        h.kind = kind;
         *d.mbox = h;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) __hip_atomic_store(&p.wflags[r], kFlagTask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     stat_add(S_DONATIONS, 1);
+    if (kind == kMboxFold) stat_add(S_FOLDDON, 1);
     stat_add(S_DONATE, uni64(now_ticks()) - w.don_t0);
 }
 
@@ -543,6 +557,53 @@ struct SmallJob {
 };
 
 enum : uint32_t { kDone = 0, kYieldFold = 1, kYieldList = 2 };
+
+// Adjacency of X_X entry xj (vx: this lane holds one) over a small universe
+// whose vertex k is task-universe vertex oidx_k, ascending in k; with a
+// one-word task universe the small universe is the task universe itself.
+__device__ __forceinline__ uint64_t fold_xrow(const Wg& w, bool vx, uint32_t xj, uint32_t oidx, uint32_t m)
+{
+    if (w.W == 1) return vx ? w.xrows[xj] : 0ull;
+    // o_k ascend with k: load each X-row word once
+    const uint64_t* xrow = w.xrows + (uint64_t)xj * w.W;
+    uint64_t xrowP = 0;
+    uint32_t k = 0;
+    while (k < m) {
+        uint32_t q = rl32(oidx, k) >> 6;
+        uint64_t word = vx ? xrow[q] : 0ull;
+        for (; k < m; ++k) {
+            uint32_t ok = rl32(oidx, k);
+            if ((ok >> 6) != q) break;
+            xrowP |= ((word >> (ok & 63)) & 1ull) << k;
+        }
+    }
+    return xrowP;
+}
+
+// Write a fold frame into d's mailbox: universe of m vertices (lane k: rank
+// su, key skey, row rowP), P / X_P masks, and this lane's X_X entry (xin) at
+// slot xslot (rank xrank, row xrowP over the universe).
+__device__ __forceinline__ void put_fold_frame(const Wg& d, uint32_t m, uint64_t P, uint64_t XP, uint32_t su,
+                                               uint64_t skey, uint64_t rowP, bool xin, uint32_t xslot,
+                                               uint32_t xrank, uint64_t xrowP)
+{
+    const uint32_t lane = lane_id();
+    uint64_t* f = d.fr;
+    uint32_t* f32 = reinterpret_cast<uint32_t*>(f + kFrU32);
+    if (lane == 0) {
+        f[0] = P;
+        f[1] = XP;
+    }
+    if (lane < m) {
+        f[kFrRow + lane] = rowP;
+        f[kFrKey + lane] = skey;
+        f32[lane] = su;
+    }
+    if (xin) {
+        f[kFrXRow + xslot] = xrowP;
+        f32[64 + xslot] = xrank;
+    }
+}
 enum : uint32_t { kExDone = 0, kExFold = 1, kExList = 2, kExMid = 3 };
 
 // ---------------------------------------------------------------- folded executor
@@ -559,26 +620,7 @@ __device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root
     const uint32_t su = j.su;
     const uint64_t skey = j.skey, rowP = j.rowP;
     const uint32_t xrank = vx ? w.xr[j.xj] : 0u;
-    uint64_t xrowP = 0;
-    if (L) {
-        if (w.W == 1) {
-            // the small universe is the task universe itself (oidx = lane)
-            xrowP = vx ? w.xrows[j.xj] : 0ull;
-        } else {
-            // o_k ascend with k: load each X-row word once
-            const uint64_t* xrow = w.xrows + (uint64_t)j.xj * w.W;
-            uint32_t k = 0;
-            while (k < m) {
-                uint32_t q = rl32(j.oidx, k) >> 6;
-                uint64_t word = vx ? xrow[q] : 0ull;
-                for (; k < m; ++k) {
-                    uint32_t ok = rl32(j.oidx, k);
-                    if ((ok >> 6) != q) break;
-                    xrowP |= ((word >> (ok & 63)) & 1ull) << k;
-                }
-            }
-        }
-    }
+    const uint64_t xrowP = L ? fold_xrow(w, vx, j.xj, j.oidx, m) : 0ull;
     uint64_t rowX = 0;
     for (uint32_t t = 0; t < L; ++t) {
         uint64_t wt = rl64(xrowP, t);
@@ -649,13 +691,13 @@ __device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root
         if (donation_wanted(p, w, npc, B != 0, anc || depth > 0, depth)) {
             uint32_t r = wl_try_pop(p, w);
             if (r != kEmptySlot) {
+                // the child keeps this universe and the members of X_X
                 Wg d = wg_view(p, r);
-                if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
-                if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
-                if ((XXc >> lane) & 1ull) d.xr[prefix_popc(XXc)] = xrank;
+                put_fold_frame(d, m, Pc, XPc, su, skey, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc), xrank,
+                               xrowP);
                 if (lane < depth) w.R[rs0 + lane] = sV;
                 wave_mem_sync();
-                publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), (uint32_t)__popcll(XXc));
+                publish_task(p, w, r, root, rs, vb, ksc, m, 0, (uint32_t)__popcll(XXc), kMboxFold);
                 continue;
             }
         }
@@ -787,12 +829,23 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
             uint32_t r = wl_try_pop(p, w);
             if (r != kEmptySlot) {
                 Wg d = wg_view(p, r);
+                if (lane < depth) w.R[rs0 + lane] = sV;
+                if (Lc <= 64 && (can_fold || Lc == 0)) {
+                    // fold frame over this universe; X_X members' rows gathered from the X rows
+                    wave_mem_sync();
+                    const bool xin = lane < Lc;
+                    const uint32_t xj = xin ? w.xx[lane] : 0u;
+                    const uint64_t xrowP = Lc ? fold_xrow(w, xin, xj, oidx, m) : 0ull;
+                    put_fold_frame(d, m, Pc, XPc, su, skey, rowP, xin, lane, xin ? w.xr[xj] : 0u, xrowP);
+                    wave_mem_sync();
+                    publish_task(p, w, r, root, rs, vb, ksc, m, 0, Lc, kMboxFold);
+                    continue;
+                }
                 if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
                 if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
                 for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
-                if (lane < depth) w.R[rs0 + lane] = sV;
                 wave_mem_sync();
-                publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), Lc);
+                publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), Lc, kMboxLists);
                 continue;
             }
         }
@@ -863,6 +916,55 @@ __device__ __forceinline__ uint32_t xx_members(Wg& w, uint64_t XX, bool to_list)
     }
     wave_mem_sync();
     return (!to_list && lane < base) ? S.sxj[lane] : 0u;
+}
+
+// A child whose P u X_P (masks Pc, XPc over the task universe) has at most
+// 64 vertices, re-indexed: lane k < msz holds task-universe vertex o (the
+// members in ascending order) and its row over the small universe.
+struct SmallView {
+    uint32_t msz, o;
+    uint64_t row, P, XP;
+};
+
+__device__ __forceinline__ SmallView compact_child(const uint64_t* rows, uint32_t ws, uint32_t W, uint64_t Pc,
+                                                   uint64_t XPc)
+{
+    const uint32_t lane = lane_id();
+    SmallView v;
+    uint64_t cand = lane < W ? (Pc | XPc) : 0ull;
+    uint32_t cnt = (uint32_t)__popcll(cand);
+    uint32_t pre = wave_excl_scan(cnt);
+    v.msz = wave_sum(cnt);
+    uint64_t cc = cand;
+    uint32_t tt = pre;
+    while (cc) {
+        uint32_t bt = (uint32_t)__builtin_ctzll(cc);
+        cc &= cc - 1;
+        S.sidx[tt++] = lane * 64 + bt;
+    }
+    wave_mem_sync();
+    const bool valid = lane < v.msz;
+    v.o = valid ? S.sidx[lane] : 0u;
+    // local row of vertex k: bit k2 set iff o_k and o_k2 are adjacent; the
+    // sorted o_k2 visit each source word once, so each word is loaded once
+    uint64_t row = 0;
+    const uint64_t* ro = rows + (uint64_t)v.o * ws;
+    uint32_t k2 = 0;
+    while (k2 < v.msz) {
+        uint32_t q = S.sidx[k2] >> 6;
+        uint64_t wq = valid ? ro[q] : 0ull;
+        for (; k2 < v.msz; ++k2) {
+            uint32_t o2 = S.sidx[k2];
+            if ((o2 >> 6) != q) break;
+            row |= ((wq >> (o2 & 63)) & 1ull) << k2;
+        }
+    }
+    v.row = row;
+    uint64_t pword = shfl64(Pc, v.o >> 6);
+    uint64_t xword = shfl64(XPc, v.o >> 6);
+    v.P = __ballot(valid && ((pword >> (v.o & 63)) & 1ull));
+    v.XP = __ballot(valid && ((xword >> (v.o & 63)) & 1ull));
+    return v;
 }
 
 // Universe of up to 4096 vertices, one 64-bit word per lane (W words).  The
@@ -993,6 +1095,22 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
             uint32_t r = wl_try_pop(p, w);
             if (r != kEmptySlot) {
                 Wg d = wg_view(p, r);
+                if (npc + nxc <= 64 && (xb ? Lc <= 64 : Lc == 0)) {
+                    // fold frame: the child re-indexed as for a hand-over to the folded executor
+                    const SmallView cv = compact_child(rows, ws, W, Pc, XPc);
+                    const bool valid = lane < cv.msz, xin = lane < Lc;
+                    uint32_t xj = 0;
+                    uint64_t xrowP = 0;
+                    if (Lc) {
+                        xj = xx_members(w, XXc, false);
+                        xrowP = fold_xrow(w, xin, xj, cv.o, cv.msz);
+                    }
+                    put_fold_frame(d, cv.msz, cv.P, cv.XP, valid ? U[cv.o] : 0u, valid ? w.ukey[cv.o] : 0ull, cv.row,
+                                   xin, lane, xin ? w.xr[xj] : 0u, xrowP);
+                    wave_mem_sync();
+                    publish_task(p, w, r, root, rs, vb, ksc, cv.msz, 0, Lc, kMboxFold);
+                    continue;
+                }
                 uint32_t bp = 0, bx = 0;
                 for (uint32_t t = 0; t < W; ++t) {
                     uint64_t pw_ = rl64(Pc, t), xw_ = rl64(XPc, t);
@@ -1012,7 +1130,7 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
                 } else {
                     for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
                 }
-                publish_task(p, w, r, root, rs, vb, ksc, npc, nxc, Lc);
+                publish_task(p, w, r, root, rs, vb, ksc, npc, nxc, Lc, kMboxLists);
                 continue;
             }
         }
@@ -1033,45 +1151,15 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
         ++depth;
         if (npc + nxc <= 64) {
             // re-index the child's P u X_P (at most 64 vertices) into registers
-            uint64_t cand = lane < W ? (Pc | XPc) : 0ull;
-            uint32_t cnt = (uint32_t)__popcll(cand);
-            uint32_t pre = wave_excl_scan(cnt);
-            uint32_t msz = wave_sum(cnt);
-            uint64_t cc = cand;
-            uint32_t tt = pre;
-            while (cc) {
-                uint32_t bt = (uint32_t)__builtin_ctzll(cc);
-                cc &= cc - 1;
-                S.sidx[tt++] = lane * 64 + bt;
-            }
-            wave_mem_sync();
-            const bool valid = lane < msz;
-            const uint32_t o = valid ? S.sidx[lane] : 0u;
-            // local row of vertex k: bit k2 set iff o_k and o_k2 are adjacent; the
-            // sorted o_k2 visit each source word once, so each word is loaded once
-            uint64_t row = 0;
-            const uint64_t* ro = rows + (uint64_t)o * ws;
-            {
-                uint32_t k2 = 0;
-                while (k2 < msz) {
-                    uint32_t q = S.sidx[k2] >> 6;
-                    uint64_t wq = valid ? ro[q] : 0ull;
-                    for (; k2 < msz; ++k2) {
-                        uint32_t o2 = S.sidx[k2];
-                        if ((o2 >> 6) != q) break;
-                        row |= ((wq >> (o2 & 63)) & 1ull) << k2;
-                    }
-                }
-            }
-            uint64_t pword = shfl64(Pc, o >> 6);
-            uint64_t xword = shfl64(XPc, o >> 6);
-            j.m = msz;
-            j.su = valid ? U[o] : 0u;
-            j.skey = valid ? w.ukey[o] : 0ull;
-            j.oidx = o;
-            j.rowP = row;
-            j.P = __ballot(valid && ((pword >> (o & 63)) & 1ull));
-            j.XP = __ballot(valid && ((xword >> (o & 63)) & 1ull));
+            const SmallView cv = compact_child(rows, ws, W, Pc, XPc);
+            const bool valid = lane < cv.msz;
+            j.m = cv.msz;
+            j.su = valid ? U[cv.o] : 0u;
+            j.skey = valid ? w.ukey[cv.o] : 0ull;
+            j.oidx = cv.o;
+            j.rowP = cv.row;
+            j.P = cv.P;
+            j.XP = cv.XP;
             j.L = Lc;
             j.ks = ksc;
             j.rs = rs + 1;
@@ -1211,10 +1299,14 @@ __device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t roo
     }
 }
 
-// Run a task whose universe U (ascending ranks) is in w.uarr[0, nu), with P
-// and X_P as bitmasks in S.pw / S.xw and the initial X_X ranks in w.xr[0, L).
-__device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks, uint32_t rs,
-                         uint32_t c, uint32_t C)
+// Bitmaps of a task whose universe U (ascending ranks) is in w.uarr[0, nu),
+// with P and X_P as bitmasks in S.pw / S.xw and the initial X_X ranks in
+// w.xr[0, L): universe rows (LDS, or HBM beyond the LDS cap) and, within the
+// X budgets, X rows and X columns.  Returns the first executor; a universe of
+// at most 64 vertices is set up in j.
+__device__ __forceinline__ uint32_t build_task(const Params& p, Wg& w, uint32_t nu, uint32_t L, uint64_t ks,
+                                               uint32_t rs, uint32_t C, SmallJob& j, const uint64_t*& rows,
+                                               uint32_t& ws)
 {
     const uint32_t lane = lane_id();
     const uint32_t W = (nu + 63) >> 6;
@@ -1237,47 +1329,62 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
         scan_lists(p, w, 1, L, nu, w.xrows, W, cols ? w.xcols : nullptr, Wx);
         stat_add(S_XROW, 1);
     }
-    uint64_t* rows;
-    uint32_t ws;
+    uint64_t* brows;
     if (nu <= 64) {
-        rows = w.lrows;
+        brows = w.lrows;
         ws = 1;
     } else if (nu <= p.lds_cap) {
-        rows = w.lrows;
+        brows = w.lrows;
         ws = W | 1u;
     } else {
-        rows = w.grows;
+        brows = w.grows;
         ws = W | 1u;
         stat_add(S_HBM, 1);
     }
-    for (uint32_t i = lane; i < nu * ws; i += 64) rows[i] = 0;
+    rows = brows;
+    for (uint32_t i = lane; i < nu * ws; i += 64) brows[i] = 0;
     wave_mem_sync();
-    scan_lists(p, w, 0, nu, nu, rows, ws, nullptr, 0);
+    scan_lists(p, w, 0, nu, nu, brows, ws, nullptr, 0);
     stat_add(S_BUILD, now_ticks() - tb0);
-    // dispatcher: one instance of each executor; a suspended executor resumes
-    // when the one it handed a child to has finished
-    SmallJob j;
     j.ks = ks;
     j.rs = rs;
     j.anc = false;
+    if (nu > 64) return kExMid;
+    const bool valid = lane < nu;
+    j.m = nu;
+    j.su = valid ? w.uarr[lane] : 0u;
+    j.skey = valid ? w.ukey[lane] : 0ull;
+    j.oidx = lane;
+    j.rowP = valid ? brows[lane] : 0ull;
+    j.P = S.pw[0];
+    j.XP = S.xw[0];
+    j.L = L;
+    j.xj = lane;  // xx[i] = i at the start of a task
+    wave_mem_sync();
+    return (C == 1 && L <= 64 && (w.have_xrows || L == 0)) ? kExFold : kExList;
+}
+
+// Run a task: a built one (build_task), or a fold frame received ready (fj,
+// with its X_X rows and ranks already in w.xrows / w.xr).
+__device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks,
+                                         uint32_t rs, uint32_t c, uint32_t C, bool frame, const SmallJob& fj)
+{
+    // dispatcher: one instance of each executor; a suspended executor resumes
+    // when the one it handed a child to has finished
+    SmallJob j;
     uint32_t ex;
     bool mid_susp = false, list_susp = false;
     uint32_t lc = c, lC = C;
-    if (nu <= 64) {
-        const bool valid = lane < nu;
-        j.m = nu;
-        j.su = valid ? w.uarr[lane] : 0u;
-        j.skey = valid ? w.ukey[lane] : 0ull;
-        j.oidx = lane;
-        j.rowP = valid ? rows[lane] : 0ull;
-        j.P = S.pw[0];
-        j.XP = S.xw[0];
-        j.L = L;
-        j.xj = lane;  // xx[i] = i at the start of a task
-        wave_mem_sync();
-        ex = (C == 1 && L <= 64 && (w.have_xrows || L == 0)) ? kExFold : kExList;
+    const uint64_t* rows = w.lrows;
+    uint32_t ws = 1;
+    if (frame) {
+        w.W = 1;
+        w.Wx = L ? 1u : 0u;
+        w.have_xrows = L > 0;
+        j = fj;
+        ex = kExFold;
     } else {
-        ex = kExMid;
+        ex = build_task(p, w, nu, L, ks, rs, C, j, rows, ws);
     }
     while (ex != kExDone && !w.abort) {
         if (ex == kExFold) {
@@ -1301,7 +1408,7 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
 
 // Task parameters set up by either source of work.
 struct TaskArgs {
-    uint32_t root, nu, L, rs, c, C;
+    uint32_t root, nu, L, rs, c, C, kind;
     uint64_t ks;
 };
 
@@ -1331,6 +1438,7 @@ __device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t 
     t.c = split & 0xFFFFu;
     if (t.C == 0) t.C = 1;
     t.ks = p.vkey[v];
+    t.kind = kMboxLists;
     return t;
 }
 
@@ -1338,7 +1446,7 @@ __device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t 
 // mailbox.  Returns false when the mailbox is not a task this kernel could have
 // written (a size beyond its capacity, a rank >= n): nothing is read through
 // such values.
-__device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs& t)
+__device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs& t, SmallJob& fj)
 {
     const uint32_t lane = lane_id();
     MboxHdr h = *w.mbox;
@@ -1347,8 +1455,43 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
     t.L = uni(h.nxx);
     t.rs = uni(h.rsize);
     t.ks = uni64(h.keysum);
+    t.kind = uni(h.kind);
     t.c = 0;
     t.C = 1;
+    if (t.kind == kMboxFold) {
+        const uint32_t m = np, L = t.L;
+        if (t.root >= p.nv || m == 0 || m > 64 || nxp != 0 || L > 64 || L > p.xcap || (L && L > p.xrow_budget) ||
+            t.rs == 0 || t.rs + 2 > p.rcap)
+            return false;
+        const uint64_t* f = w.fr;
+        const uint32_t* f32 = reinterpret_cast<const uint32_t*>(f + kFrU32);
+        const bool valid = lane < m, vx = lane < L;
+        fj.m = m;
+        fj.L = L;
+        fj.P = uni64(f[0]);
+        fj.XP = uni64(f[1]);
+        fj.su = valid ? f32[lane] : 0u;
+        fj.skey = valid ? f[kFrKey + lane] : 0ull;
+        fj.rowP = valid ? f[kFrRow + lane] : 0ull;
+        const uint32_t xrank = vx ? f32[64 + lane] : 0u;
+        const uint64_t xrow = vx ? f[kFrXRow + lane] : 0ull;
+        bool bad = (valid && fj.su >= p.nv) || (vx && xrank >= p.nv);
+        for (uint32_t i = lane; i < t.rs; i += 64) bad |= w.R[i] >= p.nv;
+        if (__ballot(bad) != 0 || ((fj.P | fj.XP) & ~low_mask(m)) != 0) return false;
+        if (vx) {
+            w.xr[lane] = xrank;
+            w.xrows[lane] = xrow;
+        }
+        fj.oidx = lane;
+        fj.xj = lane;
+        fj.rs = t.rs;
+        fj.ks = t.ks;
+        fj.anc = false;
+        t.nu = m;
+        wave_mem_sync();
+        return true;
+    }
+    if (t.kind != kMboxLists) return false;
     t.nu = np + nxp;
     if (t.root >= p.nv || np > p.ucap || nxp > p.ucap || t.nu > p.ucap || t.L > p.xcap || t.rs == 0 ||
         t.rs + 2 > p.rcap)
@@ -1396,7 +1539,7 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
 
 // Next unit of work: a (root, split) entry of the queue in phase 1, a donated
 // branch in phase 2.  Returns false when the kernel is done for this workgroup.
-__device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, TaskArgs& t)
+__device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, TaskArgs& t, SmallJob& fj)
 {
     const uint32_t lane = lane_id();
     const uint32_t me = w.me;
@@ -1455,7 +1598,7 @@ __device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, 
     }
     if (f == kFlagTerm) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (setup_received(p, w, t)) return true;
+    if (setup_received(p, w, t, fj)) return true;
     // inconsistent mailbox: report it and stop every workgroup
     if (lane == 0) atomicOr(&p.ctrl->err, 4u);
     for (uint32_t g = lane; g < p.nwg; g += 64)
@@ -1511,9 +1654,10 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     // phase 1: queue entries from the shared counter; phase 2: worker list
     bool phase1 = true;
     TaskArgs t;
-    while (!w.abort && next_task(p, w, phase1, t)) {
+    SmallJob fj;
+    while (!w.abort && next_task(p, w, phase1, t, fj)) {
         begin_task(p, w, t.root);
-        run_task(p, w, t.root, t.nu, t.L, t.ks, t.rs, t.c, t.C);
+        run_task(p, w, t.root, t.nu, t.L, t.ks, t.rs, t.c, t.C, t.kind == kMboxFold, fj);
         finish_task(p, w, t.root, t.nu, t.L, t.rs, t.c, t.C);
     }
     flush_graph(p, w);
@@ -1535,6 +1679,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         atomicAdd(&p.acc[2 + MCE_STAT_DONATE_NS], (unsigned long long)S.stat[S_DONATE]);
         atomicAdd(&p.acc[2 + MCE_STAT_POP_FAILS], (unsigned long long)S.stat[S_POPFAIL]);
         atomicAdd(&p.acc[2 + MCE_STAT_XCOL_WORDS], (unsigned long long)S.stat[S_XCOLW]);
+        atomicAdd(&p.acc[2 + MCE_STAT_FOLD_DONATIONS], (unsigned long long)S.stat[S_FOLDDON]);
     }
 }
 
@@ -1777,6 +1922,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint64_t off_P = off; off = align_up(off + (uint64_t)ucap * 4, 256);
     const uint64_t off_XP = off; off = align_up(off + (uint64_t)ucap * 4, 256);
     const uint64_t off_R = off; off = align_up(off + (uint64_t)rcap * 4, 256);
+    const uint64_t off_fr = off; off = align_up(off + kFrameBytes, 256);
     const uint64_t off_xr = off; off = align_up(off + (uint64_t)xcap * 4, 256);
     const uint64_t off_xx = off; off = align_up(off + (uint64_t)xcap * 4, 256);
     const uint64_t off_flag = off; off = align_up(off + ((uint64_t)xcap / 64 + 2) * 8, 256);
@@ -1869,6 +2015,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.off_P = off_P;
     p.off_XP = off_XP;
     p.off_R = off_R;
+    p.off_fr = off_fr;
     p.off_xr = off_xr;
     p.off_xx = off_xx;
     p.off_flag = off_flag;

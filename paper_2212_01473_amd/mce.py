@@ -43,7 +43,7 @@ F_TASK_LOG = 0x100
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
               "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words",
               "busy_ns", "max_task_ns", "xrow_tasks", "build_ns", "task_log", "donate_ns",
-              "pop_fails", "xcol_words"]
+              "pop_fails", "xcol_words", "fold_donations"]
 
 FULL = 0xFFFFFFFF
 
