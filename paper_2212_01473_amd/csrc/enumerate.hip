@@ -1195,12 +1195,25 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
 // with cols also sets bit i of column j).  All
 // 64 lanes take consecutive entries of the concatenated lists, so loads are
 // independent and lanes stay busy across short lists.
+// Entry r of the scanned list (row r) has universe vertex a as a later neighbour.
+__device__ __forceinline__ void set_pair(uint64_t* rows, uint64_t* cols, int mode, uint32_t r, uint32_t a, uint32_t ws,
+                                         uint32_t cws)
+{
+    atomicOr((unsigned long long*)&rows[(uint64_t)r * ws + (a >> 6)], 1ull << (a & 63));
+    if (mode == 0)
+        atomicOr((unsigned long long*)&rows[(uint64_t)a * ws + (r >> 6)], 1ull << (r & 63));
+    else if (cols)
+        atomicOr((unsigned long long*)&cols[(uint64_t)a * cws + (r >> 6)], 1ull << (r & 63));
+}
+
 __device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uint32_t cnt, uint32_t nu, uint64_t* rows,
                                            uint32_t ws, uint64_t* cols, uint32_t cws)
 {
     const uint32_t lane = lane_id();
     const uint32_t* U = w.uarr;
+    if (nu == 0) return;  // no entry can be found in an empty universe
     const uint32_t umin = U[0], umax = U[nu - 1];
+    const uint32_t ustep = 1u << (31 - __builtin_clz(nu));  // largest power of two <= nu
     for (uint32_t g0 = 0; g0 < cnt; g0 += 64) {
         uint32_t i = g0 + lane;
         uint32_t beg = 0, len = 0;
@@ -1216,32 +1229,29 @@ __device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uin
         wave_mem_sync();
         stat_add(S_EDGES, total);
         const uint32_t nrows = min(64u, cnt - g0);
-        for (uint32_t t = 0; t < total; t += 64) {
-            uint32_t f = t + lane;
-            if (f < total) {
-                uint32_t lo = 0, hi = nrows;  // last row with soff <= f
-                while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (S.soff[mid] <= f) lo = mid;
-                    else hi = mid;
+        // two entries per lane and step (f and f + 64), so the two dependent
+        // chains of LDS searches and the list load overlap; the searches are
+        // binary liftings with the same trip count in every lane
+        for (uint32_t t = 0; t < total; t += 128) {
+            const uint32_t fA = t + lane, fB = fA + 64;
+            const bool okA = fA < total, okB = fB < total;
+            uint32_t rA = 0, rB = 0;  // last row with soff <= f
+            for (uint32_t step = 32; step; step >>= 1) {
+                if (rA + step < nrows && S.soff[rA + step] <= fA) rA += step;
+                if (rB + step < nrows && S.soff[rB + step] <= fB) rB += step;
+            }
+            const uint32_t xA = okA ? p.oc[S.sbeg[rA] + (fA - S.soff[rA])] : 0u;
+            const uint32_t xB = okB ? p.oc[S.sbeg[rB] + (fB - S.soff[rB])] : 0u;
+            const bool inA = okA && xA >= umin && xA <= umax;
+            const bool inB = okB && xB >= umin && xB <= umax;
+            if (inA || inB) {
+                uint32_t aA = 0, aB = 0;  // entries of U below x
+                for (uint32_t step = ustep; step; step >>= 1) {
+                    if (aA + step <= nu && U[aA + step - 1] < xA) aA += step;
+                    if (aB + step <= nu && U[aB + step - 1] < xB) aB += step;
                 }
-                uint32_t x = p.oc[S.sbeg[lo] + (f - S.soff[lo])];
-                if (x >= umin && x <= umax) {
-                    uint32_t a = 0, b = nu;
-                    while (a < b) {
-                        uint32_t mid = (a + b) >> 1;
-                        if (U[mid] < x) a = mid + 1;
-                        else b = mid;
-                    }
-                    if (a < nu && U[a] == x) {
-                        uint32_t r = g0 + lo;
-                        atomicOr((unsigned long long*)&rows[(uint64_t)r * ws + (a >> 6)], 1ull << (a & 63));
-                        if (mode == 0)
-                            atomicOr((unsigned long long*)&rows[(uint64_t)a * ws + (r >> 6)], 1ull << (r & 63));
-                        else if (cols)
-                            atomicOr((unsigned long long*)&cols[(uint64_t)a * cws + (r >> 6)], 1ull << (r & 63));
-                    }
-                }
+                if (inA && aA < nu && U[aA] == xA) set_pair(rows, cols, mode, g0 + rA, aA, ws, cws);
+                if (inB && aB < nu && U[aB] == xB) set_pair(rows, cols, mode, g0 + rB, aB, ws, cws);
             }
         }
         wave_mem_sync();
