@@ -69,18 +69,26 @@ __device__ bool row_contains(const uint32_t* __restrict__ rp, const uint32_t* __
     return false;
 }
 
-// One wave per row: range, self-loop and strict order of every entry, and the
-// reverse of every arc.  Unless `full`, only arcs v -> u with v < u are looked
-// up in u's row, and the arcs with v < u and with v > u are counted (counts[0],
-// counts[1]): with strictly increasing rows the lookups map those arcs
-// injectively onto reversed arcs, so equal counts make the map a bijection and
-// the graph symmetric.  A full pass locates an offending arc when they differ.
+// One wave per row: range, self-loop and strict order of every entry.  The
+// first pass (full = 0) does no lookups: it counts the arcs v -> u with v < u
+// and with v > u (counts[0], counts[1]) and sums a 64-bit mix of the unordered
+// pair {v, u} over each kind (counts[2], counts[3]).  With strictly increasing
+// rows each kind is a set of pairs, and the graph is symmetric iff the two sets
+// are equal; unequal sets give equal counts and equal sums only if the mixes of
+// their differing pairs cancel mod 2^64.  When the pass disagrees, a full pass
+// looks up the reverse of every arc in the other row and names the first
+// offending arc.
+__device__ inline uint64_t pair_mix(uint32_t a, uint32_t b)
+{
+    return fmix64((((uint64_t)a << 32) | b) * kGamma + kGamma);
+}
+
 __global__ void k_validate_cols(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
                                 uint32_t n, unsigned long long* err, unsigned long long* counts, int full)
 {
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
-    unsigned long long up = 0, down = 0;
+    unsigned long long up = 0, down = 0, hup = 0, hdown = 0;
     for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
         uint32_t beg = rp[v], end = rp[v + 1];
         for (uint32_t e = beg + lane; e < end; e += 64) {
@@ -89,20 +97,31 @@ __global__ void k_validate_cols(const uint32_t* __restrict__ rp, const uint32_t*
             if (u >= n) kind = kErrColRange;
             else if (u == v) kind = kErrSelfLoop;
             else if (e > beg && ci[e - 1] >= u) kind = kErrOrder;
-            else if ((full || u > v) && !row_contains(rp, ci, u, (uint32_t)v)) kind = kErrAsym;
+            else if (full && !row_contains(rp, ci, u, (uint32_t)v)) kind = kErrAsym;
             if (kind)
                 atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kind);
-            up += u > v;
-            down += u < v;
+            if (!full && u < n) {
+                if (u > v) {
+                    ++up;
+                    hup += pair_mix((uint32_t)v, u);
+                } else {
+                    ++down;
+                    hdown += pair_mix(u, (uint32_t)v);
+                }
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
         up += __shfl_xor(up, off, 64);
         down += __shfl_xor(down, off, 64);
+        hup += __shfl_xor(hup, off, 64);
+        hdown += __shfl_xor(hdown, off, 64);
     }
     if (!full && lane == 0 && (up | down)) {
         atomicAdd(&counts[0], up);
         atomicAdd(&counts[1], down);
+        atomicAdd(&counts[2], hup);
+        atomicAdd(&counts[3], hdown);
     }
 }
 
@@ -492,21 +511,21 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
             return MCE_ERR_INVALID_GRAPH;
         }
         {
-            uint64_t z[2] = {0, 0};
-            MCE_HIP_TRY(hipMemcpyAsync(dmisc + 1, z, 16, hipMemcpyHostToDevice, s));
+            uint64_t z[4] = {0, 0, 0, 0};
+            MCE_HIP_TRY(hipMemcpyAsync(dmisc + 1, z, 32, hipMemcpyHostToDevice, s));
         }
         k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 0);
         MCE_HIP_TRY(hipGetLastError());
-        MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 24, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 40, hipMemcpyDeviceToHost, s));
         MCE_HIP_TRY(hipStreamSynchronize(s));
-        if (hmisc[0] == ~0ull && hmisc[1] != hmisc[2]) {
-            // some arc v -> u with v > u has no reverse: find the first one
+        if (hmisc[0] == ~0ull && (hmisc[1] != hmisc[2] || hmisc[3] != hmisc[4])) {
+            // the arcs in the two directions differ: find the first arc without a reverse
             k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 1);
             MCE_HIP_TRY(hipGetLastError());
             MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
             MCE_HIP_TRY(hipStreamSynchronize(s));
             if (hmisc[0] == ~0ull) {
-                set_error("invalid graph: asymmetric (arc counts differ)");
+                set_error("invalid graph: asymmetric (the arc sets in the two directions differ)");
                 return MCE_ERR_INVALID_GRAPH;
             }
         }

@@ -290,10 +290,15 @@ def _bad_graphs():
     # reverse, only a v > u arc lacks one (found by the arc counts)
     down_rp = np.array([0, 1, 3, 5], dtype=np.uint32)
     down_ci = np.array([1, 0, 2, 0, 1], dtype=np.uint32)
-    return [(rp, asym), (rp, unsorted), (rp, selfloop), (rp, oob), (rp, dup), (badrp, ci), (down_rp, down_ci)]
+    # arcs 0-1 both ways, 2 -> 3 and 3 -> 1 without reverses: as many arcs go up
+    # as down, but the two sets of pairs differ (found by the pair sums)
+    swap_rp = np.array([0, 1, 2, 3, 4], dtype=np.uint32)
+    swap_ci = np.array([1, 0, 3, 1], dtype=np.uint32)
+    return [(rp, asym), (rp, unsorted), (rp, selfloop), (rp, oob), (rp, dup), (badrp, ci), (down_rp, down_ci),
+            (swap_rp, swap_ci)]
 
 
-@pytest.mark.parametrize("i", range(7))
+@pytest.mark.parametrize("i", range(8))
 def test_invalid_graphs_rejected(gpu_lib, i):
     rp, ci = _bad_graphs()[i]
     with pytest.raises(gpu_lib.MCEError) as e:
