@@ -83,46 +83,83 @@ __device__ inline uint64_t pair_mix(uint32_t a, uint32_t b)
     return fmix64((((uint64_t)a << 32) | b) * kGamma + kGamma);
 }
 
+constexpr uint32_t kLongRow = 2048;  // longer rows are deferred to a workgroup each
+
+// Sum four 64-bit counters over the block, one atomic per counter.
+__device__ inline void block_add4(unsigned long long (&a)[4], unsigned long long* counts)
+{
+    const uint32_t lane = lane_id();
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_xor(a[k], off, 64);
+    __shared__ unsigned long long part[4][16];
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) part[k][threadIdx.x >> 6] = a[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long t = 0;
+        for (uint32_t k = 0; k < blockDim.x / 64; ++k) t += part[threadIdx.x][k];
+        if (t) atomicAdd(&counts[threadIdx.x], t);
+    }
+}
+
+// Checks of entry e of row v (row starts at beg); a[] gathers the counts and
+// pair sums of the first pass.
+__device__ __forceinline__ void check_arc(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
+                                          uint32_t v, uint32_t beg, uint32_t e, int full, unsigned long long* err,
+                                          unsigned long long (&a)[4])
+{
+    uint32_t u = ci[e];
+    uint32_t kind = 0;
+    if (u >= n) kind = kErrColRange;
+    else if (u == v) kind = kErrSelfLoop;
+    else if (e > beg && ci[e - 1] >= u) kind = kErrOrder;
+    else if (full && !row_contains(rp, ci, u, v)) kind = kErrAsym;
+    if (kind) atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kind);
+    if (!full && u < n) {
+        if (u > v) {
+            a[0] += 1;
+            a[2] += pair_mix(v, u);
+        } else {
+            a[1] += 1;
+            a[3] += pair_mix(u, v);
+        }
+    }
+}
+
+// One wave per row; in the first pass rows longer than kLongRow are listed in
+// defer (count *ndefer) for k_validate_long, so no wave walks a hub row alone.
 __global__ void k_validate_cols(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
-                                uint32_t n, unsigned long long* err, unsigned long long* counts, int full)
+                                uint32_t n, unsigned long long* err, unsigned long long* counts, int full,
+                                uint32_t* __restrict__ defer, uint32_t* __restrict__ ndefer)
 {
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
-    unsigned long long up = 0, down = 0, hup = 0, hdown = 0;
+    unsigned long long a[4] = {0, 0, 0, 0};
     for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
         uint32_t beg = rp[v], end = rp[v + 1];
-        for (uint32_t e = beg + lane; e < end; e += 64) {
-            uint32_t u = ci[e];
-            uint32_t kind = 0;
-            if (u >= n) kind = kErrColRange;
-            else if (u == v) kind = kErrSelfLoop;
-            else if (e > beg && ci[e - 1] >= u) kind = kErrOrder;
-            else if (full && !row_contains(rp, ci, u, (uint32_t)v)) kind = kErrAsym;
-            if (kind)
-                atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kind);
-            if (!full && u < n) {
-                if (u > v) {
-                    ++up;
-                    hup += pair_mix((uint32_t)v, u);
-                } else {
-                    ++down;
-                    hdown += pair_mix(u, (uint32_t)v);
-                }
-            }
+        if (!full && end - beg > kLongRow) {
+            if (lane == 0) defer[atomicAdd(ndefer, 1u)] = (uint32_t)v;
+            continue;
         }
+        for (uint32_t e = beg + lane; e < end; e += 64) check_arc(rp, ci, n, (uint32_t)v, beg, e, full, err, a);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        up += __shfl_xor(up, off, 64);
-        down += __shfl_xor(down, off, 64);
-        hup += __shfl_xor(hup, off, 64);
-        hdown += __shfl_xor(hdown, off, 64);
+    if (full) return;
+    block_add4(a, counts);
+}
+
+// The deferred long rows of the first pass, one workgroup per row.
+__global__ void k_validate_long(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
+                                unsigned long long* err, unsigned long long* counts,
+                                const uint32_t* __restrict__ defer, const uint32_t* __restrict__ ndefer)
+{
+    unsigned long long a[4] = {0, 0, 0, 0};
+    const uint32_t cnt = *ndefer;
+    for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint32_t v = defer[i];
+        const uint32_t beg = rp[v], end = rp[v + 1];
+        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) check_arc(rp, ci, n, v, beg, e, 0, err, a);
     }
-    if (!full && lane == 0 && (up | down)) {
-        atomicAdd(&counts[0], up);
-        atomicAdd(&counts[1], down);
-        atomicAdd(&counts[2], hup);
-        atomicAdd(&counts[3], hdown);
-    }
+    block_add4(a, counts);
 }
 
 // ---- peel ----------------------------------------------------------------------
@@ -389,16 +426,39 @@ __global__ void k_union_cols(const uint32_t* __restrict__ ci_cat, const uint32_t
 }
 
 // one wave per input vertex: out/in degree in rank space
+// Out- and in-degree in the order of every vertex (one wave per row; rows
+// longer than kLongRow are listed in defer for k_orient_count_long) and their
+// maxima (maxes[0], maxes[1]).
+__device__ inline void block_max2(uint32_t m0, uint32_t m1, unsigned int* maxes)
+{
+    __shared__ uint32_t part[2][16];
+    if (lane_id() == 0) {
+        part[0][threadIdx.x >> 6] = m0;
+        part[1][threadIdx.x >> 6] = m1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        uint32_t t = 0;
+        for (uint32_t k = 0; k < blockDim.x / 64; ++k) t = max(t, part[threadIdx.x][k]);
+        if (t) atomicMax(&maxes[threadIdx.x], t);
+    }
+}
+
 __global__ void k_orient_count(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
                                const uint32_t* __restrict__ rank, uint32_t* __restrict__ outdeg,
-                               uint32_t* __restrict__ indeg, unsigned int* __restrict__ maxes)
+                               uint32_t* __restrict__ indeg, unsigned int* __restrict__ maxes,
+                               uint32_t* __restrict__ defer, uint32_t* __restrict__ ndefer)
 {
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
-    uint32_t max_out = 0, max_in = 0;  // this wave's, one atomic each at the end
+    uint32_t max_out = 0, max_in = 0;
     for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
-        uint32_t rv = rank[v];
         uint32_t beg = rp[v], end = rp[v + 1];
+        if (end - beg > kLongRow) {
+            if (lane == 0) defer[atomicAdd(ndefer, 1u)] = (uint32_t)v;
+            continue;
+        }
+        uint32_t rv = rank[v];
         uint32_t cnt = 0;
         for (uint32_t e = beg + lane; e < end; e += 64) cnt += rank[ci[e]] > rv;
         for (int off = 32; off > 0; off >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, off);
@@ -410,10 +470,37 @@ __global__ void k_orient_count(const uint32_t* __restrict__ rp, const uint32_t* 
         max_out = max(max_out, cnt);
         max_in = max(max_in, in);
     }
-    if (lane == 0 && (max_out | max_in)) {
-        atomicMax(&maxes[0], max_out);
-        atomicMax(&maxes[1], max_in);
+    block_max2(max_out, max_in, maxes);
+}
+
+// The deferred long rows, one workgroup per row.
+__global__ void k_orient_count_long(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
+                                    const uint32_t* __restrict__ rank, uint32_t* __restrict__ outdeg,
+                                    uint32_t* __restrict__ indeg, unsigned int* __restrict__ maxes,
+                                    const uint32_t* __restrict__ defer, const uint32_t* __restrict__ ndefer)
+{
+    __shared__ uint32_t part[16];
+    uint32_t max_out = 0, max_in = 0;
+    const uint32_t total = *ndefer;
+    for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+        const uint32_t v = defer[i];
+        const uint32_t beg = rp[v], end = rp[v + 1], rv = rank[v];
+        uint32_t cnt = 0;
+        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) cnt += rank[ci[e]] > rv;
+        for (int off = 32; off > 0; off >>= 1) cnt += (uint32_t)__shfl_xor((int)cnt, off);
+        if (lane_id() == 0) part[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        uint32_t out = 0;
+        for (uint32_t k = 0; k < blockDim.x / 64; ++k) out += part[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            outdeg[rv] = out;
+            indeg[rv] = (end - beg) - out;
+        }
+        max_out = max(max_out, out);
+        max_in = max(max_in, (end - beg) - out);
     }
+    block_max2(max_out, max_in, maxes);
 }
 
 __global__ void k_orient_fill(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
@@ -511,16 +598,23 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
             return MCE_ERR_INVALID_GRAPH;
         }
         {
-            uint64_t z[4] = {0, 0, 0, 0};
-            MCE_HIP_TRY(hipMemcpyAsync(dmisc + 1, z, 32, hipMemcpyHostToDevice, s));
+            uint64_t z[5] = {0, 0, 0, 0, 0};
+            MCE_HIP_TRY(hipMemcpyAsync(dmisc + 1, z, 40, hipMemcpyHostToDevice, s));
         }
-        k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 0);
+        DevBuf defer;
+        if ((st = defer.alloc(((size_t)nnz / kLongRow + 1) * 4)) != MCE_OK) return st;
+        uint32_t* ndefer = reinterpret_cast<uint32_t*>(dmisc + 5);
+        k_validate_cols<<<blocks_for(n, 4, 1024), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 0,
+                                                                 defer.as<uint32_t>(), ndefer);
+        MCE_HIP_TRY(hipGetLastError());
+        k_validate_long<<<256, 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, defer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
         MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 40, hipMemcpyDeviceToHost, s));
         MCE_HIP_TRY(hipStreamSynchronize(s));
         if (hmisc[0] == ~0ull && (hmisc[1] != hmisc[2] || hmisc[3] != hmisc[4])) {
             // the arcs in the two directions differ: find the first arc without a reverse
-            k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 1);
+            k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 1, nullptr,
+                                                                     nullptr);
             MCE_HIP_TRY(hipGetLastError());
             MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
             MCE_HIP_TRY(hipStreamSynchronize(s));
@@ -674,13 +768,21 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     if ((st = g.op.alloc((nn + 1) * 4)) != MCE_OK) return st;
     if ((st = g.ip.alloc((nn + 1) * 4)) != MCE_OK) return st;
     {
-        uint64_t z[4] = {0, 0, 0, 0};
-        MCE_HIP_TRY(hipMemcpyAsync(dmisc, z, 32, hipMemcpyHostToDevice, s));
+        uint64_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        MCE_HIP_TRY(hipMemcpyAsync(dmisc, z, 64, hipMemcpyHostToDevice, s));
     }
+    DevBuf odefer;
+    if ((st = odefer.alloc(((size_t)g.nnz / kLongRow + 1) * 4)) != MCE_OK) return st;
     if (n) {
-        k_orient_count<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(),
+        uint32_t* ndefer = reinterpret_cast<uint32_t*>(dmisc) + 12;
+        k_orient_count<<<blocks_for(n, 4, 1024), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(),
                                                                 outdeg.as<uint32_t>(), indeg.as<uint32_t>(),
-                                                                reinterpret_cast<unsigned int*>(dmisc));
+                                                                reinterpret_cast<unsigned int*>(dmisc),
+                                                                odefer.as<uint32_t>(), ndefer);
+        MCE_HIP_TRY(hipGetLastError());
+        k_orient_count_long<<<256, 256, 0, s>>>(rp, ci, rank.as<uint32_t>(), outdeg.as<uint32_t>(),
+                                                  indeg.as<uint32_t>(), reinterpret_cast<unsigned int*>(dmisc),
+                                                  odefer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
     }
     DevBuf stmp;
