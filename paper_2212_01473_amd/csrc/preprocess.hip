@@ -704,12 +704,38 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
             set_error(std::string("peel graph capture: ") + hipGetErrorString(e));
             return MCE_ERR_DEVICE;
         }
-        while (true) {
-            e = hipGraphLaunch(exec, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(&hs, ps, sizeof(hs), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess || hs.done) break;
+        // two replays in flight: the state after replay i is read while
+        // replay i + 1 runs (pinned copies, one event each), so the device
+        // does not wait for the host between replays; a replay after the
+        // last round does nothing
+        PeelState* hst = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        if (e == hipSuccess) e = hipHostMalloc((void**)&hst, 2 * sizeof(PeelState), hipHostMallocDefault);
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipEventCreateWithFlags(&ev[b], hipEventDisableTiming);
+        auto replay = [&](int b) {
+            hipError_t r = hipGraphLaunch(exec, s);
+            if (r == hipSuccess) r = hipMemcpyAsync(&hst[b], ps, sizeof(PeelState), hipMemcpyDeviceToHost, s);
+            if (r == hipSuccess) r = hipEventRecord(ev[b], s);
+            return r;
+        };
+        // every step removes a frontier or selects one, so 2n steps suffice
+        const size_t max_replays = 2 * (size_t)n / kPeelSteps + 4;
+        bool finished = false;
+        if (e == hipSuccess) e = replay(0);
+        for (size_t i = 0, b = 0; e == hipSuccess && i < max_replays; ++i, b ^= 1) {
+            e = replay((int)(b ^ 1));
+            if (e == hipSuccess) e = hipEventSynchronize(ev[b]);
+            if (e == hipSuccess && hst[b].done) {
+                finished = true;
+                break;
+            }
         }
+        if (e == hipSuccess && !finished) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) hs = *(const PeelState*)(hst[0].done ? &hst[0] : &hst[1]);
+        for (int b = 0; b < 2; ++b)
+            if (ev[b]) (void)hipEventDestroy(ev[b]);
+        if (hst) (void)hipHostFree(hst);
         cleanup();
         if (e != hipSuccess) {
             set_error(std::string("peel: ") + hipGetErrorString(e));
