@@ -163,7 +163,7 @@ typedef struct {
     uint64_t* root_hash;        /* MCE_F_ROOT_STATS: device uint64[n] */
     uint64_t* root_nodes;       /* MCE_F_ROOT_STATS: device uint64[n] (search-tree nodes) */
     uint32_t xrow_ratio;        /* build X bitmap rows for a task when |X| <= ratio * max(|P u X_P|, 64);
-                                   0 = default 8; larger X uses lookups in the original graph */
+                                   0 = default 32; larger X uses lookups in the original graph */
     uint32_t xrow_min_u;        /* ... and only when |P u X_P| >= xrow_min_u; 0 = default 16 */
     uint64_t xrow_budget_words; /* X bitmap rows per workgroup, 64-bit words; 0 = default 2^18 */
     uint32_t donate_every;      /* offer every k-th eligible branch to the worker list; 0 = 1 */

@@ -411,7 +411,7 @@ mce_status mce_autotune(mce_graph* g, const mce_options* base, mce_options* tune
         {&mce_options::bitmap_max_p, {64, 128, 256}},
         {&mce_options::wg_per_cu, {0, 4, 2}},
         {&mce_options::donate_max_depth, {0, 3}},
-        {&mce_options::xrow_ratio, {2, 8, 32}},
+        {&mce_options::xrow_ratio, {8, 32, 128}},
     };
     for (uint32_t pass = 0; pass < passes; ++pass) {
         for (const Knob& k : knobs) {

@@ -150,7 +150,7 @@ struct EnumConfig {
     uint64_t* stream_offsets = nullptr;
     uint64_t stream_ocap = 0;
     uint64_t xrow_budget_words = 1ull << 18;  // X rows per workgroup (words)
-    uint32_t xrow_ratio = 8;                 // X rows when |X| <= ratio * max(|U|, 64)
+    uint32_t xrow_ratio = 32;                // X rows when |X| <= ratio * max(|U|, 64)
     uint32_t xrow_min_u = 16;                // ... and |U| >= xrow_min_u
     const void* model = nullptr;             // MLP weights (device) for MCE_F_LEARNED_ORDER
     uint32_t split_top = 0;

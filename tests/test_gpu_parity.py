@@ -132,6 +132,9 @@ def test_chung_lu_planted_small(gpu_lib):
     dict(bitmap_max_p=64, donate_min_p=2, wg_per_cu=2),
     dict(flags=0x40),  # reverse degeneracy order
     dict(donate_min_p=10, bitmap_max_p=256),  # the donation size of Section III-C
+    dict(xrow_min_u=4096),  # no X rows: X_X as the partitioned index list with lookups
+    dict(xrow_min_u=4096, donate_min_p=2, wg_per_cu=1),
+    dict(xrow_ratio=1, bitmap_max_p=64),
 ])
 def test_knobs_invariant(gpu_lib, kw):
     g = I.chung_lu_planted(n=8000, wmax=400, n_cliques=30, cmin=15, cmax=45, pool=300, seed=11)
