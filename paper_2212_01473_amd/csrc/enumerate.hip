@@ -511,7 +511,8 @@ __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child
 }
 
 // Finish a donation to r: R (this workgroup's R[0, rs) plus vb), header, one
-// release fence, then the flag.  P, X_P and X_X were written by the caller.
+// release fence, then the flag.  The caller wrote the branch itself: the P,
+// X_P and X_X lists (kMboxLists) or a fold frame (kMboxFold).
 __device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
                              uint64_t ks, uint32_t np, uint32_t nxp, uint32_t nxx, uint32_t kind)
 {
@@ -1022,7 +1023,14 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
                 if ((cw >> lane) & 1ull) {
                     uint32_t sc = 0;
                     const uint64_t* ri = rows + (uint64_t)i * ws;
-                    for (uint32_t q = 0; q < W; ++q) sc += (uint32_t)__popcll(rl64(P, q) & ri[q]);
+                    // eight row words per round trip: all loads issue before the first use
+                    for (uint32_t q = 0; q < W; q += 8) {
+                        uint64_t r[8];
+#pragma unroll
+                        for (uint32_t k = 0; k < 8; ++k) r[k] = q + k < W ? ri[q + k] : 0ull;
+#pragma unroll
+                        for (uint32_t k = 0; k < 8; ++k) sc += (uint32_t)__popcll(rl64(P, (q + k) & 63u) & r[k]);
+                    }
                     best = max(best, (sc << 13) | (8191u - i));
                 }
             }
