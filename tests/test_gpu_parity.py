@@ -149,6 +149,16 @@ def test_worker_list_donates(gpu_lib):
     assert got.stats["donations"] > 0
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(xrow_min_u=4096)])
+def test_fold_frames_carry_donations(gpu_lib, kw):
+    # small universes: donated branches travel as register frames, which the
+    # receiver runs without building bitmaps; without X rows only branches
+    # with an empty X_X can fold
+    g = I.chung_lu_planted(n=8000, wmax=400, n_cliques=30, cmin=15, cmax=45, pool=300, seed=11)
+    got, _ = check(gpu_lib, g, donate_min_p=2, wg_per_cu=1, **kw)
+    assert 0 < got.stats["fold_donations"] <= got.stats["donations"]
+
+
 def test_custom_order(gpu_lib):
     import torch
 

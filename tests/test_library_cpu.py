@@ -128,6 +128,16 @@ def test_options_carry_learned_flags():
         mce.make_options(split=True)
 
 
+def test_stat_names_cover_header_indices():
+    # one binding name per MCE_STAT_* index, in index order, within stats[]
+    text = open(HEADER).read()
+    idx = sorted(int(v) for v in re.findall(r"MCE_STAT_\w+\s*=\s*(\d+)", text))
+    assert idx == list(range(len(idx)))
+    assert len(mce.STAT_NAMES) == len(idx)
+    size = int(re.search(r"uint64_t stats\[(\d+)\]", text).group(1))
+    assert len(idx) <= size
+
+
 def test_enumeration_kernel_resources():
     """The build records each kernel's resources from the compiler; the DFS
     kernel must keep 3 wavefronts per SIMD and use no scratch (a silent
