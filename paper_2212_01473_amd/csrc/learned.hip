@@ -74,6 +74,7 @@ __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
             const uint32_t pmax = P[np - 1];
+            const uint32_t pstep = 1u << (31 - __builtin_clz(np));  // largest power of two <= np
             for (uint32_t a0 = 0; a0 < np; a0 += 64) {
                 uint32_t a = a0 + lane, beg = 0, len = 0;
                 if (a < np) {
@@ -94,22 +95,29 @@ __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 const uint32_t nrows = min(64u, np - a0);
-                for (uint32_t f = lane; f < total; f += 64) {
-                    uint32_t lo = 0, hi = nrows;  // last row with soff <= f
-                    while (hi - lo > 1) {
-                        uint32_t mid = (lo + hi) >> 1;
-                        if (soff[wv][mid] <= f) lo = mid;
-                        else hi = mid;
+                // two entries per lane and step (f and f + 64); both searches are
+                // binary liftings with the same trip count in every lane, so the
+                // two chains of LDS loads and the list loads overlap
+                for (uint32_t t = 0; t < total; t += 128) {
+                    const uint32_t fA = t + lane, fB = fA + 64;
+                    const bool okA = fA < total, okB = fB < total;
+                    uint32_t rA = 0, rB = 0;  // last row with soff <= f
+                    for (uint32_t step = 32; step; step >>= 1) {
+                        if (rA + step < nrows && soff[wv][rA + step] <= fA) rA += step;
+                        if (rB + step < nrows && soff[wv][rB + step] <= fB) rB += step;
                     }
-                    uint32_t x = oc[sbeg[wv][lo] + (f - soff[wv][lo])];
-                    if (x <= pmax) {
-                        uint32_t l2 = a0 + lo + 1, h2 = np;
-                        while (l2 < h2) {
-                            uint32_t mid = (l2 + h2) >> 1;
-                            if (P[mid] < x) l2 = mid + 1;
-                            else h2 = mid;
+                    const uint32_t xA = okA ? oc[sbeg[wv][rA] + (fA - soff[wv][rA])] : 0u;
+                    const uint32_t xB = okB ? oc[sbeg[wv][rB] + (fB - soff[wv][rB])] : 0u;
+                    const bool inA = okA && xA <= pmax, inB = okB && xB <= pmax;
+                    if (inA || inB) {
+                        uint32_t aA = 0, aB = 0;  // entries of P below x
+                        for (uint32_t step = pstep; step; step >>= 1) {
+                            if (aA + step <= np && P[aA + step - 1] < xA) aA += step;
+                            if (aB + step <= np && P[aB + step - 1] < xB) aB += step;
                         }
-                        tri += l2 < np && P[l2] == x;
+                        // a later neighbour of P[a] found in P lies after position a
+                        tri += inA && aA < np && P[aA] == xA;
+                        tri += inB && aB < np && P[aB] == xB;
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
