@@ -10,10 +10,11 @@
 //     earlier neighbours).  It only shrinks with depth, so it is one index list
 //     partitioned in place with per-level end pointers (Section III-E, Fig. 2).
 //     Its adjacency to U is either looked up in the original graph (binary
-//     search in the sorted later-neighbour list of the X vertex) or, when the
-//     task is small enough, read from per-task bitmap rows "X rows" built once
-//     at task start (the full induced subgraph of Section III-D, restricted to
-//     X x U);
+//     search in the sorted later-neighbour list of the X vertex) or, when |X|
+//     is within the budgets, read from bitmaps built once at task start: X rows
+//     (X x U) for the register executors and X columns (U -> bitmap over X)
+//     for the mid executor, where a child's X_X is then one AND (the full
+//     induced subgraph of Section III-D, restricted to X x U);
 //   * pivots maximise |P n N(u)| (Tomita); candidates are P u X_P, plus the
 //     X_X vertices once they are folded into registers (below).
 //
@@ -23,15 +24,17 @@
 //          per-workgroup HBM scratch above the LDS budget); stack in HBM.
 //   list   |P u X_P| <= 64 with a long X_X: lane k holds the 64-bit row of
 //          local vertex k; P, X_P, branches are wave-uniform words; X_X stays
-//          an index list; stack in LDS.
+//          an index list; the stack lives in VGPR lanes (lane d = level d).
 //   folded |P u X_P| <= 64 and |X_X| <= 64 with X rows available: the X_X
-//          vertices get register rows too, so the search touches no memory
-//          except its LDS stack, and X_X vertices are pivot candidates.
+//          vertices get register rows too, so the search touches no memory;
+//          X_X vertices are pivot candidates; stack in VGPR lanes.
 //
 // Work distribution (Section III-C): phase 1 pops (root, split) entries from
 // a shared counter; phase 2 is the worker list: idle workgroups set their bit
-// in a bitmap, busy ones claim a set bit and hand the branch to its owner.  Results accumulate per graph
-// (several graphs are enumerated as one disjoint union in batched mode).
+// in a bitmap, busy ones claim a set bit and hand a branch to its owner, as
+// lists or, when it fits 64 vertices, as a fold frame of register rows.
+// Results accumulate per graph (several graphs are enumerated as one disjoint
+// union in batched mode).
 #include "mce_internal.h"
 
 namespace mce {
@@ -39,7 +42,7 @@ namespace mce {
 namespace {
 
 constexpr uint32_t kFlagIdle = 0u, kFlagTask = 1u, kFlagTerm = 2u;
-constexpr uint32_t kEmptySlot = 0xFFFFFFFFu;
+constexpr uint32_t kNoWorkgroup = 0xFFFFFFFFu;
 constexpr int kHistLds = 256;
 constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
@@ -431,7 +434,7 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
     return w;
 }
 
-// Claim an idle workgroup (or kEmptySlot).  All 64 lanes read one word of the
+// Claim an idle workgroup (or kNoWorkgroup).  All 64 lanes read one word of the
 // idle bitmap each, starting at a word that rotates per attempt; lane 0 then
 // clears a set bit of a non-empty word with one fetch-and, which either wins
 // that bit or returns the word's current value for the next try.  Donors start
@@ -445,22 +448,22 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
     w.don_t0 = uni64(now_ticks());
     const uint32_t q0 = (w.me + 7u * w.pops++) % nw;
     const uint32_t s = w.me & 63u;
-    uint32_t r = kEmptySlot;
+    uint32_t r = kNoWorkgroup;
     uint32_t tried = 0;
-    for (uint32_t base = 0; base < nw && r == kEmptySlot && tried < 4; base += 64) {
+    for (uint32_t base = 0; base < nw && r == kNoWorkgroup && tried < 4; base += 64) {
         const uint32_t k = base + lane;
         uint32_t q = q0 + k;
         if (q >= nw) q -= nw;
         uint64_t b = 0;
         if (k < nw) b = __hip_atomic_load(&p.idle_bits[q * kIdleStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint64_t nz = __ballot(b != 0);
-        while (nz != 0 && r == kEmptySlot && tried < 4) {
+        while (nz != 0 && r == kNoWorkgroup && tried < 4) {
             const uint32_t l = (uint32_t)__builtin_ctzll(nz);
             nz &= nz - 1;
             ++tried;
             uint64_t bw = rl64(b, l);
             const uint32_t qw = rl32(q, l);
-            uint32_t got = kEmptySlot;
+            uint32_t got = kNoWorkgroup;
             if (lane == 0) {
                 for (int t = 0; t < 3 && bw != 0; ++t) {
                     const uint64_t rot = s ? ((bw >> s) | (bw << (64u - s))) : bw;
@@ -474,7 +477,7 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
                     }
                     bw = old & ~m;
                 }
-                if (got != kEmptySlot) {
+                if (got != kNoWorkgroup) {
                     __hip_atomic_fetch_add(&p.ctrl->waiting, ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     // the receiver stops counting as idle before it is handed work
                     __hip_atomic_fetch_add(&p.ctrl->packed, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -483,7 +486,7 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
             r = uni(got);
         }
     }
-    if (r == kEmptySlot) {
+    if (r == kNoWorkgroup) {
         // skip the next offer: other donors emptied the bitmap first
         w.wl_seen = 0;
         stat_add(S_POPFAIL, 1);
@@ -691,7 +694,7 @@ __device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root
         uint32_t npc = (uint32_t)__popcll(Pc);
         if (donation_wanted(p, w, npc, B != 0, anc || depth > 0, depth)) {
             uint32_t r = wl_try_pop(p, w);
-            if (r != kEmptySlot) {
+            if (r != kNoWorkgroup) {
                 // the child keeps this universe and the members of X_X
                 Wg d = wg_view(p, r);
                 put_fold_frame(d, m, Pc, XPc, su, skey, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc), xrank,
@@ -828,7 +831,7 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
         uint32_t npc = (uint32_t)__popcll(Pc);
         if (donation_wanted(p, w, npc, B != 0, anc || depth > 0, depth)) {
             uint32_t r = wl_try_pop(p, w);
-            if (r != kEmptySlot) {
+            if (r != kNoWorkgroup) {
                 Wg d = wg_view(p, r);
                 if (lane < depth) w.R[rs0 + lane] = sV;
                 if (Lc <= 64 && (can_fold || Lc == 0)) {
@@ -1101,7 +1104,7 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
         }
         if (donation_wanted(p, w, npc, more_here, anc || depth > 0, depth)) {
             uint32_t r = wl_try_pop(p, w);
-            if (r != kEmptySlot) {
+            if (r != kNoWorkgroup) {
                 Wg d = wg_view(p, r);
                 if (npc + nxc <= 64 && (xb ? Lc <= 64 : Lc == 0)) {
                     // fold frame: the child re-indexed as for a hand-over to the folded executor
