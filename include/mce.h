@@ -136,6 +136,10 @@ mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t
 #define MCE_F_REVERSE_ORDER 0x40u  /* process roots in reverse degeneracy order */
 #define MCE_F_CUSTOM_ORDER  0x80u  /* process roots in the order given by opt->root_order */
 #define MCE_F_TASK_LOG      0x100u /* record tasks slower than opt->task_log_min_us in opt->task_log */
+#define MCE_F_L2_ROOTS      0x200u /* independent second-level subtrees (Algorithm 4): one task per edge
+                                      {v, w} with v a root of the window and w a later neighbour of v;
+                                      R = {v, w}, P = common neighbours after w, X = common neighbours
+                                      before w.  Same results; excludes MCE_F_LEARNED_ORDER */
 
 #define MCE_OPTIONS_VERSION 1u
 

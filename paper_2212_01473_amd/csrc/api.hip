@@ -108,6 +108,8 @@ mce_status config_from(const mce_options* opt, EnumConfig& cfg)
         return fail(MCE_ERR_INVALID_ARG, "MCE_F_SPLIT needs MCE_F_LEARNED_ORDER");
     if ((cfg.flags & MCE_F_LEARNED_ORDER) && (cfg.flags & (MCE_F_CUSTOM_ORDER | MCE_F_REVERSE_ORDER)))
         return fail(MCE_ERR_INVALID_ARG, "learned order excludes custom and reverse orders");
+    if ((cfg.flags & MCE_F_L2_ROOTS) && (cfg.flags & MCE_F_LEARNED_ORDER))
+        return fail(MCE_ERR_INVALID_ARG, "MCE_F_L2_ROOTS excludes the learned order");
     if (cfg.bitmap_max_p > 4096) return fail(MCE_ERR_INVALID_ARG, "bitmap_max_p must be <= 4096");
     return MCE_OK;
 }

@@ -88,6 +88,8 @@ struct Params {
     const uint32_t* gid;       // graph of each rank, or null (one graph)
     const uint32_t* roots;
     const uint32_t* splits;    // (C << 16) | c per queue entry, or null
+    const uint32_t* l2v;       // second-level tasks: root rank per queue entry, or null
+    const uint32_t* l2e;       // ... and the edge index of its later neighbour in oc
     uint32_t nroots;
     Ctrl* ctrl;
     unsigned long long* acc;   // kernel-wide statistics
@@ -1404,6 +1406,11 @@ __device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, 
         w.have_xrows = L > 0;
         j = fj;
         ex = kExFold;
+    } else if (nu == 0) {
+        // a second-level task with no common later neighbour: R itself is
+        // maximal iff X is empty too
+        if (L == 0) report(p, w, rs, ks);
+        return;
     } else {
         ex = build_task(p, w, nu, L, ks, rs, C, j, rows, ws);
     }
@@ -1460,6 +1467,68 @@ __device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t 
     if (t.C == 0) t.C = 1;
     t.ks = p.vkey[v];
     t.kind = kMboxLists;
+    return t;
+}
+
+// Second-level subtree of the edge {v, u} (Algorithm 4), u = oc[e] a later
+// neighbour of root v: R = {v, u}; P = the common neighbours ordered after u
+// (later neighbours of v after u that are later neighbours of u, ascending);
+// X = the common neighbours ordered before u (earlier neighbours of v, and
+// later ones before u, that have u as a later neighbour).  Every X vertex is
+// an earlier neighbour of u, so |X| <= the in-degree bound of the scratch.
+__device__ __forceinline__ TaskArgs setup_l2(const Params& p, Wg& w, uint32_t v, uint32_t e)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t u = p.oc[e];
+    const uint32_t beg = p.op[v], end = p.op[v + 1];
+    uint32_t np = 0;
+    for (uint32_t b = e + 1; b < end; b += 64) {
+        const uint32_t i = b + lane;
+        uint32_t x = 0;
+        bool in = false;
+        if (i < end) {
+            x = p.oc[i];
+            in = has_later(p, u, x, w.probes);
+        }
+        const uint64_t m = __ballot(in);
+        if (in) w.uarr[np + prefix_popc(m)] = x;
+        np += (uint32_t)__popcll(m);
+    }
+    const uint32_t ib = p.ip[v], ni = p.ip[v + 1] - ib;
+    const uint32_t total = ni + (e - beg);
+    uint32_t nx = 0;
+    for (uint32_t b = 0; b < total; b += 64) {
+        const uint32_t i = b + lane;
+        uint32_t x = 0;
+        bool in = false;
+        if (i < total) {
+            x = i < ni ? p.ic[ib + i] : p.oc[beg + (i - ni)];
+            in = has_later(p, x, u, w.probes);
+        }
+        const uint64_t m = __ballot(in);
+        if (in) w.xr[nx + prefix_popc(m)] = x;
+        nx += (uint32_t)__popcll(m);
+    }
+    stat_add(S_ROOTW, (end - e - 1) + total);
+    if (lane == 0) {
+        w.R[0] = v;
+        w.R[1] = u;
+    }
+    const uint32_t W = (np + 63) >> 6;
+    for (uint32_t q = lane; q < W; q += 64) {
+        S.pw[q] = low_mask(np - q * 64);
+        S.xw[q] = 0;
+    }
+    wave_mem_sync();
+    TaskArgs t;
+    t.root = v;
+    t.nu = np;
+    t.L = nx;
+    t.rs = 2;
+    t.c = 0;
+    t.C = 1;
+    t.kind = kMboxLists;
+    t.ks = p.vkey[v] + p.vkey[u];
     return t;
 }
 
@@ -1569,6 +1638,10 @@ __device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, 
         if (lane == 0) idx = atomicAdd(&p.ctrl->root_cursor, 1u);
         idx = uni(idx);
         if (idx < p.nroots) {
+            if (p.l2v) {
+                t = setup_l2(p, w, p.l2v[idx], p.l2e[idx]);
+                return true;
+            }
             uint32_t v = p.roots[idx];
             t = setup_root(p, w, v, p.splits ? p.splits[idx] : 0u);
             return true;
@@ -1731,6 +1804,29 @@ __global__ void k_root_compact(const uint32_t* __restrict__ cand, const uint32_t
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         if (flag[i]) roots[pos[i]] = cand[i];
+}
+
+// Second-level tasks of the queue's roots: one per later neighbour, in root
+// order (cnt[i] = out-degree of root i; off = its exclusive scan).
+__global__ void k_l2_counts(const uint32_t* __restrict__ roots, uint32_t nroots, const uint32_t* __restrict__ op,
+                            uint32_t* __restrict__ cnt)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nroots; i += (size_t)gridDim.x * blockDim.x)
+        cnt[i] = op[roots[i] + 1] - op[roots[i]];
+}
+
+__global__ void k_l2_expand(const uint32_t* __restrict__ roots, uint32_t nroots, const uint32_t* __restrict__ op,
+                            const uint32_t* __restrict__ off, uint32_t* __restrict__ l2v, uint32_t* __restrict__ l2e)
+{
+    const uint32_t lane = lane_id();
+    const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
+    for (size_t i = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < nroots; i += waves) {
+        const uint32_t v = roots[i], beg = op[v], d = op[v + 1] - beg, o = off[i];
+        for (uint32_t j = lane; j < d; j += 64) {
+            l2v[o + j] = v;
+            l2e[o + j] = beg + j;
+        }
+    }
 }
 
 // A custom root order must be a permutation of 0..n-1: count each id, flag
@@ -1997,6 +2093,28 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
         if ((rc = build_root_queue(g, cfg, st, s, &nroots)) != MCE_OK) return rc;
         roots = st.roots.as<uint32_t>();
     }
+    const uint32_t* l2v = nullptr;
+    const uint32_t* l2e = nullptr;
+    if ((cfg.flags & MCE_F_L2_ROOTS) && nroots) {
+        // the queue's roots expanded into their second-level tasks
+        uint32_t* cnt = st.tmp_a.as<uint32_t>();
+        uint32_t* off = st.tmp_b.as<uint32_t>();
+        uint32_t* dtotal = st.small.as<uint32_t>() + 2;
+        k_l2_counts<<<blocks_for(nroots, 256, 8192), 256, 0, s>>>(roots, nroots, g.op.as<uint32_t>(), cnt);
+        MCE_HIP_TRY(hipGetLastError());
+        if ((rc = exclusive_scan_u32(cnt, off, nroots, dtotal, st.scan_tmp.as<uint64_t>(), s)) != MCE_OK) return rc;
+        uint32_t ntasks = 0;
+        MCE_HIP_TRY(hipMemcpyAsync(&ntasks, dtotal, 4, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        if ((rc = st.l2v.alloc((size_t)std::max(ntasks, 1u) * 4)) != MCE_OK) return rc;
+        if ((rc = st.l2e.alloc((size_t)std::max(ntasks, 1u) * 4)) != MCE_OK) return rc;
+        k_l2_expand<<<blocks_for(nroots, 4, 8192), 256, 0, s>>>(roots, nroots, g.op.as<uint32_t>(), off,
+                                                                 st.l2v.as<uint32_t>(), st.l2e.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        l2v = st.l2v.as<uint32_t>();
+        l2e = st.l2e.as<uint32_t>();
+        nroots = ntasks;
+    }
     IsoStream iso{};
     if ((cfg.flags & MCE_F_STREAM) && cfg.stream_vertices && cfg.stream_offsets && g.ngraphs <= 1) {
         iso.ctrl = reinterpret_cast<Ctrl*>(st.ctrl.p);
@@ -2025,6 +2143,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.gid = g.ngraphs > 1 ? g.gid.as<uint32_t>() : nullptr;
     p.roots = roots;
     p.splits = splits;
+    p.l2v = l2v;
+    p.l2e = l2e;
     p.nroots = nroots;
     p.ctrl = reinterpret_cast<Ctrl*>(st.ctrl.p);
     p.acc = reinterpret_cast<unsigned long long*>(st.acc.p);

@@ -186,6 +186,7 @@ struct LearnedQueue {
 struct EnumState {
     LearnedQueue lq;
     DevBuf roots, ctrl, acc, gacc, hist, scratch, idle, flags, small;
+    DevBuf l2v, l2e;  // second-level tasks: root rank and edge index in the later-neighbour CSR
     DevBuf tmp_a, tmp_b, tmp_c, scan_tmp;
     size_t scratch_stride = 0;
     uint32_t grid = 0;

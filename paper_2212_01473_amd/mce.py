@@ -39,6 +39,7 @@ F_ROOT_STATS = 0x20
 F_REVERSE_ORDER = 0x40
 F_CUSTOM_ORDER = 0x80
 F_TASK_LOG = 0x100
+F_L2_ROOTS = 0x200
 
 STAT_NAMES = ["nodes", "donations", "tasks", "roots", "workgroups", "kernel_ns", "setup_ns", "xtests",
               "build_edges", "hbm_row_tasks", "idle_ns", "lds_bytes", "probes", "root_words",
@@ -295,14 +296,14 @@ def make_options(max_root_core: int = FULL, worker_list: bool = True, flags: int
                  bitmap_max_p: int = 0, donate_min_p: int = 0, donate_max_depth: int = 0,
                  timeout_ms: int = 0, stream=None, root_order=None, root_stats=None, xrow_ratio: int = 0,
                  xrow_budget_words: int = 0, xrow_min_u: int = 0, donate_every: int = 0,
-                 task_log=None, task_log_min_us: int = 0) -> Options:
+                 task_log=None, task_log_min_us: int = 0, l2_roots: bool = False) -> Options:
     o = Options()
     o.donate_every = donate_every
     o.xrow_ratio = xrow_ratio
     o.xrow_min_u = xrow_min_u
     o.xrow_budget_words = xrow_budget_words
     o.struct_size = C.sizeof(Options)
-    o.flags = flags | (F_WORKER_LIST if worker_list else 0) | F_STATS
+    o.flags = flags | (F_WORKER_LIST if worker_list else 0) | F_STATS | (F_L2_ROOTS if l2_roots else 0)
     if model is not None:
         o.flags |= F_LEARNED_ORDER | (F_SPLIT if split else 0)
         o.model = C.c_void_p(model.data_ptr())

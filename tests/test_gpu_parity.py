@@ -143,6 +143,32 @@ def test_knobs_invariant(gpu_lib, kw):
     check(gpu_lib, _dense(4), **kw)
 
 
+# ---------------------------------------------------------------- second-level subtrees (Algorithm 4)
+
+@pytest.mark.parametrize("kw", [dict(), dict(worker_list=False), dict(donate_min_p=2, wg_per_cu=1),
+                                dict(xrow_min_u=4096), dict(bitmap_max_p=64)])
+def test_l2_roots_keep_results(gpu_lib, kw):
+    graphs = [I.fig1a_example(), I.complete_graph(9), I.moon_moser(4), I.erdos_renyi(300, 0.08, 5), _dense(2),
+              I.chung_lu_planted(n=8000, wmax=400, n_cliques=30, cmin=15, cmax=45, pool=300, seed=11)]
+    for g in graphs:
+        got, _ = check(gpu_lib, g, l2_roots=True, **kw)
+    g = I.rmat(12, 16, 0.57, 0.19, 0.19, 0.05, 3)
+    for c in (8, 20, FULL):
+        check(gpu_lib, g, c, l2_roots=True, **kw)
+
+
+def test_l2_roots_reject_learned_order(gpu_lib):
+    import torch
+
+    from paper_2212_01473_amd import learned
+
+    model = torch.from_numpy(learned.init_model(7)).cuda()
+    with gpu_lib.load_graph(I.complete_graph(5)) as dg:
+        with pytest.raises(gpu_lib.MCEError) as e:
+            gpu_lib.enumerate_cliques(dg, l2_roots=True, model=model)
+    assert e.value.status == gpu_lib.MCE_ERR_INVALID_ARG
+
+
 def test_worker_list_donates(gpu_lib):
     # few workgroups, one heavy subtree: idle workgroups must receive branches
     got, _ = check(gpu_lib, _dense(4), donate_min_p=2, wg_per_cu=1)
