@@ -134,7 +134,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat18", choices=sorted(WORKLOADS))
-    ap.add_argument("--form", default=None, choices=["plain", "learned", "batched", "batched_learned", "sequential"])
+    ap.add_argument("--form", default=None,
+                    choices=["plain", "learned", "l2", "batched", "batched_learned", "sequential"])
     ap.add_argument("--compare", default=None,
                     help="comma-separated forms also timed in this run, at equal results ('' for none)")
     ap.add_argument("--window", type=int, default=None, help="override the core window c")
@@ -202,6 +203,7 @@ def main():
             return step
 
         steps["plain"] = graph_step({})
+        steps["l2"] = graph_step(dict(l2_roots=True))  # second-level subtrees (Algorithm 4)
         if model is not None:
             steps["learned"] = graph_step(dict(model=model, split=True))
         units = g.n
