@@ -133,3 +133,114 @@ def features(g, roots, order):
         out[i] = [np.log1p(deg[v]), np.log1p(core[v]), np.log1p(deg[nb].sum()),
                   e / (k * (k - 1) / 2) if k >= 2 else 0.0]
     return out
+
+
+# ------------------------------------------------------------ rounding-aware references
+# Error bounds follow the classical forward analysis of sums of products
+# (Higham, "Accuracy and Stability of Numerical Algorithms", 2nd ed., Sec. 3.1
+# and 3.5): a quantity formed through at most k floating-point roundings of
+# unit roundoff u differs from its exact value by at most gamma_k times the
+# same expression evaluated with the absolute value of every operand, where
+# gamma_k = k u / (1 - k u).
+
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+def gamma(k, u=U32):
+    return k * u / (1.0 - k * u)
+
+
+def bf16_round(x):
+    """FP32 values rounded to bfloat16 (round to nearest, ties to even), as
+    float64.  The input is first converted to FP32 (round to nearest)."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    b = a.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, X):
+    """Forward pass with BF16 weights, biases and activations (rounded after
+    every ReLU, and the normalised input after its FP32 arithmetic) and FP32
+    sums, as an FP64 reference value y plus a radius r such that every FP32
+    evaluation of the same network with any summation order lies in
+    [y - r, y + r].
+
+    Interval propagation: a layer's pre-activation lies within gamma_k times
+    its absolute sum (k = number of terms) plus the propagated deviation of its
+    inputs; ReLU and round-to-nearest are monotone, so the deviation of a
+    rounded activation is bounded by rounding the interval's end points.  An
+    activation whose interval does not reach a BF16 rounding boundary is
+    exact."""
+    p = unpack(theta)
+    W = [bf16_round(p["W1"]), bf16_round(p["W2"]), bf16_round(p["W3"])]
+    B = [bf16_round(p["b1"]), bf16_round(p["b2"]), bf16_round(p["b3"])]
+    W4, b4 = bf16_round(p["W4"]), float(bf16_round(p["b4"]))
+    X32 = np.asarray(X, dtype=np.float32)
+    mean = np.asarray(p["mean"], dtype=np.float32)
+    sd = np.asarray(p["std"], dtype=np.float32)
+    h = bf16_round((X32 - mean) / sd)  # FP32 subtraction and division, then BF16
+    dh = np.zeros_like(h)
+    for li, (Wl, bl) in enumerate(zip(W, B)):
+        # the 64-input layers may accumulate on matrix units whose internal
+        # rounding is not specified: their bound takes twice the roundings
+        k = (Wl.shape[1] + 1) * (2 if li else 1)
+        z = h @ Wl.T + bl
+        mag = (np.abs(h) + dh) @ np.abs(Wl).T + np.abs(bl)
+        rad = gamma(k) * mag + dh @ np.abs(Wl).T
+        hr = bf16_round(np.maximum(z, 0.0))
+        lo = bf16_round(np.maximum(z - rad, 0.0))
+        hi = bf16_round(np.maximum(z + rad, 0.0))
+        dh = np.maximum(hi - hr, hr - lo)
+        h = hr
+    y = h @ W4 + b4
+    mag = (np.abs(h) + dh) @ np.abs(W4) + abs(b4)
+    rad = gamma(W4.shape[0] + 1) * mag + dh @ np.abs(W4)
+    return y, rad
+
+
+def loss_grad_bound(theta, X, t, k_rounds):
+    """Magnitudes for an element-wise bound on an FP32 evaluation of
+    loss_grad: (A_grad, A_loss, margin).  A_grad is the gradient evaluated with
+    absolute values throughout (|W|, absolute forward sums, and |dL/dy|
+    replaced by 2 (|y - t| + |y|_abs) / n, which covers the forward error
+    that enters y - t; t must be representable in FP32).  An FP32
+    evaluation whose longest chain of roundings per entry is k_rounds differs
+    from the exact gradient by at most gamma(k_rounds) * A_grad, provided it
+    takes the same ReLU decisions.  margin[s] is the
+    smallest |z| / (gamma(k_rounds) * |z|_abs) over the pre-activations of
+    sample s: where it exceeds 1 no rounding can flip that sample's decisions."""
+    p = unpack(theta)
+    X = np.asarray(X, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    n = X.shape[0]
+    y, c = forward(theta, X)
+    # |x - mean| / std rounds relative to (|x| + |mean|) / std
+    a0 = (np.abs(X) + np.abs(p["mean"])) / np.abs(p["std"])
+    aW1, aW2, aW3, aW4 = (np.abs(p[k]) for k in ("W1", "W2", "W3", "W4"))
+    m1 = np.abs(a0) @ aW1.T + np.abs(p["b1"])
+    m2 = (m1 * (c["z1"] > 0)) @ aW2.T + np.abs(p["b2"])
+    m3 = (m2 * (c["z2"] > 0)) @ aW3.T + np.abs(p["b3"])
+    ya = (m3 * (c["z3"] > 0)) @ aW4 + abs(p["b4"])
+    g = gamma(k_rounds)
+    margin = np.full(n, np.inf)
+    for z, m in ((c["z1"], m1), (c["z2"], m2), (c["z3"], m3)):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(m > 0, np.abs(z) / (g * m), np.inf)
+        margin = np.minimum(margin, r.min(axis=1))
+    dya = 2.0 * (ya + np.abs(y - t)) / n
+    h1a, h2a, h3a = m1 * (c["z1"] > 0), m2 * (c["z2"] > 0), m3 * (c["z3"] > 0)
+    A = np.zeros(N_PARAMS)
+    A[oW4:ob4] = h3a.T @ dya
+    A[ob4] = dya.sum()
+    d3 = np.outer(dya, aW4) * (c["z3"] > 0)
+    A[oW3:ob3] = (d3.T @ h2a).ravel()
+    A[ob3:oW4] = d3.sum(0)
+    d2 = (d3 @ aW3) * (c["z2"] > 0)
+    A[oW2:ob2] = (d2.T @ h1a).ravel()
+    A[ob2:oW3] = d2.sum(0)
+    d1 = (d2 @ aW2) * (c["z1"] > 0)
+    A[oW1:ob1] = (d1.T @ np.abs(a0)).ravel()
+    A[ob1:oW2] = d1.sum(0)
+    A_loss = float(np.mean((ya + np.abs(y - t)) ** 2))
+    return A, A_loss, margin

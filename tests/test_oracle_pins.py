@@ -41,6 +41,56 @@ def test_key_matches_published_splitmix64_outputs():
     assert [oracle.key(v) for v in range(len(expected))] == expected
 
 
+_HASH_GRAPHS = {"fig1a": I.fig1a_example, "empty3": lambda: I.empty_graph(3),
+                "k4": lambda: I.complete_graph(4), "mm3": lambda: I.moon_moser(3)}
+
+
+def _hash_vectors():
+    return {name: int(h, 16) for name, h in (ln.split() for ln in read_golden_lines("hash_vectors.txt"))}
+
+
+def test_hash_vectors():
+    """The whole-graph hash of four small graphs against vectors computed
+    outside this repository from the hash's definition (key, the |C| term,
+    the finaliser and the sum over cliques all enter them)."""
+    vec = _hash_vectors()
+    assert sorted(vec) == sorted(_HASH_GRAPHS)
+    for name, make in _HASH_GRAPHS.items():
+        assert oracle.mce(make()).hash == vec[name], name
+
+
+def _fmix_py(z):
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & MASK64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+@pytest.mark.parametrize("mutation", ["no_size_term", "xor_not_sum", "key_of_v_not_v_plus_1"])
+def test_hash_vectors_reject_plausible_mistakes(mutation):
+    """The stored vectors are sensitive to the mistakes one could make in the
+    hash: each mutated definition, applied to the oracle's cliques, misses at
+    least one vector."""
+    vec = _hash_vectors()
+    misses = 0
+    for name, make in _HASH_GRAPHS.items():
+        cl = _full(make()).cliques
+        H = 0
+        for c in cl:
+            if mutation == "key_of_v_not_v_plus_1":
+                keys = [_fmix_py((v * oracle.GAMMA) & MASK64) for v in c]
+            else:
+                keys = [oracle.key(v) for v in c]
+            s = sum(keys) & MASK64
+            if mutation != "no_size_term":
+                s = (s + len(c) * oracle.GAMMA) & MASK64
+            h = _fmix_py(s)
+            H = (H ^ h) if mutation == "xor_not_sum" else ((H + h) & MASK64)
+        misses += H != vec[name]
+    assert misses >= 1
+
+
 def test_hash_is_additive_over_disjoint_unions():
     a, b = I.moon_moser(3), I.cycle_graph(7)
     ra, rb = oracle.mce(a), oracle.mce(b)
