@@ -69,101 +69,95 @@ __device__ bool row_contains(const uint32_t* __restrict__ rp, const uint32_t* __
     return false;
 }
 
-// One wave per row: range, self-loop and strict order of every entry.  The
-// first pass (full = 0) does no lookups: it counts the arcs v -> u with v < u
-// and with v > u (counts[0], counts[1]) and sums a 64-bit mix of the unordered
-// pair {v, u} over each kind (counts[2], counts[3]).  With strictly increasing
-// rows each kind is a set of pairs, and the graph is symmetric iff the two sets
-// are equal; unequal sets give equal counts and equal sums only if the mixes of
-// their differing pairs cancel mod 2^64.  When the pass disagrees, a full pass
-// looks up the reverse of every arc in the other row and names the first
-// offending arc.
-__device__ inline uint64_t pair_mix(uint32_t a, uint32_t b)
-{
-    return fmix64((((uint64_t)a << 32) | b) * kGamma + kGamma);
-}
+// Symmetry is decided exactly, without hashing.  With strictly increasing rows
+// and no self-loops the arcs of each direction form a set of ordered pairs.
+// The first pass (kCheckShape) checks ranges, self-loops and order, and counts
+// the arcs v -> u with v < u ("up") and with v > u ("down").  The second pass
+// (kCheckUp, only when the counts agree) looks up the reverse of every up arc.
+// If every up arc has its reverse, reversal maps the up arcs one-to-one into
+// the down arcs; equal counts make that map onto, so every down arc has its
+// reverse too and the graph is symmetric.  Whenever either pass fails, a
+// third pass (kCheckAll) looks up the reverse of every arc and names the first
+// offending (row, position).
+enum CheckMode : int { kCheckShape = 0, kCheckUp = 1, kCheckAll = 2 };
 
 constexpr uint32_t kLongRow = 2048;  // longer rows are deferred to a workgroup each
 
-// Sum four 64-bit counters over the block, one atomic per counter.
-__device__ inline void block_add4(unsigned long long (&a)[4], unsigned long long* counts)
+// Sum two 64-bit counters over the block, one atomic per counter.
+__device__ inline void block_add2(unsigned long long (&a)[2], unsigned long long* counts)
 {
     const uint32_t lane = lane_id();
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 2; ++k)
         for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_xor(a[k], off, 64);
-    __shared__ unsigned long long part[4][16];
+    __shared__ unsigned long long part[2][16];
     if (lane == 0)
-        for (int k = 0; k < 4; ++k) part[k][threadIdx.x >> 6] = a[k];
+        for (int k = 0; k < 2; ++k) part[k][threadIdx.x >> 6] = a[k];
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < 2) {
         unsigned long long t = 0;
         for (uint32_t k = 0; k < blockDim.x / 64; ++k) t += part[threadIdx.x][k];
         if (t) atomicAdd(&counts[threadIdx.x], t);
     }
 }
 
-// Checks of entry e of row v (row starts at beg); a[] gathers the counts and
-// pair sums of the first pass.
+// Checks of entry e of row v (row starts at beg) in the given mode; a[] gathers
+// the up and down counts of the first pass.
 __device__ __forceinline__ void check_arc(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
-                                          uint32_t v, uint32_t beg, uint32_t e, int full, unsigned long long* err,
-                                          unsigned long long (&a)[4])
+                                          uint32_t v, uint32_t beg, uint32_t e, int mode, unsigned long long* err,
+                                          unsigned long long (&a)[2])
 {
     uint32_t u = ci[e];
     uint32_t kind = 0;
-    if (u >= n) kind = kErrColRange;
-    else if (u == v) kind = kErrSelfLoop;
-    else if (e > beg && ci[e - 1] >= u) kind = kErrOrder;
-    else if (full && !row_contains(rp, ci, u, v)) kind = kErrAsym;
-    if (kind) atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kind);
-    if (!full && u < n) {
-        if (u > v) {
-            a[0] += 1;
-            a[2] += pair_mix(v, u);
-        } else {
-            a[1] += 1;
-            a[3] += pair_mix(u, v);
-        }
+    if (mode == kCheckUp) {
+        if (u > v && !row_contains(rp, ci, u, v)) kind = kErrAsym;
+    } else {
+        if (u >= n) kind = kErrColRange;
+        else if (u == v) kind = kErrSelfLoop;
+        else if (e > beg && ci[e - 1] >= u) kind = kErrOrder;
+        else if (mode == kCheckAll && !row_contains(rp, ci, u, v)) kind = kErrAsym;
+        if (mode == kCheckShape && u < n) a[u > v ? 0 : 1] += 1;
     }
+    if (kind) atomicMin(err, ((unsigned long long)v << 32) | ((unsigned long long)(e - beg) << 3) | kind);
 }
 
-// One wave per row; in the first pass rows longer than kLongRow are listed in
-// defer (count *ndefer) for k_validate_long, so no wave walks a hub row alone.
+// One wave per row.  In the first two modes rows longer than kLongRow are left
+// to k_validate_long (the first pass lists them in defer, count *ndefer), so no
+// wave walks a hub row alone; kCheckAll takes every row.
 __global__ void k_validate_cols(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci,
-                                uint32_t n, unsigned long long* err, unsigned long long* counts, int full,
+                                uint32_t n, unsigned long long* err, unsigned long long* counts, int mode,
                                 uint32_t* __restrict__ defer, uint32_t* __restrict__ ndefer)
 {
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
-    unsigned long long a[4] = {0, 0, 0, 0};
+    unsigned long long a[2] = {0, 0};
     for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
         uint32_t beg = rp[v], end = rp[v + 1];
-        if (!full && end - beg > kLongRow) {
-            if (lane == 0) defer[atomicAdd(ndefer, 1u)] = (uint32_t)v;
+        if (mode != kCheckAll && end - beg > kLongRow) {
+            if (mode == kCheckShape && lane == 0) defer[atomicAdd(ndefer, 1u)] = (uint32_t)v;
             continue;
         }
-        for (uint32_t e = beg + lane; e < end; e += 64) check_arc(rp, ci, n, (uint32_t)v, beg, e, full, err, a);
+        for (uint32_t e = beg + lane; e < end; e += 64) check_arc(rp, ci, n, (uint32_t)v, beg, e, mode, err, a);
     }
-    if (full) return;
-    block_add4(a, counts);
+    if (mode == kCheckShape) block_add2(a, counts);
 }
 
-// The deferred long rows of the first pass, one workgroup per row.
+// The deferred long rows of the first two modes, one workgroup per row.
 __global__ void k_validate_long(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint32_t n,
-                                unsigned long long* err, unsigned long long* counts,
+                                unsigned long long* err, unsigned long long* counts, int mode,
                                 const uint32_t* __restrict__ defer, const uint32_t* __restrict__ ndefer)
 {
-    unsigned long long a[4] = {0, 0, 0, 0};
+    unsigned long long a[2] = {0, 0};
     const uint32_t cnt = *ndefer;
     for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const uint32_t v = defer[i];
         const uint32_t beg = rp[v], end = rp[v + 1];
-        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) check_arc(rp, ci, n, v, beg, e, 0, err, a);
+        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) check_arc(rp, ci, n, v, beg, e, mode, err, a);
     }
-    block_add4(a, counts);
+    if (mode == kCheckShape) block_add2(a, counts);
 }
 
 // ---- peel ----------------------------------------------------------------------
-// Synchronous-round peel (Section III-B), driven from device memory: every step
+// Synchronous-round peel for the degeneracy order (Section II-D), driven from device memory: every step
 // reads its counts from PeelState, so a fixed sequence of launches (captured
 // once in a hipGraph) runs any number of rounds; a step after the last round
 // does nothing.  One step: a new level when the frontier ran empty (minimum
@@ -598,28 +592,43 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
             return MCE_ERR_INVALID_GRAPH;
         }
         {
-            uint64_t z[5] = {0, 0, 0, 0, 0};
-            MCE_HIP_TRY(hipMemcpyAsync(dmisc + 1, z, 40, hipMemcpyHostToDevice, s));
+            uint64_t z[3] = {0, 0, 0};
+            MCE_HIP_TRY(hipMemcpyAsync(dmisc + 1, z, 24, hipMemcpyHostToDevice, s));
         }
         DevBuf defer;
         if ((st = defer.alloc(((size_t)nnz / kLongRow + 1) * 4)) != MCE_OK) return st;
-        uint32_t* ndefer = reinterpret_cast<uint32_t*>(dmisc + 5);
-        k_validate_cols<<<blocks_for(n, 4, 1024), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 0,
+        uint32_t* ndefer = reinterpret_cast<uint32_t*>(dmisc + 3);
+        k_validate_cols<<<blocks_for(n, 4, 1024), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, kCheckShape,
                                                                  defer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
-        k_validate_long<<<256, 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, defer.as<uint32_t>(), ndefer);
+        k_validate_long<<<256, 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, kCheckShape, defer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
-        MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 40, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 24, hipMemcpyDeviceToHost, s));
         MCE_HIP_TRY(hipStreamSynchronize(s));
-        if (hmisc[0] == ~0ull && (hmisc[1] != hmisc[2] || hmisc[3] != hmisc[4])) {
-            // the arcs in the two directions differ: find the first arc without a reverse
-            k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, 1, nullptr,
-                                                                     nullptr);
+        bool name_arc = hmisc[0] == ~0ull && hmisc[1] != hmisc[2];
+        if (hmisc[0] == ~0ull && !name_arc) {
+            // equal counts: the reverse of every up arc decides symmetry
+            k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, nullptr, kCheckUp,
+                                                                     nullptr, nullptr);
+            MCE_HIP_TRY(hipGetLastError());
+            k_validate_long<<<256, 256, 0, s>>>(rp, ci, n, dmisc, nullptr, kCheckUp, defer.as<uint32_t>(),
+                                                ndefer);
+            MCE_HIP_TRY(hipGetLastError());
+            MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+            name_arc = hmisc[0] != ~0ull;
+        }
+        if (name_arc) {
+            // asymmetric: name the first arc (in row, position order) without a reverse
+            uint64_t init2 = ~0ull;
+            MCE_HIP_TRY(hipMemcpyAsync(dmisc, &init2, 8, hipMemcpyHostToDevice, s));
+            k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, nullptr, kCheckAll,
+                                                                     nullptr, nullptr);
             MCE_HIP_TRY(hipGetLastError());
             MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
             MCE_HIP_TRY(hipStreamSynchronize(s));
             if (hmisc[0] == ~0ull) {
-                set_error("invalid graph: asymmetric (the arc sets in the two directions differ)");
+                set_error("invalid graph: asymmetric (the numbers of arcs in the two directions differ)");
                 return MCE_ERR_INVALID_GRAPH;
             }
         }

@@ -330,7 +330,7 @@ def _bad_graphs():
     down_rp = np.array([0, 1, 3, 5], dtype=np.uint32)
     down_ci = np.array([1, 0, 2, 0, 1], dtype=np.uint32)
     # arcs 0-1 both ways, 2 -> 3 and 3 -> 1 without reverses: as many arcs go up
-    # as down, but the two sets of pairs differ (found by the pair sums)
+    # as down, but the two sets of pairs differ (found by the up-arc lookups)
     swap_rp = np.array([0, 1, 2, 3, 4], dtype=np.uint32)
     swap_ci = np.array([1, 0, 3, 1], dtype=np.uint32)
     return [(rp, asym), (rp, unsorted), (rp, selfloop), (rp, oob), (rp, dup), (badrp, ci), (down_rp, down_ci),
@@ -344,6 +344,47 @@ def test_invalid_graphs_rejected(gpu_lib, i):
         gpu_lib.load_csr(rp, ci)
     assert e.value.status == gpu_lib.MCE_ERR_INVALID_GRAPH
     assert "row" in str(e.value)
+
+
+def _first_arc_without_reverse(rp, ci):
+    """(row, position) of the first arc, in row-major order, whose reverse is
+    missing; written with plain Python sets."""
+    n = len(rp) - 1
+    rows = [set(ci[rp[v]:rp[v + 1]].tolist()) for v in range(n)]
+    for v in range(n):
+        for pos, u in enumerate(ci[rp[v]:rp[v + 1]].tolist()):
+            if v not in rows[u]:
+                return v, pos
+    return None
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_asymmetric_with_equal_arc_counts_is_named(gpu_lib, seed):
+    """One arc v -> u with u < v is removed and another arc b -> a with a < b is
+    added: the numbers of arcs going up (to a larger id) and down stay equal,
+    so only exact reverse lookups can reject the graph.  The message names the
+    first offending arc in row-major order."""
+    g = I.erdos_renyi(300, 0.05, 10 + seed)
+    rng = np.random.default_rng(seed)
+    rows = [list(g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]) for v in range(g.n)]
+    downs = [(v, u) for v in range(g.n) for u in rows[v] if u < v]
+    v, u = downs[rng.integers(len(downs))]
+    rows[v].remove(u)
+    while True:
+        a, b = sorted(int(x) for x in rng.choice(g.n, 2, replace=False))
+        if a not in rows[b]:
+            break
+    rows[b] = sorted(rows[b] + [a])
+    rp = np.zeros(g.n + 1, dtype=np.uint32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([x for r in rows for x in r], dtype=np.uint32)
+    up = sum(1 for x in range(g.n) for y in rows[x] if y > x)
+    assert 2 * up == len(ci)  # as many arcs go up as down
+    row, pos = _first_arc_without_reverse(rp, ci)
+    with pytest.raises(gpu_lib.MCEError) as e:
+        gpu_lib.load_csr(rp, ci)
+    assert e.value.status == gpu_lib.MCE_ERR_INVALID_GRAPH
+    assert f"asymmetric (missing reverse arc) at row {row} position {pos}" in str(e.value)
 
 
 def test_hist_too_small(gpu_lib):
