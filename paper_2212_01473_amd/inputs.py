@@ -265,30 +265,53 @@ def erdos_renyi(n: int, p: float, seed) -> CSRGraph:
 
 
 def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, d: float, seed,
-         chunk: int = 1 << 24) -> CSRGraph:
+         chunk: int = 1 << 24, workers: int = 8) -> CSRGraph:
+    """R-MAT: n = 2^scale vertices, edge_factor * n samples; per sample and bit
+    (most significant first) one uniform u picks the quadrant (u < a: (0,0),
+    < a+b: (0,1), < a+b+c: (1,0), else (1,1)).  Self-loops and duplicates are
+    dropped and the graph is symmetrised.
+
+    The samples are drawn in chunks of `chunk`, each chunk bit by bit from one
+    PCG64 stream; chunks run in threads, each starting from the stream advanced
+    to its first draw, and the arcs are deduplicated in row-range buckets, so
+    the graph does not depend on `workers`."""
     n = 1 << scale
     m = n * edge_factor
-    rng = _rng(seed)
-    src_all, dst_all = [], []
-    t_ab, t_abc = a + b, a + b + c
-    done = 0
-    while done < m:
-        k = min(chunk, m - done)
+    thr = np.array([a, a + b, a + b + c])
+    nb = max(1, int(workers))
+    rows_per = (n + nb - 1) // nb
+    bounds = np.array([min(n, (i + 1) * rows_per) * n for i in range(nb - 1)], dtype=np.int64)
+
+    def sample(start):
+        k = min(chunk, m - start)
+        rng = _rng(seed)
+        rng.bit_generator.advance(start * scale)  # one 64-bit draw per uniform
         s = np.zeros(k, dtype=np.int64)
         t = np.zeros(k, dtype=np.int64)
         for bit in range(scale - 1, -1, -1):
-            u = rng.random(k)
-            sb = (u >= t_ab).astype(np.int64)           # (1,0) or (1,1)
-            tb = ((u >= a) & (u < t_ab)) | (u >= t_abc)  # (0,1) or (1,1)
-            s |= sb << bit
-            t |= tb.astype(np.int64) << bit
-        src_all.append(s)
-        dst_all.append(t)
-        done += k
-    src = np.concatenate(src_all)
-    dst = np.concatenate(dst_all)
-    del src_all, dst_all
-    return from_edges(n, src, dst, f"rmat{scale}_ef{edge_factor}")
+            q = np.searchsorted(thr, rng.random(k), side="right")  # quadrant 0..3
+            s |= (q >> 1) << bit
+            t |= (q & 1) << bit
+        keep = s != t
+        s, t = s[keep], t[keep]
+        arcs = np.unique(np.concatenate([s * n + t, t * n + s]))  # row * n + col, both directions
+        return np.split(arcs, np.searchsorted(arcs, bounds))
+
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(nb) as ex:
+        parts = list(ex.map(sample, range(0, m, chunk)))
+        merged = list(ex.map(lambda i: np.unique(np.concatenate([p[i] for p in parts])), range(nb)))
+    del parts
+    arcs = np.concatenate(merged)
+    del merged
+    row = arcs // n
+    col = (arcs - row * n).astype(np.uint32)
+    del arcs
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(row, minlength=n), out=rp[1:])
+    rp_dtype = np.uint32 if rp[-1] < 2**32 else np.uint64
+    return CSRGraph(n=n, row_ptr=rp.astype(rp_dtype), col_idx=col, name=f"rmat{scale}_ef{edge_factor}")
 
 
 def chung_lu_planted(n: int = 1_000_000, exponent: float = 2.1, wmin: float = 2.0,
