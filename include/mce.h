@@ -294,6 +294,25 @@ mce_status mce_model_loss_grad(const float* model, const float* feat, const floa
                                float* grad, float* loss, void* stream);
 
 /*
+ * mce_model_loss_grad for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, with the activations
+ * and partial sums in a fixed device array of the library (about 24.5 MiB,
+ * held on every device the library runs on until the process ends) instead
+ * of per-call buffers.  Allocates nothing, device or host.
+ *
+ * n: 1 .. MCE_NOALLOC_MAX_SAMPLES, else MCE_ERR_INVALID_ARG (larger sets go
+ * through mce_model_loss_grad).  model, feat (float[n*4]), target (float[n])
+ * and grad (float[MCE_MODEL_FLOATS]) are device pointers as there; loss: host
+ * float or NULL.  stream: hipStream_t of the current device, or NULL.  Calls
+ * on one device share the array: calls that overlap on one device (other host
+ * threads, other streams) race and must be serialised by the caller.
+ */
+#define MCE_NOALLOC_MAX_SAMPLES 16384u
+mce_status mce_model_loss_grad_noalloc(const float* model, const float* feat, const float* target, uint32_t n,
+                                       float* grad, float* loss, void* stream);
+
+/*
  * Autotuner for the performance knobs (none of them changes the result):
  * coordinate descent over donate_min_p, bitmap_max_p, wg_per_cu,
  * donate_max_depth and xrow_ratio, timing setup + kernel with device events on

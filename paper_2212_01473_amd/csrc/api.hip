@@ -317,6 +317,14 @@ mce_status mce_model_loss_grad(const float* model, const float* feat, const floa
     return model_loss_grad(model, feat, target, n, grad, loss, reinterpret_cast<hipStream_t>(stream));
 }
 
+mce_status mce_model_loss_grad_noalloc(const float* model, const float* feat, const float* target, uint32_t n,
+                                       float* grad, float* loss, void* stream)
+{
+    set_error("");
+    if (!model || !feat || !target || !grad) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
+    return model_loss_grad_noalloc(model, feat, target, n, grad, loss, reinterpret_cast<hipStream_t>(stream));
+}
+
 void mce_free(mce_graph* g) { delete g; }
 
 const char* mce_status_string(mce_status s)

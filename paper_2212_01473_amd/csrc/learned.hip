@@ -8,6 +8,7 @@
 #include "mce_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace mce {
 
@@ -588,6 +589,55 @@ mce_status model_predict(const float* model, const float* feat, uint32_t n, floa
 }
 
 namespace {
+// Sizes and layout of the training buffers for n samples: activations
+// (feature-major a0, h1..h3, d1..d3, dy), per-chunk gradient partials and
+// per-block loss partials.
+size_t act_floats(uint32_t n) { return ((size_t)kIn + 6 * kH + 1) * n; }
+uint32_t grad_parts(uint32_t n) { return (n + kGradChunk - 1) / kGradChunk; }
+uint32_t loss_parts(uint32_t n) { return blocks_for(n, 256, 2048); }
+
+TrainBufs bind_bufs(float* act, float* part, uint32_t n)
+{
+    TrainBufs b;
+    b.a0 = act;
+    b.h1 = b.a0 + (size_t)kIn * n;
+    b.h2 = b.h1 + (size_t)kH * n;
+    b.h3 = b.h2 + (size_t)kH * n;
+    b.d1 = b.h3 + (size_t)kH * n;
+    b.d2 = b.d1 + (size_t)kH * n;
+    b.d3 = b.d2 + (size_t)kH * n;
+    b.dy = b.d3 + (size_t)kH * n;
+    b.part = part;
+    return b;
+}
+
+// Forward/backward, gradient partials and their fixed-order reduction into
+// grad; the loss (mean over samples, summed in double on the host in block
+// order) when loss_host is given.
+mce_status run_loss_grad(const float* model, const float* feat, const float* target, uint32_t n, const TrainBufs& b,
+                         uint32_t nparts, float* lpart, uint32_t nloss, float* grad, hipStream_t s, float* loss_host)
+{
+    k_mlp_fwd_bwd<<<nloss, 256, 0, s>>>(model, feat, target, n, b, lpart);
+    MCE_HIP_TRY(hipGetLastError());
+    k_mlp_grad_partial<<<nparts, 256, 0, s>>>(b, n);
+    MCE_HIP_TRY(hipGetLastError());
+    k_grad_reduce<<<blocks_for(kModel, 256), 256, 0, s>>>(b.part, nparts, grad);
+    MCE_HIP_TRY(hipGetLastError());
+    if (loss_host) {
+        constexpr uint32_t kChunk = 64;  // partials copied per round trip (host stack, no heap)
+        float lp[kChunk];
+        double t = 0;
+        for (uint32_t i0 = 0; i0 < nloss; i0 += kChunk) {
+            const uint32_t k = nloss - i0 < kChunk ? nloss - i0 : kChunk;
+            MCE_HIP_TRY(hipMemcpyAsync(lp, lpart + i0, k * 4, hipMemcpyDeviceToHost, s));
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+            for (uint32_t i = 0; i < k; ++i) t += lp[i];
+        }
+        *loss_host = (float)(t / (n ? n : 1));
+    }
+    return MCE_OK;
+}
+
 struct TrainState {
     DevBuf act, part, grad, m, v, lpart;
     TrainBufs b;
@@ -595,45 +645,22 @@ struct TrainState {
     mce_status setup(uint32_t n)
     {
         mce_status st;
-        size_t cols = (size_t)kIn + 6 * kH + 1;  // a0, h1..h3, d1..d3, dy
-        if ((st = act.alloc(cols * n * 4 + 64)) != MCE_OK) return st;
-        nparts = (n + kGradChunk - 1) / kGradChunk;
+        if ((st = act.alloc(act_floats(n) * 4 + 64)) != MCE_OK) return st;
+        nparts = grad_parts(n);
         if ((st = part.alloc((size_t)nparts * kTrainable * 4 + 64)) != MCE_OK) return st;
         if ((st = grad.alloc(kModel * 4)) != MCE_OK) return st;
         if ((st = m.alloc(kModel * 4)) != MCE_OK) return st;
         if ((st = v.alloc(kModel * 4)) != MCE_OK) return st;
-        nloss = blocks_for(n, 256, 2048);
+        nloss = loss_parts(n);
         if ((st = lpart.alloc((size_t)nloss * 4)) != MCE_OK) return st;
-        float* a = act.as<float>();
-        b.a0 = a;
-        b.h1 = b.a0 + (size_t)kIn * n;
-        b.h2 = b.h1 + (size_t)kH * n;
-        b.h3 = b.h2 + (size_t)kH * n;
-        b.d1 = b.h3 + (size_t)kH * n;
-        b.d2 = b.d1 + (size_t)kH * n;
-        b.d3 = b.d2 + (size_t)kH * n;
-        b.dy = b.d3 + (size_t)kH * n;
-        b.part = part.as<float>();
+        b = bind_bufs(act.as<float>(), part.as<float>(), n);
         return MCE_OK;
     }
     mce_status loss_grad(const float* model, const float* feat, const float* target, uint32_t n, hipStream_t s,
                          float* loss_host)
     {
-        k_mlp_fwd_bwd<<<nloss, 256, 0, s>>>(model, feat, target, n, b, lpart.as<float>());
-        MCE_HIP_TRY(hipGetLastError());
-        k_mlp_grad_partial<<<nparts, 256, 0, s>>>(b, n);
-        MCE_HIP_TRY(hipGetLastError());
-        k_grad_reduce<<<blocks_for(kModel, 256), 256, 0, s>>>(part.as<float>(), nparts, grad.as<float>());
-        MCE_HIP_TRY(hipGetLastError());
-        if (loss_host) {
-            std::vector<float> lp(nloss);
-            MCE_HIP_TRY(hipMemcpyAsync(lp.data(), lpart.p, nloss * 4, hipMemcpyDeviceToHost, s));
-            MCE_HIP_TRY(hipStreamSynchronize(s));
-            double t = 0;
-            for (float x : lp) t += x;
-            *loss_host = (float)(t / (n ? n : 1));
-        }
-        return MCE_OK;
+        return run_loss_grad(model, feat, target, n, b, nparts, lpart.as<float>(), nloss, grad.as<float>(), s,
+                             loss_host);
     }
 };
 }  // namespace
@@ -650,6 +677,84 @@ mce_status model_loss_grad(const float* model, const float* feat, const float* t
     if (st != MCE_OK) return st;
     if ((st = ts.loss_grad(model, feat, target, n, s, loss)) != MCE_OK) return st;
     MCE_HIP_TRY(hipMemcpyAsync(grad, ts.grad.p, kModel * 4, hipMemcpyDeviceToDevice, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    return MCE_OK;
+}
+
+// ---------------------------------------------------------------- loss and gradient without allocation
+// For callers that cannot allocate device memory: the activations and partial
+// sums of mce_model_loss_grad live in one file-scope device array of fixed
+// size instead of buffers allocated per call.  Each device that runs the
+// library holds its own copy until the process ends; its address on a device
+// is looked up once, with that device current, and kept.  Calls on one device
+// share the array, so overlapping calls there race; nothing in it has to start
+// at zero (every word a call reads was written earlier in the same call).
+constexpr uint32_t kNaMax = MCE_NOALLOC_MAX_SAMPLES;
+constexpr size_t kNaActBytes = (((size_t)kIn + 6 * kH + 1) * kNaMax * 4 + 255) & ~(size_t)255;
+constexpr size_t kNaPartBytes = ((size_t)((kNaMax + kGradChunk - 1) / kGradChunk) * kTrainable * 4 + 255) & ~(size_t)255;
+constexpr size_t kNaLossBytes = ((size_t)((kNaMax + 255) / 256) * 4 + 255) & ~(size_t)255;
+constexpr size_t kNaBytes = kNaActBytes + kNaPartBytes + kNaLossBytes;
+static_assert((kNaMax + 255) / 256 <= 2048, "loss partials: one per block of 256 samples");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kNaDevices = 64;
+std::mutex g_na_mu;
+unsigned char* g_na_ptr[kNaDevices] = {};
+
+// The device address of this device's scratch array; the stream (if given)
+// must belong to the current device.
+mce_status noalloc_scratch(hipStream_t s, unsigned char** out)
+{
+    int dev = 0;
+    MCE_HIP_TRY(hipGetDevice(&dev));
+    if (s) {
+        hipDevice_t sd = 0;
+        MCE_HIP_TRY(hipStreamGetDevice(s, &sd));
+        if ((int)sd != dev) {
+            set_error("the stream belongs to another device than the current one");
+            return MCE_ERR_INVALID_ARG;
+        }
+    }
+    if (dev < 0 || dev >= kNaDevices) {
+        set_error("device index beyond the library's table of scratch addresses");
+        return MCE_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return MCE_ERR_DEVICE;
+        }
+        g_na_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_na_ptr[dev];
+    return MCE_OK;
+}
+}  // namespace
+
+mce_status model_loss_grad_noalloc(const float* model, const float* feat, const float* target, uint32_t n,
+                                   float* grad, float* loss, hipStream_t s)
+{
+    if (n == 0) {
+        set_error("no samples");
+        return MCE_ERR_INVALID_ARG;
+    }
+    if (n > kNaMax) {
+        set_error("n = " + std::to_string(n) + " exceeds MCE_NOALLOC_MAX_SAMPLES = " + std::to_string(kNaMax) +
+                  " (use mce_model_loss_grad)");
+        return MCE_ERR_INVALID_ARG;
+    }
+    unsigned char* base = nullptr;
+    mce_status st = noalloc_scratch(s, &base);
+    if (st != MCE_OK) return st;
+    const TrainBufs b = bind_bufs(reinterpret_cast<float*>(base), reinterpret_cast<float*>(base + kNaActBytes), n);
+    float* lpart = reinterpret_cast<float*>(base + kNaActBytes + kNaPartBytes);
+    if ((st = run_loss_grad(model, feat, target, n, b, grad_parts(n), lpart, loss_parts(n), grad, s, loss)) != MCE_OK)
+        return st;
     MCE_HIP_TRY(hipStreamSynchronize(s));
     return MCE_OK;
 }

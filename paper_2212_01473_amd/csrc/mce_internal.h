@@ -207,6 +207,8 @@ mce_status ids_to_ranks(const Oriented& g, const uint32_t* ids, uint32_t n, uint
 mce_status model_predict(const float* model, const float* feat, uint32_t n, float* out, hipStream_t s);
 mce_status model_loss_grad(const float* model, const float* feat, const float* target, uint32_t n, float* grad,
                            float* loss, hipStream_t s);
+mce_status model_loss_grad_noalloc(const float* model, const float* feat, const float* target, uint32_t n,
+                                   float* grad, float* loss, hipStream_t s);
 mce_status model_fit_norm(float* model, const float* feat, uint32_t n, hipStream_t s);
 mce_status model_train(float* model, const float* feat, const float* target, uint32_t n, uint32_t epochs, float lr,
                        float b1, float b2, float eps, bool fit_norm, float* loss_hist, hipStream_t s);

@@ -50,9 +50,11 @@ FULL = 0xFFFFFFFF
 
 EXPORTED = ["mce_load_csr", "mce_load_csr_batch", "mce_graph_get_info", "mce_graph_copy_order", "mce_enumerate",
             "mce_enumerate_batch", "mce_free", "mce_status_string", "mce_last_error", "mce_version",
-            "mce_root_features", "mce_model_predict", "mce_model_train", "mce_model_loss_grad", "mce_autotune"]
+            "mce_root_features", "mce_model_predict", "mce_model_train", "mce_model_loss_grad",
+            "mce_model_loss_grad_noalloc", "mce_autotune"]
 
 MODEL_FLOATS = 8713
+MCE_NOALLOC_MAX_SAMPLES = 16384  # include/mce.h
 
 
 class MCEError(RuntimeError):
@@ -139,6 +141,9 @@ def load_library(path: str | None = None):
     lib.mce_model_loss_grad.restype = C.c_int
     lib.mce_model_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
                                         C.POINTER(C.c_float), C.c_void_p]
+    lib.mce_model_loss_grad_noalloc.restype = C.c_int
+    lib.mce_model_loss_grad_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p,
+                                                C.POINTER(C.c_float), C.c_void_p]
     lib.mce_autotune.restype = C.c_int
     lib.mce_autotune.argtypes = [C.c_void_p, C.POINTER(Options), C.POINTER(Options), C.POINTER(TuneReport)]
     _lib = lib
@@ -435,6 +440,17 @@ def model_loss_grad(model, feat, target):
                                               C.c_void_p(grad.data_ptr()), C.byref(loss), _torch_stream()),
            "mce_model_loss_grad")
     return grad, float(loss.value)
+
+
+def model_loss_grad_noalloc(model, feat, target, grad) -> float:
+    """mce_model_loss_grad_noalloc: the gradient into the caller's device
+    tensor grad (float32[MODEL_FLOATS]); returns the loss."""
+    loss = C.c_float()
+    _check(load_library().mce_model_loss_grad_noalloc(C.c_void_p(model.data_ptr()), C.c_void_p(feat.data_ptr()),
+                                                      C.c_void_p(target.data_ptr()), int(feat.shape[0]),
+                                                      C.c_void_p(grad.data_ptr()), C.byref(loss), _torch_stream()),
+           "mce_model_loss_grad_noalloc")
+    return float(loss.value)
 
 
 def model_train(model, feat, target, epochs: int = 300, lr: float = 3e-3, beta1: float = 0.9,

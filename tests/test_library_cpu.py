@@ -28,6 +28,14 @@ def test_library_loads_and_exports_header_symbols():
         assert hasattr(lib, name)
 
 
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    m = re.search(r"#define MCE_NOALLOC_MAX_SAMPLES (\d+)u", text)
+    assert m and int(m.group(1)) == mce.MCE_NOALLOC_MAX_SAMPLES
+    m = re.search(r"#define MCE_MODEL_FLOATS (\d+)", text)
+    assert m and int(m.group(1)) == mce.MODEL_FLOATS
+
+
 def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text(r'''
