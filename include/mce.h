@@ -68,11 +68,17 @@ typedef struct {
     uint32_t max_out_degree; /* largest |P| of a first-level subtree (<= d) */
     uint32_t max_in_degree;  /* largest |X| of a first-level subtree (<= Delta) */
     uint32_t n_graphs;       /* graphs in the handle (1 unless batch-loaded) */
+    uint32_t peel_mode;      /* how the peel ran: 1 = one cooperative launch with grid
+                                barriers, 2 = step kernels replayed from a captured graph */
 } mce_graph_info;
 
 /* ---- load flags */
 #define MCE_LOAD_DEVICE_PTRS 0x1u  /* row_ptr/col_idx are device pointers */
 #define MCE_LOAD_NO_VALIDATE 0x2u  /* skip the graph-rule checks (caller vouches) */
+#define MCE_LOAD_PEEL_STEPS 0x4u   /* run the peel as step kernels replayed from a captured
+                                      graph instead of one cooperative launch (same result;
+                                      the library also falls back to it by itself when the
+                                      device cannot run the single launch) */
 
 /*
  * Load an undirected simple graph given as CSR with both arc directions stored

@@ -58,6 +58,7 @@ mce_status load_one(const uint32_t* row_ptr, const uint32_t* col_idx, uint32_t n
         rp = drp.as<uint32_t>();
         ci = dci.as<uint32_t>();
     }
+    og.peel_steps = (flags & MCE_LOAD_PEEL_STEPS) != 0;
     return preprocess_graph(rp, ci, n, nnz, validate, s, og);
 }
 
@@ -73,6 +74,7 @@ void fill_info(const Oriented& o, uint32_t idx, mce_graph_info* out)
     out->max_out_degree = m.max_out;
     out->max_in_degree = m.max_in;
     out->n_graphs = o.ngraphs;
+    out->peel_mode = o.peel_mode;
 }
 
 mce_status config_from(const mce_options* opt, EnumConfig& cfg)
@@ -148,7 +150,8 @@ mce_status mce_load_csr(const uint32_t* row_ptr, const uint32_t* col_idx, uint32
     if (!row_ptr) return fail(MCE_ERR_INVALID_ARG, "row_ptr is NULL");
     if (!col_idx && nnz) return fail(MCE_ERR_INVALID_ARG, "col_idx is NULL");
     if (n == 0xFFFFFFFFu) return fail(MCE_ERR_INVALID_ARG, "n too large");
-    if (flags & ~(MCE_LOAD_DEVICE_PTRS | MCE_LOAD_NO_VALIDATE)) return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
+    if (flags & ~(MCE_LOAD_DEVICE_PTRS | MCE_LOAD_NO_VALIDATE | MCE_LOAD_PEEL_STEPS))
+        return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     auto g = std::make_unique<mce_graph>();
     g->graphs.emplace_back(new Oriented());
@@ -168,7 +171,8 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
     *out = nullptr;
     if (!row_ptr_cat || !row_off || !col_off) return fail(MCE_ERR_INVALID_ARG, "NULL batch array");
     if (n_graphs == 0) return fail(MCE_ERR_INVALID_ARG, "n_graphs is 0");
-    if (flags & ~(MCE_LOAD_DEVICE_PTRS | MCE_LOAD_NO_VALIDATE)) return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
+    if (flags & ~(MCE_LOAD_DEVICE_PTRS | MCE_LOAD_NO_VALIDATE | MCE_LOAD_PEEL_STEPS))
+        return fail(MCE_ERR_INVALID_ARG, "unknown load flags");
     for (uint32_t i = 0; i < n_graphs; ++i) {
         if (row_off[i + 1] <= row_off[i] || col_off[i + 1] < col_off[i])
             return fail(MCE_ERR_INVALID_ARG, "batch offsets not increasing at graph " + std::to_string(i));
@@ -178,6 +182,7 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
     auto g = std::make_unique<mce_graph>();
     g->batch = true;
     g->graphs.emplace_back(new Oriented());
+    g->graphs[0]->peel_steps = (flags & MCE_LOAD_PEEL_STEPS) != 0;
     mce_status st = preprocess_batch(row_ptr_cat, col_idx_cat, row_off, col_off, n_graphs,
                                      (flags & MCE_LOAD_NO_VALIDATE) == 0, (flags & MCE_LOAD_DEVICE_PTRS) != 0, s,
                                      *g->graphs[0]);

@@ -100,6 +100,8 @@ struct Oriented {
     uint32_t max_degree = 0, degeneracy = 0, rounds = 0;
     uint32_t max_out = 0, max_in = 0;
     uint64_t n_isolated = 0;
+    bool peel_steps = false;  // in: run the peel as step kernels replayed from a graph
+    uint32_t peel_mode = 0;   // out: 1 = one cooperative launch, 2 = step kernels
     // rank space
     DevBuf op, oc;    // out CSR: later neighbours, sorted ascending by rank
     DevBuf ip, ic;    // in CSR: earlier neighbours (unsorted)

@@ -333,6 +333,193 @@ __global__ void k_pd_advance(PeelState* ps, uint32_t n)
     }
 }
 
+// ---- single-launch peel ----------------------------------------------------------
+// The same rounds as the step kernels above in one launch: every workgroup is
+// resident at once (cooperative launch) and the workgroups meet at a grid
+// barrier after each phase.  Each workgroup keeps its own copy of the peel's
+// bookkeeping (level, round, buffer parities, sizes) and updates it the same way
+// from the shared counters after each barrier, so an ordinary round needs one
+// barrier and a round that opens a new level three.  The counters of round r
+// live in slot r % 3; workgroup 0 clears the slot of round r + 1 when round r
+// starts (that slot was last read at the start of round r - 1, before every
+// workgroup reached the barriers of round r - 1).
+struct alignas(256) PeelSlot {
+    uint32_t min_deg, n_front, n_alive, n_next;
+};
+struct PeelSync {
+    alignas(256) uint32_t count;  // arrivals at the current barrier
+    alignas(256) uint32_t gen;    // barrier generation
+    alignas(256) uint32_t err;    // 1: a barrier wait timed out, 2: no remaining vertex, 4: round limit
+    PeelSlot slot[3];
+    alignas(256) uint32_t out_r, out_k, out_done;
+};
+
+// Grid barrier with a bounded wait: false when a wait ran past the deadline or
+// another workgroup reported an error (then every workgroup leaves the kernel).
+__device__ bool grid_barrier(PeelSync* ps, uint32_t nb, uint64_t deadline)
+{
+    __shared__ uint32_t ok_s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        const uint32_t g = __hip_atomic_load(&ps->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t arrived = __hip_atomic_fetch_add(&ps->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nb - 1) {
+            __hip_atomic_store(&ps->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ps->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&ps->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&ps->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    ok = 0;
+                    break;
+                }
+                if (__builtin_amdgcn_s_memrealtime() > deadline) {
+                    __hip_atomic_fetch_or(&ps->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0u;
+}
+
+__global__ void __launch_bounds__(256) k_peel_persistent(const uint32_t* __restrict__ rp,
+                                                         const uint32_t* __restrict__ ci, uint32_t n, PeelBufs b,
+                                                         uint32_t* __restrict__ deg, uint32_t* __restrict__ round,
+                                                         uint32_t* __restrict__ core, PeelSync* ps,
+                                                         uint64_t timeout_ticks)
+{
+    const uint32_t nb = gridDim.x;
+    const uint64_t deadline = __builtin_amdgcn_s_memrealtime() + timeout_ticks;
+    const uint32_t lane = lane_id();
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t nthreads = (size_t)nb * blockDim.x;
+    const size_t wid = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const size_t nwaves = (size_t)nb * (blockDim.x / 64);
+    // bookkeeping, identical in every workgroup
+    uint32_t k = 0, r = 0, pa = 0, pf = 0, n_alive = n, n_cur = 0;
+    uint64_t removed = 0;
+    bool need_level = n > 0;
+    const uint64_t max_rounds = 2 * (uint64_t)n + 4;  // every round removes at least one vertex
+    while (removed < n) {
+        if (r >= max_rounds) {
+            if (leader) __hip_atomic_fetch_or(&ps->err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        PeelSlot* sl = &ps->slot[r % 3];
+        if (leader) {
+            PeelSlot* nx = &ps->slot[(r + 1) % 3];
+            __hip_atomic_store(&nx->min_deg, kUnset, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&nx->n_front, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&nx->n_alive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&nx->n_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (need_level) {
+            // the minimum remaining degree opens the level
+            const uint32_t* A = b.alive[pa];
+            uint32_t m = kUnset;
+            for (size_t i = tid; i < n_alive; i += nthreads) {
+                const uint32_t v = A[i];
+                if (round[v] == kUnset) m = min(m, deg[v]);
+            }
+            for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
+            if (lane == 0 && m != kUnset) atomicMin(&sl->min_deg, m);
+            if (!grid_barrier(ps, nb, deadline)) return;
+            const uint32_t md = __hip_atomic_load(&sl->min_deg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (md == kUnset) {
+                if (leader) __hip_atomic_fetch_or(&ps->err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            k = max(k, md);
+            // the level's first frontier: every remaining vertex of degree <= k
+            uint32_t* A2 = b.alive[pa ^ 1u];
+            uint32_t* F = b.front[pf];
+            for (size_t base = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n_alive;
+                 base += nthreads) {
+                const size_t i = base + lane;
+                uint32_t v = 0;
+                bool sel = false, keep = false;
+                if (i < n_alive) {
+                    v = A[i];
+                    if (round[v] == kUnset) {
+                        if (deg[v] <= k) sel = true;
+                        else keep = true;
+                    }
+                }
+                const uint64_t ms = __ballot(sel), mk = __ballot(keep);
+                uint32_t bs = 0, bk = 0;
+                if (lane == 0) {
+                    if (ms) bs = atomicAdd(&sl->n_front, (uint32_t)__popcll(ms));
+                    if (mk) bk = atomicAdd(&sl->n_alive, (uint32_t)__popcll(mk));
+                }
+                bs = __shfl(bs, 0);
+                bk = __shfl(bk, 0);
+                if (sel) {
+                    round[v] = r;
+                    core[v] = k;
+                    F[bs + prefix_popc(ms)] = v;
+                }
+                if (keep) A2[bk + prefix_popc(mk)] = v;
+            }
+            if (!grid_barrier(ps, nb, deadline)) return;
+            n_cur = __hip_atomic_load(&sl->n_front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            n_alive = __hip_atomic_load(&sl->n_alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pa ^= 1u;
+            need_level = false;
+        }
+        // remove the frontier: a neighbour whose degree falls from k + 1 to k
+        // joins the next round (one wave per frontier vertex)
+        {
+            const uint32_t* F = b.front[pf];
+            uint32_t* F2 = b.front[pf ^ 1u];
+            const uint32_t r_next = r + 1;
+            for (size_t f = wid; f < n_cur; f += nwaves) {
+                const uint32_t v = F[f];
+                const uint32_t beg = rp[v], end = rp[v + 1];
+                for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+                    const uint32_t e = e0 + lane;
+                    bool joined = false;
+                    uint32_t u = 0;
+                    if (e < end) {
+                        u = ci[e];
+                        if (__hip_atomic_load(&round[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kUnset) {
+                            const uint32_t old = atomicSub(&deg[u], 1u);
+                            if (old == k + 1) {
+                                joined = true;
+                                __hip_atomic_store(&round[u], r_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                core[u] = k;
+                            }
+                        }
+                    }
+                    const uint64_t m = __ballot(joined);
+                    uint32_t bo = 0;
+                    if (lane == 0 && m) bo = atomicAdd(&sl->n_next, (uint32_t)__popcll(m));
+                    bo = __shfl(bo, 0);
+                    if (joined) F2[bo + prefix_popc(m)] = u;
+                }
+            }
+        }
+        if (!grid_barrier(ps, nb, deadline)) return;
+        removed += n_cur;
+        r += 1;
+        pf ^= 1u;
+        n_cur = __hip_atomic_load(&sl->n_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (n_cur == 0 && removed < n) need_level = true;
+    }
+    if (leader) {
+        ps->out_r = r;
+        ps->out_k = k;
+        ps->out_done = 1u;
+    }
+}
+
 // ---- orientation -------------------------------------------------------------------
 // rank[], core by rank, key by rank (key of the id local to the vertex's graph),
 // and the graph of each rank when a batch is loaded as one disjoint union.
@@ -563,6 +750,68 @@ __global__ void __launch_bounds__(64) k_sort_rows(const uint32_t* __restrict__ o
 
 }  // namespace
 
+namespace {
+
+const void* hmisc_zero()
+{
+    static const uint64_t z[4] = {0, 0, 0, 0};
+    return z;
+}
+
+// The peel as one cooperative launch (k_peel_persistent).  peeled = false
+// leaves the caller to run the step kernels: the device does not support
+// cooperative launches, the launch was refused, or a barrier wait timed out.
+mce_status peel_single_launch(const uint32_t* rp, const uint32_t* ci, uint32_t n, PeelBufs pb, uint32_t* deg,
+                              uint32_t* round, uint32_t* core, hipStream_t s, PeelState& hs, bool& peeled)
+{
+    peeled = false;
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    MCE_HIP_TRY(hipGetDevice(&dev));
+    MCE_HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    MCE_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (!coop || cus <= 0) return MCE_OK;
+    MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_peel_persistent),
+                                                             256, 0));
+    per_cu = std::min(per_cu, 2);
+    if (per_cu < 1) return MCE_OK;
+    const uint32_t nb = (uint32_t)(per_cu * cus);
+    DevBuf sync;
+    mce_status st;
+    if ((st = sync.alloc(sizeof(PeelSync))) != MCE_OK) return st;
+    PeelSync h0;
+    std::memset(&h0, 0, sizeof(h0));
+    for (auto& sl : h0.slot) sl.min_deg = kUnset;
+    MCE_HIP_TRY(hipMemcpyAsync(sync.p, &h0, sizeof(h0), hipMemcpyHostToDevice, s));
+    PeelSync* dsync = sync.as<PeelSync>();
+    uint64_t ticks = 30ull * 100000000ull;  // 30 s of the 100 MHz device clock per barrier wait
+    void* args[] = {(void*)&rp, (void*)&ci, (void*)&n, (void*)&pb, (void*)&deg, (void*)&round, (void*)&core,
+                    (void*)&dsync, (void*)&ticks};
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_peel_persistent), dim3(nb), dim3(256),
+                                              args, 0, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return MCE_OK;
+    }
+    PeelSync out;
+    MCE_HIP_TRY(hipMemcpyAsync(&out, dsync, sizeof(out), hipMemcpyDeviceToHost, s));
+    MCE_HIP_TRY(hipStreamSynchronize(s));
+    if (out.err & 1u) return MCE_OK;
+    if (out.err & 2u) {
+        set_error("internal: peel found no remaining vertex");
+        return MCE_ERR_DEVICE;
+    }
+    if ((out.err & 4u) || !out.out_done) {
+        set_error("internal: peel did not finish within 2n + 4 rounds");
+        return MCE_ERR_DEVICE;
+    }
+    hs.r = out.out_r;
+    hs.k = out.out_k;
+    peeled = true;
+    return MCE_OK;
+}
+
+}  // namespace
+
 mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t nnz,
                             bool validate, hipStream_t s, Oriented& g, const uint32_t* gid_in,
                             const uint32_t* voff, uint32_t ngraphs)
@@ -679,13 +928,36 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     g.n_isolated = hmisc[1];
 
     PeelState hs{};
-    if (n) {
+    PeelBufs pb;
+    pb.alive[0] = alive_a.as<uint32_t>();
+    pb.alive[1] = alive_b.as<uint32_t>();
+    pb.front[0] = front_a.as<uint32_t>();
+    pb.front[1] = front_b.as<uint32_t>();
+    bool peeled = n == 0;
+    g.peel_mode = 0;
+    if (n && !g.peel_steps) {
+        // one launch with grid barriers; falls back to the step kernels when the
+        // device cannot run it (no cooperative launch, or a barrier timed out)
+        if ((st = peel_single_launch(rp, ci, n, pb, deg.as<uint32_t>(), dround, dcore, s, hs, peeled)) != MCE_OK)
+            return st;
+        if (peeled) g.peel_mode = 1;
+        else {
+            // start over: the attempt may have removed vertices
+            MCE_HIP_TRY(hipMemcpyAsync(dmisc, hmisc_zero(), 32, hipMemcpyHostToDevice, s));
+            PeelState p0{};
+            p0.n_alive = n;
+            p0.min_deg = kUnset;
+            p0.need_level = 1u;
+            MCE_HIP_TRY(hipMemcpyAsync(ps, &p0, sizeof(p0), hipMemcpyHostToDevice, s));
+            k_peel_init<<<blocks_for(n, 256, 4096), 256, 0, s>>>(rp, n, deg.as<uint32_t>(), dround,
+                                                                  alive_a.as<uint32_t>(), dmisc);
+            MCE_HIP_TRY(hipGetLastError());
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
+    if (!peeled) {
+        g.peel_mode = 2;
         // kPeelSteps steps captured once, replayed until the peel is done
-        PeelBufs pb;
-        pb.alive[0] = alive_a.as<uint32_t>();
-        pb.alive[1] = alive_b.as<uint32_t>();
-        pb.front[0] = front_a.as<uint32_t>();
-        pb.front[1] = front_b.as<uint32_t>();
         const unsigned gsel = blocks_for(n, 256, 1024), gdec = blocks_for(n, 4, 2048);
         hipStream_t cs = nullptr;
         hipGraph_t graph = nullptr;

@@ -29,6 +29,7 @@ MCE_ERR_UNSUPPORTED = -7
 
 MCE_LOAD_DEVICE_PTRS = 0x1
 MCE_LOAD_NO_VALIDATE = 0x2
+MCE_LOAD_PEEL_STEPS = 0x4
 
 F_WORKER_LIST = 0x01
 F_LEARNED_ORDER = 0x02
@@ -66,7 +67,8 @@ class MCEError(RuntimeError):
 class GraphInfo(C.Structure):
     _fields_ = [("n", C.c_uint32), ("nnz", C.c_uint64), ("max_degree", C.c_uint32),
                 ("degeneracy", C.c_uint32), ("n_isolated", C.c_uint64), ("peel_rounds", C.c_uint32),
-                ("max_out_degree", C.c_uint32), ("max_in_degree", C.c_uint32), ("n_graphs", C.c_uint32)]
+                ("max_out_degree", C.c_uint32), ("max_in_degree", C.c_uint32), ("n_graphs", C.c_uint32),
+                ("peel_mode", C.c_uint32)]
 
 
 class Options(C.Structure):
@@ -228,10 +230,11 @@ class Graph:
         self.free()
 
 
-def load_csr(row_ptr, col_idx, n: int | None = None, validate: bool = True, stream=None) -> Graph:
+def load_csr(row_ptr, col_idx, n: int | None = None, validate: bool = True, stream=None,
+             peel_steps: bool = False) -> Graph:
     """Load a CSR graph from numpy arrays (host) or torch device tensors."""
     lib = load_library()
-    flags = 0 if validate else MCE_LOAD_NO_VALIDATE
+    flags = (0 if validate else MCE_LOAD_NO_VALIDATE) | (MCE_LOAD_PEEL_STEPS if peel_steps else 0)
     if _is_device_tensor(row_ptr):
         flags |= MCE_LOAD_DEVICE_PTRS
         nn = int(row_ptr.numel()) - 1 if n is None else n
@@ -257,12 +260,12 @@ def load_csr(row_ptr, col_idx, n: int | None = None, validate: bool = True, stre
     return Graph(h)
 
 
-def load_graph(g, validate: bool = True) -> Graph:
+def load_graph(g, validate: bool = True, peel_steps: bool = False) -> Graph:
     """Load an ``inputs.CSRGraph``."""
-    return load_csr(g.row_ptr, g.col_idx, g.n, validate=validate)
+    return load_csr(g.row_ptr, g.col_idx, g.n, validate=validate, peel_steps=peel_steps)
 
 
-def load_batch(graphs, validate: bool = True) -> Graph:
+def load_batch(graphs, validate: bool = True, peel_steps: bool = False) -> Graph:
     """mce_load_csr_batch from host arrays (a list of CSRGraph)."""
     from .inputs import concat_batch
 
@@ -271,7 +274,7 @@ def load_batch(graphs, validate: bool = True) -> Graph:
     if ci.size == 0:
         ci = np.zeros(1, dtype=np.uint32)
     h = C.c_void_p()
-    flags = 0 if validate else MCE_LOAD_NO_VALIDATE
+    flags = (0 if validate else MCE_LOAD_NO_VALIDATE) | (MCE_LOAD_PEEL_STEPS if peel_steps else 0)
     st = lib.mce_load_csr_batch(C.c_void_p(rp.ctypes.data), C.c_void_p(ci.ctypes.data),
                                 C.c_void_p(row_off.ctypes.data), C.c_void_p(col_off.ctypes.data),
                                 len(graphs), flags, _torch_stream(), C.byref(h))

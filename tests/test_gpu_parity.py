@@ -228,12 +228,15 @@ def test_root_features_reject_bad_ids(gpu_lib):
 @pytest.mark.parametrize("make", [lambda: I.workload("er1000"),
                                   lambda: I.rmat(13, 16, 0.57, 0.19, 0.19, 0.05, 3),
                                   lambda: I.path_graph(300), lambda: I.fig1a_example()])
-def test_peel_matches_sync_simulation(gpu_lib, make):
+@pytest.mark.parametrize("peel_steps", [False, True], ids=["single_launch", "step_kernels"])
+def test_peel_matches_sync_simulation(gpu_lib, make, peel_steps):
     g = make()
     core, rnd, nr = oracle.sync_peel(g)
-    with gpu_lib.load_graph(g) as dg:
+    with gpu_lib.load_graph(g, peel_steps=peel_steps) as dg:
         gc, gr, order = dg.order_arrays()
         info = dg.info()
+    # the single launch must be the one that ran (no silent fall back)
+    assert info.peel_mode == (0 if g.n == 0 else 2 if peel_steps else 1)
     assert (gc == core).all()
     assert (gr == rnd).all()
     assert info.peel_rounds == nr
