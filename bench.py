@@ -7,9 +7,9 @@ learned form: root features, BF16 cost-model inference, ordering and split),
 and the persistent enumeration kernel, ending with the results on the host.
 
 Workloads (seeded synthetic graphs shaped like the paper's inputs):
-  rmat18     R-MAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 2,
-             core window c = 264 (default)
-  rmat22     R-MAT scale 22, edge factor 32, same quadrants, seed 5, window c = 425
+  rmat22     R-MAT scale 22, edge factor 32, a=.57 b=.19 c=.19 d=.05, seed 5,
+             core window c = 425 (default: the largest single-GPU workload)
+  rmat18     R-MAT scale 18, edge factor 16, same quadrants, seed 2, window c = 264
   chunglu1m  Chung-Lu 1M vertices (exponent 2.1, max weight 5000) + 2000 planted
              cliques of size U[20,60], seed 3, full enumeration
   er1000     Erdos-Renyi G(1000, 0.02), seed 1, full enumeration
@@ -24,13 +24,19 @@ Forms:
   batched    (batch4096) every graph in one launch, knobs autotuned beforehand
              on a held-out batch (512 graphs, seed 104)
   batched_learned  the batched form with the learned order and split
-  sequential (batch4096) one load + enumerate per graph
+  sequential (batch4096) one load + enumerate per graph, plain form
+
+By default the line reports R-MAT 22 in the learned form with the plain form
+timed beside it at equal results, and a "batch" section with the 4096-graph
+batch in the batched+learned, batched and sequential forms.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -43,19 +49,28 @@ sys.path.insert(0, ROOT)
 
 FULL = 0xFFFFFFFF
 WORKLOADS = {
-    "er1000": dict(kind="graph", c=FULL, form="plain", compare="",
+    "er1000": dict(kind="graph", c=FULL, form="plain", compare="", cpu_mod=1,
                    desc="Erdos-Renyi G(n=1000, p=0.02), seed 1, full enumeration"),
-    "rmat18": dict(kind="graph", c=264, form="plain", compare="learned",
+    "rmat18": dict(kind="graph", c=264, form="plain", compare="learned", cpu_mod=4,
                    desc="R-MAT scale 18, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 2, core window c=264"),
-    "chunglu1m": dict(kind="graph", c=FULL, form="plain", compare="",
+    "chunglu1m": dict(kind="graph", c=FULL, form="plain", compare="learned", cpu_mod=4,
                       desc="Chung-Lu 1M vertices, exponent 2.1, max weight 5000, 2000 planted cliques U[20,60], "
                            "seed 3, full enumeration"),
-    "rmat22": dict(kind="graph", c=425, form="learned", compare="plain",
+    "rmat22": dict(kind="graph", c=425, form="learned", compare="plain", cpu_mod=256,
                    desc="R-MAT scale 22, edge factor 32, a=.57 b=.19 c=.19 d=.05, seed 5, core window c=425"),
-    "batch4096": dict(kind="batch", c=FULL, form="batched", compare="",
+    "batch4096": dict(kind="batch", c=FULL, form="batched_learned", compare="batched,sequential", cpu_mod=64,
                       desc="4096 graphs, n log-uniform [50,5000], half ER avg degree U[5,40], half planted "
                            "partition (8 blocks, p_in .3, p_out .005), seed 4, full enumeration"),
 }
+
+# MI355X peaks (published; gfx950 unit counts at the 2.4 GHz peak clock)
+HBM_PEAK_GBS = 8000.0
+CUS, SIMDS, CLOCK_GHZ = 256, 4, 2.4
+# one wave64 VALU instruction per SIMD every 4 cycles; one scalar instruction per CU and cycle
+VALU_PEAK_GINST = CUS * SIMDS * CLOCK_GHZ / 4
+SALU_PEAK_GINST = CUS * CLOCK_GHZ
+# LDS: 128 bytes per CU and cycle
+LDS_PEAK_GBS = CUS * 128 * CLOCK_GHZ
 
 
 def log(*a):
@@ -73,20 +88,56 @@ def algorithmic_bytes(stats) -> int:
             + 8 * stats["xcol_words"] + 4 * stats["probes"])
 
 
-def measured_traffic(workload: str, c: int):
-    """HBM bytes per launch of k_enumerate from the committed rocprofv3 counter
-    summary, used only when it was taken on the current kernel source and on
-    this workload; otherwise None."""
-    import glob
-    import hashlib
-
+def kernel_source_sha() -> str:
     src = os.path.join(ROOT, "paper_2212_01473_amd", "csrc", "enumerate.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    for path in glob.glob(os.path.join(ROOT, "profiles", "k_enumerate_*_traffic.json")):
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def committed_profile(kind: str, workload: str, c: int):
+    """A committed rocprofv3 counter summary of k_enumerate (profiles/*_<kind>.json)
+    taken on the current kernel source and on this workload, else None."""
+    sha = kernel_source_sha()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_enumerate_*_{kind}.json"))):
         d = json.load(open(path))
         if d.get("source_sha256_prefix") == sha and d.get("workload") == f"{workload} c={c}":
-            return d["fetch_bytes"] + d["write_bytes"]
+            d["file"] = os.path.relpath(path, ROOT)
+            return d
     return None
+
+
+def rooflines(workload: str, c: int, st, kern_ms: float):
+    """The roofline objects of the dominant kernel (k_enumerate).  Instruction
+    issue binds it: the SQ counter summary gives instructions per tree node,
+    scaled to this launch's nodes and divided by the live kernel time.  HBM:
+    the kernel's algorithmic bytes over the same time; traffic from the
+    FETCH_SIZE / WRITE_SIZE summary.  LDS: the bytes of the LDS instructions
+    counted, at most 8 bytes per lane."""
+    sec = kern_ms / 1e3
+    alg = algorithmic_bytes(st)
+    traffic = committed_profile("traffic", workload, c)
+    hbm = {"bound": "hbm", "kernel": "k_enumerate", "achieved": round(alg / sec / 1e9, 2), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(alg / sec / 1e9 / HBM_PEAK_GBS, 5),
+           "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
+           "algorithmic_bytes": alg, "avg_kernel_ms": round(kern_ms, 3)}
+    sq = committed_profile("sq", workload, c)
+    if sq is None:
+        return hbm, {"hbm": hbm}
+    nodes = st["nodes"]
+    valu = sq["valu_per_node"] * nodes / sec / 1e9
+    salu = sq["salu_per_node"] * nodes / sec / 1e9
+    lds = sq["lds_per_node"] * nodes * 64 * 8 / sec / 1e9
+    fv, fs = valu / VALU_PEAK_GINST, salu / SALU_PEAK_GINST
+    issue = {"bound": "alu", "kernel": "k_enumerate", "achieved": round(max(valu, salu), 2),
+             "peak": round(VALU_PEAK_GINST if fv >= fs else SALU_PEAK_GINST, 1), "unit": "Ginst/s",
+             "frac": round(max(fv, fs), 4), "traffic": hbm["traffic"],
+             "binding": "valu issue" if fv >= fs else "salu issue",
+             "valu": {"achieved": round(valu, 2), "peak": round(VALU_PEAK_GINST, 1), "frac": round(fv, 4)},
+             "salu": {"achieved": round(salu, 2), "peak": round(SALU_PEAK_GINST, 1), "frac": round(fs, 4)},
+             "per_node": {k: sq[k] for k in ("valu_per_node", "salu_per_node", "lds_per_node", "vmem_per_node")},
+             "counters": sq["file"], "avg_kernel_ms": round(kern_ms, 3)}
+    lds_o = {"bound": "lds", "achieved": round(lds, 2), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
+             "frac": round(lds / LDS_PEAK_GBS, 5), "note": "upper bound: 8 bytes per lane of every LDS instruction"}
+    return issue, {"hbm": hbm, "lds": lds_o}
 
 
 def cpu_baseline_graph(g, c, frac_mod: int):
@@ -128,23 +179,173 @@ def cpu_baseline_batch(batch, every: int):
                       f"{dt:.2f} s", "seconds": round(dt, 3)}
 
 
+def timed(steps, f, nsteps, nwarm):
+    """nwarm untimed steps, then nsteps timed between device synchronisations;
+    every step must give the same results."""
+    import torch
+
+    for i in range(nwarm):
+        res, st, _ = steps[f]()
+        log(f"[bench] {f} warmup {i}: count={sum(r.count for r in res)} kernel={st['kernel_ns'] / 1e6:.1f}ms")
+    torch.cuda.synchronize()
+    out = []
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        out.append(steps[f]())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    keys = {tuple((r.count, r.hash) for r in res) for res, _, _ in out}
+    assert len(keys) == 1, f"{f}: results differ between steps"
+    return out, el / nsteps
+
+
+def result_key(res):
+    return tuple((r.count, r.hash, tuple(r.hist.tolist())) for r in res)
+
+
+def graph_steps(name, c, knobs, forms):
+    """Step callables of a single-graph workload for the requested forms."""
+    import torch
+
+    from paper_2212_01473_amd import inputs as I
+    from paper_2212_01473_amd import mce
+
+    t0 = time.perf_counter()
+    g = I.workload(name)
+    log(f"[bench] workload {name}: n={g.n} m={g.m} ready in {time.perf_counter() - t0:.1f}s")
+    rp = torch.from_numpy(g.row_ptr.astype(np.int64)).to(torch.int32).cuda()
+    ci = torch.from_numpy(g.col_idx.astype(np.int64)).to(torch.int32).cuda()
+    model = None
+    if "learned" in forms:
+        from paper_2212_01473_amd import learned
+
+        t1 = time.perf_counter()
+        model = learned.cached_model()
+        log(f"[bench] cost model ready in {time.perf_counter() - t1:.1f}s")
+
+    def graph_step(extra):
+        def step():
+            dg = mce.load_csr(rp, ci, g.n)
+            info = dg.info()
+            r = mce.enumerate_cliques(dg, max_root_core=c, hist_len=info.degeneracy + 2, **knobs, **extra)
+            dg.free()
+            return [r], r.stats, info
+        return step
+
+    steps = {"plain": graph_step({}), "l2": graph_step(dict(l2_roots=True))}
+    if model is not None:
+        steps["learned"] = graph_step(dict(model=model, split=True))
+    return g, steps
+
+
+def batch_steps(knobs, forms):
+    import torch
+
+    from paper_2212_01473_amd import inputs as I
+    from paper_2212_01473_amd import mce
+
+    t0 = time.perf_counter()
+    batch = I.workload_batch("batch4096")
+    log(f"[bench] batch4096: {len(batch)} graphs, {int(batch.row_off[-1]) - len(batch)} vertices, "
+        f"{batch.col_idx_cat.size // 2} edges, ready in {time.perf_counter() - t0:.1f}s")
+    rp = torch.from_numpy(batch.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
+    ci = torch.from_numpy(batch.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
+    # knobs tuned on a held-out batch, outside the timed region
+    t1 = time.perf_counter()
+    tb = I.workload_batch("batch512_tune")
+    trp = torch.from_numpy(tb.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
+    tci = torch.from_numpy(tb.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
+    with mce.load_batch_device(trp, tci, tb.row_off, tb.col_off) as tg:
+        tuned, rep = mce.autotune(tg, **knobs)
+    log(f"[bench] autotuned on the held-out batch in {time.perf_counter() - t1:.1f}s: {rep}")
+    del trp, tci
+    bmodel = None
+    if "batched_learned" in forms:
+        from paper_2212_01473_amd import learned
+
+        bmodel = learned.cached_model()
+
+    def batched():
+        dg = mce.load_batch_device(rp, ci, batch.row_off, batch.col_off)
+        res = mce.enumerate_batch(dg, options=tuned)
+        dg.free()
+        return res, res[0].stats, None
+
+    def batched_learned():
+        dg = mce.load_batch_device(rp, ci, batch.row_off, batch.col_off)
+        opt = mce.make_options(**knobs, model=bmodel, split=True)
+        for k in ("donate_min_p", "bitmap_max_p", "wg_per_cu", "donate_max_depth", "xrow_ratio"):
+            setattr(opt, k, getattr(tuned, k))
+        res = mce.enumerate_batch(dg, options=opt)
+        dg.free()
+        return res, res[0].stats, None
+
+    def sequential():
+        res, stats = [], None
+        for i in range(len(batch)):
+            a, b = int(batch.row_off[i]), int(batch.row_off[i + 1])
+            cc, d = int(batch.col_off[i]), int(batch.col_off[i + 1])
+            dg = mce.load_csr(rp[a:b], ci[cc:d] if d > cc else ci[:1], b - a - 1)
+            r = mce.enumerate_cliques(dg, **knobs)
+            dg.free()
+            res.append(r)
+            stats = r.stats
+        return res, stats, None
+
+    steps = {"batched": batched, "batched_learned": batched_learned, "sequential": sequential}
+    return batch, steps, rep
+
+
+def compare_forms(steps, forms, key, nsteps, nwarm, reported_sec, count):
+    comp = {}
+    for f in forms:
+        one = f == "sequential"
+        cr, csec = timed(steps, f, 1 if one else nsteps, 0 if one else nwarm)
+        assert result_key(cr[-1][0]) == key, f"form {f} changed the results"
+        comp[f] = {"ms_per_step": round(csec * 1e3, 3), "value": count / csec,
+                   "kernel_ms": round(cr[-1][1]["kernel_ns"] / 1e6, 3),
+                   "setup_ms": round(cr[-1][1]["setup_ns"] / 1e6, 3),
+                   "reported_form_speedup": round(csec / reported_sec, 3)}
+        log(f"[bench] {f}: {csec * 1e3:.1f} ms/step (reported form: {reported_sec * 1e3:.1f})")
+    return comp
+
+
+def batch_section(args, knobs):
+    """The 4096-graph batch: batched+learned (reported), batched, sequential."""
+    spec = WORKLOADS["batch4096"]
+    forms = ["batched_learned", "batched", "sequential"]
+    batch, steps, rep = batch_steps(knobs, forms)
+    n = min(args.steps, args.batch_steps)
+    runs, sec = timed(steps, forms[0], n, min(args.warmup, 1))
+    res = runs[-1][0]
+    count = sum(r.count for r in res)
+    comp = compare_forms(steps, forms[1:], result_key(res), n, min(args.warmup, 1), sec, count)
+    return {"workload": spec["desc"], "form": forms[0], "value": count / sec, "unit": "cliques/s",
+            "ms_per_step": round(sec * 1e3, 3), "steps": n, "count": count,
+            "kernel_ms": round(runs[-1][1]["kernel_ns"] / 1e6, 3), "autotuned": rep, "compare": comp}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--form", default=None,
                     choices=["plain", "learned", "l2", "batched", "batched_learned", "sequential"])
     ap.add_argument("--compare", default=None,
                     help="comma-separated forms also timed in this run, at equal results ('' for none)")
+    ap.add_argument("--compare-steps", type=int, default=10, help="at most this many timed steps per compared form")
+    ap.add_argument("--batch", choices=["on", "off"], default="on",
+                    help="with a single-graph workload, also time the 4096-graph batch section")
+    ap.add_argument("--batch-steps", type=int, default=5, help="at most this many timed steps per batch form")
     ap.add_argument("--window", type=int, default=None, help="override the core window c")
     ap.add_argument("--no-worker-list", action="store_true")
     ap.add_argument("--bitmap-max-p", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--donate-min-p", type=int, default=0)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
-    ap.add_argument("--cpu-sample-mod", type=int, default=4)
+    ap.add_argument("--cpu-sample-mod", type=int, default=0, help="0: the workload's default sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch one elementwise kernel that reads and writes 1 GiB each, as the "
                          "reference for scaling hardware byte counters")
@@ -157,7 +358,6 @@ def main():
 
     import torch
 
-    from paper_2212_01473_amd import inputs as I
     from paper_2212_01473_amd import mce
 
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -178,138 +378,37 @@ def main():
         del src, dst
         log("[bench] calibration kernel: 1 GiB read + 1 GiB written")
 
-    t0 = time.perf_counter()
-    steps = {}  # form -> callable returning (results, stats of the launch)
     if spec["kind"] == "graph":
-        g = I.workload(args.workload)
-        log(f"[bench] workload {args.workload}: n={g.n} m={g.m} ready in {time.perf_counter() - t0:.1f}s")
-        rp = torch.from_numpy(g.row_ptr.astype(np.int64)).to(torch.int32).cuda()
-        ci = torch.from_numpy(g.col_idx.astype(np.int64)).to(torch.int32).cuda()
-        model = None
-        if "learned" in [form] + compare:
-            from paper_2212_01473_amd import learned
-
-            t1 = time.perf_counter()
-            model = learned.cached_model()
-            log(f"[bench] cost model ready in {time.perf_counter() - t1:.1f}s")
-
-        def graph_step(extra):
-            def step():
-                dg = mce.load_csr(rp, ci, g.n)
-                info = dg.info()
-                r = mce.enumerate_cliques(dg, max_root_core=c, hist_len=info.degeneracy + 2, **knobs, **extra)
-                dg.free()
-                return [r], r.stats, info
-            return step
-
-        steps["plain"] = graph_step({})
-        steps["l2"] = graph_step(dict(l2_roots=True))  # second-level subtrees (Algorithm 4)
-        if model is not None:
-            steps["learned"] = graph_step(dict(model=model, split=True))
+        g, steps = graph_steps(args.workload, c, knobs, [form] + compare)
         units = g.n
     else:
-        batch = I.workload_batch(args.workload)
-        log(f"[bench] workload {args.workload}: {len(batch)} graphs, {int(batch.row_off[-1]) - len(batch)} "
-            f"vertices, {batch.col_idx_cat.size // 2} edges, ready in {time.perf_counter() - t0:.1f}s")
-        rp = torch.from_numpy(batch.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
-        ci = torch.from_numpy(batch.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
-        # knobs tuned on a held-out batch, outside the timed region
-        t1 = time.perf_counter()
-        tb = I.workload_batch("batch512_tune")
-        trp = torch.from_numpy(tb.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
-        tci = torch.from_numpy(tb.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
-        with mce.load_batch_device(trp, tci, tb.row_off, tb.col_off) as tg:
-            tuned, rep = mce.autotune(tg, **knobs)
-        log(f"[bench] autotuned on the held-out batch in {time.perf_counter() - t1:.1f}s: {rep}")
-        del trp, tci
-
-        def batched():
-            dg = mce.load_batch_device(rp, ci, batch.row_off, batch.col_off)
-            res = mce.enumerate_batch(dg, options=tuned)
-            dg.free()
-            return res, res[0].stats, None
-
-        bmodel = None
-        if "batched_learned" in [form] + compare:
-            from paper_2212_01473_amd import learned
-
-            bmodel = learned.cached_model()
-
-        def batched_learned():
-            dg = mce.load_batch_device(rp, ci, batch.row_off, batch.col_off)
-            opt = mce.make_options(**knobs, model=bmodel, split=True)
-            for k in ("donate_min_p", "bitmap_max_p", "wg_per_cu", "donate_max_depth", "xrow_ratio"):
-                setattr(opt, k, getattr(tuned, k))
-            res = mce.enumerate_batch(dg, options=opt)
-            dg.free()
-            return res, res[0].stats, None
-
-        def sequential():
-            res, stats = [], None
-            for i in range(len(batch)):
-                a, b = int(batch.row_off[i]), int(batch.row_off[i + 1])
-                cc, d = int(batch.col_off[i]), int(batch.col_off[i + 1])
-                dg = mce.load_csr(rp[a:b], ci[cc:d] if d > cc else ci[:1], b - a - 1)
-                r = mce.enumerate_cliques(dg, **knobs)
-                dg.free()
-                res.append(r)
-                stats = r.stats
-            return res, stats, None
-
-        steps["batched"] = batched
-        steps["batched_learned"] = batched_learned
-        steps["sequential"] = sequential
-        units = len(batch)
+        g, steps, _ = batch_steps(knobs, [form] + compare)
+        units = len(g)
     for f in [form] + compare:
         if f not in steps:
             raise SystemExit(f"form {f} does not apply to workload {args.workload}")
 
-    def timed(f, nsteps, nwarm):
-        for i in range(nwarm):
-            res, st, _ = steps[f]()
-            log(f"[bench] {f} warmup {i}: count={sum(r.count for r in res)} kernel={st['kernel_ns'] / 1e6:.1f}ms")
-        torch.cuda.synchronize()
-        out = []
-        t0 = time.perf_counter()
-        for i in range(nsteps):
-            out.append(steps[f]())
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        keys = {tuple((r.count, r.hash) for r in res) for res, _, _ in out}
-        assert len(keys) == 1, f"{f}: results differ between steps"
-        return out, el / nsteps
-
-    runs, sec = timed(form, args.steps, args.warmup)
+    runs, sec = timed(steps, form, args.steps, args.warmup)
     res, st, info = runs[-1]
-    key = tuple((r.count, r.hash, tuple(r.hist.tolist())) for r in res)
+    key = result_key(res)
     count = sum(r.count for r in res)
     for i, (rr, s, _) in enumerate(runs):
         log(f"[bench] {form} step {i}: count={sum(r.count for r in rr)} kernel={s['kernel_ns'] / 1e6:.2f}ms "
             f"setup={s['setup_ns'] / 1e6:.2f}ms nodes={s['nodes']} donations={s['donations']}")
-    comp = {}
-    for f in compare:
-        cr, csec = timed(f, max(1, args.steps if f != "sequential" else 1), args.warmup if f != "sequential" else 0)
-        ckey = tuple((r.count, r.hash, tuple(r.hist.tolist())) for r in cr[-1][0])
-        assert ckey == key, f"form {f} changed the results"
-        comp[f] = {"ms_per_step": round(csec * 1e3, 3), "value": count / csec,
-                   "kernel_ms": round(cr[-1][1]["kernel_ns"] / 1e6, 3),
-                   "setup_ms": round(cr[-1][1]["setup_ns"] / 1e6, 3), "speedup_of_reported_form": round(csec / sec, 3)}
-        log(f"[bench] {f}: {csec * 1e3:.1f} ms/step (reported form {form}: {sec * 1e3:.1f})")
+    comp = compare_forms(steps, compare, key, min(args.steps, args.compare_steps), min(args.warmup, 1), sec, count)
 
     kern_ms = sum(s["kernel_ns"] for _, s, _ in runs) / len(runs) / 1e6
-    alg = algorithmic_bytes(st)
-    achieved = alg / (kern_ms / 1e3) / 1e9
-    peak = 8000.0
     cfg = {"workload": spec["desc"] if args.window is None else f"{args.workload} c={c}", "form": form,
            "count": count, "units": units}
     if info is not None:
         cfg.update({"n": int(info.n), "degeneracy": int(info.degeneracy), "max_degree": int(info.max_degree),
                     "core_window": c if c != FULL else "full", "hash": f"{res[0].hash:#018x}",
-                    "max_clique": res[0].max_size})
+                    "max_clique": res[0].max_size, "peel_mode": int(info.peel_mode)})
     cfg.update({"workgroups": st["workgroups"], "tree_nodes": st["nodes"], "donations": st["donations"],
                 "kernel_ms": round(kern_ms, 3), "setup_ms": round(st["setup_ns"] / 1e6, 3)})
+    roof, others = rooflines(args.workload, c, st, kern_ms)
     out = {
-        "metric": "maximal cliques/sec (wall time per step in ms_per_step)",
+        "metric": "maximal cliques/sec (wall time per step in ms_per_step); learned vs plain form",
         "value": count / sec,
         "unit": "cliques/s",
         "n_gpus": 1,
@@ -323,17 +422,18 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": cfg,
         "compare": comp,
-        "roofline": {"bound": "hbm", "kernel": "k_enumerate", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "GB/s", "frac": round(achieved / peak, 5),
-                     "traffic": measured_traffic(args.workload, c) if spec["kind"] == "graph" else None,
-                     "algorithmic_bytes": alg, "avg_kernel_ms": round(kern_ms, 3)},
+        "roofline": roof,
+        "roofline_other": others,
     }
+    if spec["kind"] == "graph" and args.batch == "on":
+        out["batch"] = batch_section(args, knobs)
     if args.cpu_baseline == "on":
         log("[bench] timing the CPU oracle on a sample")
+        mod = args.cpu_sample_mod or spec["cpu_mod"]
         if spec["kind"] == "graph":
-            out["cpu_baseline"] = cpu_baseline_graph(g, c, args.cpu_sample_mod)
+            out["cpu_baseline"] = cpu_baseline_graph(g, c, mod)
         else:
-            out["cpu_baseline"] = cpu_baseline_batch(batch, 64)
+            out["cpu_baseline"] = cpu_baseline_batch(g, mod)
     print(json.dumps(out), flush=True)
 
 

@@ -204,3 +204,60 @@ def test_trained_model_ranks_held_out_roots(gpu_lib):
     rl = np.argsort(np.argsort(lab))
     rho = np.corrcoef(rp, rl)[0, 1]
     assert rho > 0.6, rho
+
+
+def _list_schedule_makespan(cost, order, machines):
+    """Greedy list scheduling: the roots in the given order, each to the
+    machine that becomes free first (what a shared root counter does with
+    equal workgroups and no donations); the largest finishing time."""
+    import heapq
+
+    free = [0.0] * machines
+    for j in order:
+        heapq.heapreplace(free, free[0] + float(cost[j]))
+    return max(free)
+
+
+def test_trained_model_gains_over_degeneracy_order(gpu_lib):
+    """What the trained network gains over the method without it, measured on
+    a held-out graph from the per-root tree-node counts of the plain run:
+    recall of the heaviest 1% of roots among the first 1% of the queue, and
+    the makespan of the queue under list scheduling, for degeneracy order
+    (the plain queue), the out-degree heuristic and the model's order."""
+    import torch
+    from paper_2212_01473_amd import learned
+
+    model = _trained_model(gpu_lib)
+    g = I.rmat(15, 16, 0.57, 0.19, 0.19, 0.05, 97)
+    n_nodes = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros_like(n_nodes)
+    hsh = torch.zeros_like(n_nodes)
+    with gpu_lib.load_graph(g) as dg:
+        c = int(0.7 * dg.info().degeneracy)
+        gpu_lib.enumerate_cliques(dg, max_root_core=c, root_stats=(cnt, hsh, n_nodes))
+        core, _, order = dg.order_arrays()
+        rank = np.empty(g.n, dtype=np.int64)
+        rank[order] = np.arange(g.n)
+        roots = order[(core[order] <= c)]
+        src = np.repeat(np.arange(g.n), g.degrees())
+        later = rank[g.col_idx.astype(np.int64)] > rank[src]
+        outdeg = np.bincount(src[later], minlength=g.n)
+        roots = roots[outdeg[roots] > 0]  # the queue: window roots with P non-empty, in degeneracy order
+        feat = gpu_lib.root_features(dg, torch.from_numpy(roots.astype(np.int32)).cuda())
+    pred = gpu_lib.model_predict(model, feat).cpu().numpy()
+    cost = n_nodes.cpu().numpy()[roots].astype(np.float64)
+    nr = len(roots)
+    top = max(1, nr // 100)
+    heavy = set(np.argsort(-cost, kind="stable")[:top].tolist())
+    orders = {
+        "degeneracy": np.arange(nr),
+        "out_degree": np.argsort(-outdeg[roots], kind="stable"),
+        "model": np.argsort(-pred, kind="stable"),
+    }
+    machines = 256
+    lower = max(cost.sum() / machines, cost.max())
+    recall = {k: len(heavy & set(o[:top].tolist())) / top for k, o in orders.items()}
+    makespan = {k: _list_schedule_makespan(cost, o, machines) / lower for k, o in orders.items()}
+    print(f"roots {nr}, top 1% = {top}: recall {recall}; makespan / lower bound {makespan}")
+    assert recall["model"] > recall["degeneracy"]
+    assert makespan["model"] < makespan["degeneracy"]

@@ -42,21 +42,40 @@ def test_full_workload_matches_oracle(gpu_lib, name, workload):
             assert _hist_dict(r.hist) == exp["hist"], kw
 
 
-def test_batch4096_sampled_graphs_match_oracle(gpu_lib):
+GOLD_BATCH = json.load(open(os.path.join(ROOT, "tests", "golden", "batch4096_full.json")))
+
+
+def _batch_sha256(batch) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for a in (batch.row_ptr_cat, batch.col_idx_cat, batch.row_off, batch.col_off):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("form", ["batched", "batched_learned"])
+def test_batch4096_every_graph_matches_oracle(gpu_lib, form):
+    """All 4,096 graphs of the batch (both halves: Erdos-Renyi and planted
+    partition) in one launch, each against the oracle's count, hash and
+    histogram; the learned order and split must not change any of them."""
     import torch
 
-    exp = GOLD["batch4096_sample"]
+    exp = GOLD_BATCH
     batch = I.workload_batch("batch4096")
+    assert _batch_sha256(batch) == exp["batch_sha256"]
     rp = torch.from_numpy(batch.row_ptr_cat.astype(np.int64)).to(torch.int32).cuda()
     ci = torch.from_numpy(batch.col_idx_cat.astype(np.int64)).to(torch.int32).cuda()
+    kw = dict(model=_untrained_model(), split=True) if form == "batched_learned" else {}
     with gpu_lib.load_batch_device(rp, ci, batch.row_off, batch.col_off) as dg:
-        res = gpu_lib.enumerate_batch(dg, timeout_ms=120000)
-    assert len(res) == len(batch) == 4096
-    for key, e in exp["graphs"].items():
-        i = int(key)
-        assert batch.graph(i).sha256() == e["sha256"], i
-        r = res[i]
-        assert (r.count, f"{r.hash:#018x}", _hist_dict(r.hist)) == (e["count"], e["hash"], e["hist"]), i
+        res = gpu_lib.enumerate_batch(dg, timeout_ms=300000, **kw)
+    assert len(res) == len(batch) == exp["n_graphs"] == 4096
+    bad = []
+    for i, (r, e) in enumerate(zip(res, exp["graphs"])):
+        if (r.count, f"{r.hash:#018x}", _hist_dict(r.hist)) != (e[0], e[1], e[2]):
+            bad.append(i)
+    assert not bad, f"{len(bad)} graphs differ, first {bad[:10]}"
+    assert sum(r.count for r in res) == sum(e[0] for e in exp["graphs"])
 
 
 def test_rmat22_sampled_roots_match_oracle(gpu_lib):
