@@ -10,8 +10,9 @@ Kingma and Ba, "Adam: A Method for Stochastic Optimization", ICLR 2015
 
 Features of a first-level subtree of root v (plain definitions): log(1 +
 degree), log(1 + core number), log(1 + sum of neighbour degrees), and the edge
-density of P = the later neighbours of v (edges inside P over C(|P|, 2), 0 if
-|P| < 2).
+density of P = the later neighbours of v: edges inside P over C(|P|, 2) (0 if
+|P| < 2) when C(|P|, 2) <= 256, else the fraction of adjacent pairs among 256
+pairs of P drawn from SplitMix64 (see sampled_pair).
 """
 from __future__ import annotations
 
@@ -110,6 +111,33 @@ def fit_norm(theta, X):
     return out
 
 
+DENSITY_PAIRS = 256
+_GAMMA = 0x9E3779B97F4A7C15
+_MASK = (1 << 64) - 1
+
+
+def splitmix64(c: int, seed: int = 0) -> int:
+    """Output number c (from 0) of SplitMix64 with the given seed (Steele, Lea
+    and Flood, OOPSLA 2014): the finaliser applied to seed + (c + 1) * gamma."""
+    z = (seed + (c + 1) * _GAMMA) & _MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+    return z ^ (z >> 31)
+
+
+def sampled_pair(v: int, t: int, k: int):
+    """Pair t (0 <= t < DENSITY_PAIRS) of positions in a k-element P of root v
+    (input id): x = output t of SplitMix64 seeded with the vertex key of v
+    (output v of SplitMix64 seeded with 0); a = (low 32 bits of x) mod k;
+    b = (high 32 bits) mod (k - 1), moved past a.  Returns (i, j), i < j."""
+    x = splitmix64(t, seed=splitmix64(v))
+    a = (x & 0xFFFFFFFF) % k
+    b = (x >> 32) % (k - 1)
+    if b >= a:
+        b += 1
+    return min(a, b), max(a, b)
+
+
 def features(g, roots, order):
     """Features of the given roots (input ids) under the given vertex order."""
     n = g.n
@@ -123,15 +151,27 @@ def features(g, roots, order):
     for i, v in enumerate(roots):
         nb = g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]].astype(np.int64)
         P = nb[pos[nb] > pos[v]]
-        Pset = set(P.tolist())
-        e = 0
-        for u in P:
-            for w in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
-                if int(w) in Pset and pos[w] > pos[u]:
-                    e += 1
         k = len(P)
-        out[i] = [np.log1p(deg[v]), np.log1p(core[v]), np.log1p(deg[nb].sum()),
-                  e / (k * (k - 1) / 2) if k >= 2 else 0.0]
+        if k < 2:
+            density = 0.0
+        elif k * (k - 1) // 2 <= DENSITY_PAIRS:
+            Pset = set(P.tolist())
+            e = 0
+            for u in P:
+                for w in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                    if int(w) in Pset and pos[w] > pos[u]:
+                        e += 1
+            density = e / (k * (k - 1) / 2)
+        else:
+            Ps = P[np.argsort(pos[P], kind="stable")]  # P in the order's sequence
+            hits = 0
+            for t in range(DENSITY_PAIRS):
+                a, b = sampled_pair(int(v), t, k)
+                u, w = int(Ps[a]), int(Ps[b])
+                row = g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]
+                hits += int(np.any(row == w))
+            density = hits / DENSITY_PAIRS
+        out[i] = [np.log1p(deg[v]), np.log1p(core[v]), np.log1p(deg[nb].sum()), density]
     return out
 
 

@@ -126,6 +126,19 @@ struct Params {
     uint64_t tlog_min_ticks;
 };
 
+// The enumeration kernel's Params, read from the kernel-argument segment (it is
+// the kernel's only argument) through a pointer the compiler cannot see through,
+// so each function loads the fields it uses where it uses them (scalar loads
+// from the constant cache) instead of keeping every field in scalar registers
+// for the whole persistent loop.
+typedef const __attribute__((address_space(4))) Params* ParamsK;
+__device__ __forceinline__ const Params& kparams()
+{
+    ParamsK k = (ParamsK)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(k));
+    return *(const Params*)k;
+}
+
 // ---------------------------------------------------------------- wave helpers
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -226,6 +239,7 @@ struct LdsFixed {
                         // counter, list R offset
     uint32_t hist[kHistLds];
     uint32_t sidx[64], soff[64], sbeg[64], sxj[64];
+    uint32_t probes[64];  // per lane: list entries read by the X_X binary searches
 };
 __shared__ LdsFixed S;
 
@@ -235,27 +249,43 @@ __device__ inline void stat_add(int k, uint64_t v)
     if (__lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&S.stat[k]), (unsigned long long)v);
 }
 
+// The dynamic LDS of a workgroup: universe keys, universe ranks, bitmap rows.
+extern __shared__ __align__(16) unsigned char lds_dyn[];
+
 struct Wg {
-    // HBM scratch
-    MboxHdr* mbox;
-    uint32_t* mP;      // mailbox P ranks
-    uint32_t* mXP;     // mailbox X_P ranks
-    uint32_t* R;       // ranks of R
-    uint64_t* fr;      // mailbox fold frame
-    uint32_t* xr;      // the task's initial X_X ranks (mailbox target)
-    uint32_t* xx;      // X_X as indices into xr, partitioned in place
-    uint64_t* xflag;
-    uint32_t* hpos;
-    uint32_t* spos;
-    uint64_t* grows;
-    uint64_t* xrows;
-    uint64_t* xcols;
-    uint64_t* gstack;
-    uint64_t* gmeta;
-    // LDS sized per launch
-    uint32_t* uarr;
-    uint64_t* ukey;
-    uint64_t* lrows;
+    uint32_t me;        // this workgroup's index (selects its scratch block)
+    // Scratch and LDS regions, computed where they are used from the
+    // workgroup index and the launch's layout (no pointer stays in registers).
+    __device__ __forceinline__ uint8_t* base() const
+    {
+        const Params& p = kparams();
+        return p.scratch + (uint64_t)me * p.stride;
+    }
+    __device__ __forceinline__ MboxHdr* mbox() const { return reinterpret_cast<MboxHdr*>(base()); }
+    __device__ __forceinline__ uint32_t* mP() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_P); }     // mailbox P ranks
+    __device__ __forceinline__ uint32_t* mXP() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_XP); }   // mailbox X_P ranks
+    __device__ __forceinline__ uint32_t* R() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_R); }      // ranks of R
+    __device__ __forceinline__ uint64_t* fr() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_fr); }    // mailbox fold frame
+    __device__ __forceinline__ uint32_t* xr() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_xr); }    // the task's initial X_X ranks
+    __device__ __forceinline__ uint32_t* xx() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_xx); }    // X_X as indices into xr
+    __device__ __forceinline__ uint64_t* xflag() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_flag); }
+    __device__ __forceinline__ uint32_t* hpos() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_hpos); }
+    __device__ __forceinline__ uint32_t* spos() const { return reinterpret_cast<uint32_t*>(base() + kparams().off_spos); }
+    __device__ __forceinline__ uint64_t* grows() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_rows); }
+    __device__ __forceinline__ uint64_t* xrows() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_xrows); }
+    __device__ __forceinline__ uint64_t* xcols() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_xcols); }
+    __device__ __forceinline__ uint64_t* gstack() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_stack); }
+    __device__ __forceinline__ uint64_t* gmeta() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_meta); }
+    __device__ __forceinline__ uint64_t* ukey() const { return reinterpret_cast<uint64_t*>(lds_dyn); }
+    __device__ __forceinline__ uint32_t* uarr() const
+    {
+        return reinterpret_cast<uint32_t*>(lds_dyn + (size_t)kparams().ucap * 8);
+    }
+    __device__ __forceinline__ uint64_t* lrows() const
+    {
+        const uint32_t ucap = kparams().ucap;
+        return reinterpret_cast<uint64_t*>(lds_dyn + (size_t)ucap * 8 + (size_t)((ucap + 3) & ~3u) * 4);
+    }
     // current task
     uint32_t W;         // words of the task's universe
     uint32_t Wx;        // words of the task's X list bitmap (X columns built), else 0
@@ -267,35 +297,41 @@ struct Wg {
     uint64_t task_t0;
     uint64_t nodes, nodes_t0;  // search-tree nodes (all tasks; at the current task's start)
     uint64_t don_t0;  // start of the current donation attempt
-    uint32_t probes;  // per lane
     uint32_t wl_tick, wl_seen, poll, pops;
     uint32_t don_min;  // smallest |P| of a branch offered to the worker list (~0: no worker list)
     uint64_t deadline;
-    uint32_t me;
     bool abort;
 };
+// This workgroup's own state lives in LDS, so the scalar registers are left to
+// the search; the fields are touched outside the inner loops only.
+__shared__ Wg SW;
 
 // Is b among the later neighbours of x?  (x precedes b in the order.)
-__device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b, uint32_t& probes)
+__device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b)
 {
-    uint32_t lo = p.op[x], hi = p.op[x + 1];
+    uint32_t lo = p.op[x], hi = p.op[x + 1], probes = 0;
+    bool found = false;
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
         uint32_t v = p.oc[mid];
         ++probes;
-        if (v == b) return true;
+        if (v == b) {
+            found = true;
+            break;
+        }
         if (v < b) lo = mid + 1;
         else hi = mid;
     }
-    return false;
+    S.probes[__lane_id()] += probes;
+    return found;
 }
 
 // Adjacency of X_X entry j (index into xr) to the universe vertex with index
 // bidx and rank brank.
 __device__ inline bool xtest(const Params& p, Wg& w, uint32_t j, uint32_t bidx, uint32_t brank)
 {
-    if (w.have_xrows) return (w.xrows[(uint64_t)j * w.W + (bidx >> 6)] >> (bidx & 63)) & 1ull;
-    return has_later(p, w.xr[j], brank, w.probes);
+    if (w.have_xrows) return (w.xrows()[(uint64_t)j * w.W + (bidx >> 6)] >> (bidx & 63)) & 1ull;
+    return has_later(p, w.xr()[j], brank);
 }
 
 __device__ __forceinline__ bool xx_any(const Params& p, Wg& w, uint32_t L, uint32_t bidx, uint32_t brank)
@@ -303,7 +339,7 @@ __device__ __forceinline__ bool xx_any(const Params& p, Wg& w, uint32_t L, uint3
     const uint32_t lane = lane_id();
     for (uint32_t base = 0; base < L; base += 64) {
         uint32_t i = base + lane;
-        bool hit = i < L && xtest(p, w, w.xx[i], bidx, brank);
+        bool hit = i < L && xtest(p, w, w.xx()[i], bidx, brank);
         stat_add(S_XTESTS, min(64u, L - base));
         if (__ballot(hit)) return true;
     }
@@ -319,9 +355,9 @@ __device__ __forceinline__ uint32_t xx_partition(const Params& p, Wg& w, uint32_
     uint32_t K = 0;
     for (uint32_t base = 0; base < L; base += 64) {
         uint32_t i = base + lane;
-        bool keep = i < L && xtest(p, w, w.xx[i], bidx, brank);
+        bool keep = i < L && xtest(p, w, w.xx()[i], bidx, brank);
         uint64_t m = __ballot(keep);
-        if (lane == 0) w.xflag[base >> 6] = m;
+        if (lane == 0) w.xflag()[base >> 6] = m;
         K += (uint32_t)__popcll(m);
     }
     stat_add(S_XTESTS, L);
@@ -329,36 +365,38 @@ __device__ __forceinline__ uint32_t xx_partition(const Params& p, Wg& w, uint32_
     wave_mem_sync();
     uint32_t nh = 0;
     for (uint32_t base = 0; base < K; base += 64) {
-        uint64_t m = w.xflag[base >> 6];
+        uint64_t m = w.xflag()[base >> 6];
         uint32_t i = base + lane;
         bool hole = i < K && !((m >> lane) & 1ull);
         uint64_t hm = __ballot(hole);
-        if (hole) w.hpos[nh + prefix_popc(hm)] = i;
+        if (hole) w.hpos()[nh + prefix_popc(hm)] = i;
         nh += (uint32_t)__popcll(hm);
     }
     uint32_t ns = 0;
     for (uint32_t base = K & ~63u; base < L; base += 64) {
-        uint64_t m = w.xflag[base >> 6];
+        uint64_t m = w.xflag()[base >> 6];
         uint32_t i = base + lane;
         bool stray = i >= K && i < L && ((m >> lane) & 1ull);
         uint64_t sm = __ballot(stray);
-        if (stray) w.spos[ns + prefix_popc(sm)] = i;
+        if (stray) w.spos()[ns + prefix_popc(sm)] = i;
         ns += (uint32_t)__popcll(sm);
     }
     wave_mem_sync();
     for (uint32_t k = lane; k < nh; k += 64) {
-        uint32_t a = w.hpos[k], s = w.spos[k];
-        uint32_t va = w.xx[a], vs = w.xx[s];
-        w.xx[a] = vs;
-        w.xx[s] = va;
+        uint32_t a = w.hpos()[k], s = w.spos()[k];
+        uint32_t va = w.xx()[a], vs = w.xx()[s];
+        w.xx()[a] = vs;
+        w.xx()[s] = va;
     }
     wave_mem_sync();
     return K;
 }
 
 // ---------------------------------------------------------------- results
-__device__ __forceinline__ void flush_graph(const Params& p, Wg& w)
+__device__ __forceinline__ void flush_graph(const Params& p_arg, Wg& w)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     if (lane == 0 && (w.count | w.hash)) {
         atomicAdd(&p.gacc[2 * w.cur_gid], (unsigned long long)w.count);
@@ -379,8 +417,10 @@ __device__ __forceinline__ void flush_graph(const Params& p, Wg& w)
     w.hmax = 0;
 }
 
-__device__ void report(const Params& p, Wg& w, uint32_t rsize, uint64_t ks)
+__device__ void report(const Params& p_arg, Wg& w, uint32_t rsize, uint64_t ks)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     uint64_t h = fmix64(ks + (uint64_t)rsize * kGamma);
     w.count += 1;
     w.hash += h;
@@ -404,16 +444,20 @@ __device__ void report(const Params& p, Wg& w, uint32_t rsize, uint64_t ks)
         v = uni64(v);
         bool fits = v + rsize <= p.s_vcap;
         if (fits)
-            for (uint32_t j = lane; j < rsize; j += 64) p.s_verts[v + j] = p.perm[w.R[j]];
+            for (uint32_t j = lane; j < rsize; j += 64) p.s_verts[v + j] = p.perm[w.R()[j]];
         if (lane == 0) {
             if (c < p.s_ocap) p.s_offs[c] = fits ? ((v << 16) | rsize) : ~0ull;
             if (!fits || c >= p.s_ocap) p.ctrl->stream_trunc = 1;
         }
     }
+    // keep the per-size LDS counters (32-bit) far from overflow within one task
+    if (w.count > (1ull << 30)) flush_graph(p, w);
 }
 
-__device__ inline bool check_deadline(const Params& p, Wg& w)
+__device__ inline bool check_deadline(const Params& p_arg, Wg& w)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     if (w.abort) return true;
     if (now_ticks() > w.deadline) {
         if (lane_id() == 0) atomicOr(&p.ctrl->err, 1u);
@@ -425,14 +469,9 @@ __device__ inline bool check_deadline(const Params& p, Wg& w)
 // ---------------------------------------------------------------- worker list
 __device__ inline Wg wg_view(const Params& p, uint32_t g)
 {
+    (void)p;
     Wg w;
-    uint8_t* base = p.scratch + (uint64_t)g * p.stride;
-    w.mbox = reinterpret_cast<MboxHdr*>(base);
-    w.mP = reinterpret_cast<uint32_t*>(base + p.off_P);
-    w.mXP = reinterpret_cast<uint32_t*>(base + p.off_XP);
-    w.R = reinterpret_cast<uint32_t*>(base + p.off_R);
-    w.fr = reinterpret_cast<uint64_t*>(base + p.off_fr);
-    w.xr = reinterpret_cast<uint32_t*>(base + p.off_xr);
+    w.me = g;
     return w;
 }
 
@@ -443,8 +482,10 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
 // at different words and bits, so claims rarely collide.  The bitmap carries
 // no task data: all accesses are relaxed; the task is published with
 // release/acquire on the receiver's flag.
-__device__ uint32_t wl_try_pop(const Params& p, Wg& w)
+__device__ uint32_t wl_try_pop(const Params& p_arg, Wg& w)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     const uint32_t nw = p.idle_words;
     w.don_t0 = uni64(now_ticks());
@@ -501,9 +542,11 @@ __device__ uint32_t wl_try_pop(const Params& p, Wg& w)
 // branches with |P| >= donate_min_p, with unexplored siblings at this level and
 // unexplored branches at an earlier level.  The waiting count read here was
 // loaded at the previous check, so its latency overlaps the search.
-__device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child, bool more_here, bool anc,
+__device__ inline bool donation_wanted(const Params& p_arg, Wg& w, uint32_t np_child, bool more_here, bool anc,
                                        uint32_t depth)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     // w.don_min: donate_min_p, or ~0 without the worker list; almost every
     // branch stops at this one compare
     if (__builtin_expect(np_child < w.don_min, 1)) return false;
@@ -518,14 +561,16 @@ __device__ inline bool donation_wanted(const Params& p, Wg& w, uint32_t np_child
 // Finish a donation to r: R (this workgroup's R[0, rs) plus vb), header, one
 // release fence, then the flag.  The caller wrote the branch itself: the P,
 // X_P and X_X lists (kMboxLists) or a fold frame (kMboxFold).
-__device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
+__device__ void publish_task(const Params& p_arg, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
                              uint64_t ks, uint32_t np, uint32_t nxp, uint32_t nxx, uint32_t kind)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     Wg d = wg_view(p, r);
-    for (uint32_t i = lane; i < rs; i += 64) d.R[i] = w.R[i];
+    for (uint32_t i = lane; i < rs; i += 64) d.R()[i] = w.R()[i];
     if (lane == 0) {
-        d.R[rs] = vb;
+        d.R()[rs] = vb;
         MboxHdr h;
         h.root = root;
         h.rsize = rs + 1;
@@ -534,7 +579,7 @@ __device__ void publish_task(const Params& p, Wg& w, uint32_t r, uint32_t root, 
         h.nxp = nxp;
         h.nxx = nxx;
         h.kind = kind;
-        *d.mbox = h;
+        *d.mbox() = h;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) __hip_atomic_store(&p.wflags[r], kFlagTask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -569,9 +614,9 @@ enum : uint32_t { kDone = 0, kYieldFold = 1, kYieldList = 2 };
 // one-word task universe the small universe is the task universe itself.
 __device__ __forceinline__ uint64_t fold_xrow(const Wg& w, bool vx, uint32_t xj, uint32_t oidx, uint32_t m)
 {
-    if (w.W == 1) return vx ? w.xrows[xj] : 0ull;
+    if (w.W == 1) return vx ? w.xrows()[xj] : 0ull;
     // o_k ascend with k: load each X-row word once
-    const uint64_t* xrow = w.xrows + (uint64_t)xj * w.W;
+    const uint64_t* xrow = w.xrows() + (uint64_t)xj * w.W;
     uint64_t xrowP = 0;
     uint32_t k = 0;
     while (k < m) {
@@ -594,7 +639,7 @@ __device__ __forceinline__ void put_fold_frame(const Wg& d, uint32_t m, uint64_t
                                                uint32_t xrank, uint64_t xrowP)
 {
     const uint32_t lane = lane_id();
-    uint64_t* f = d.fr;
+    uint64_t* f = d.fr();
     uint32_t* f32 = reinterpret_cast<uint32_t*>(f + kFrU32);
     if (lane == 0) {
         f[0] = P;
@@ -613,115 +658,214 @@ __device__ __forceinline__ void put_fold_frame(const Wg& d, uint32_t m, uint64_t
 enum : uint32_t { kExDone = 0, kExFold = 1, kExList = 2, kExMid = 3 };
 
 // ---------------------------------------------------------------- folded executor
+// Register stack writes: lane l of v takes the wave-uniform x (v_writelane).
+// The compiler offers no builtin for it; the declaration binds the LLVM
+// intrinsic, so hazards are still handled by the backend.
+extern "C" __device__ int mce_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ inline uint32_t wlane32(uint32_t v, uint32_t l, uint32_t x)
+{
+    return (uint32_t)mce_writelane_i32((int)x, (int)l, (int)v);
+}
+__device__ inline uint64_t wlane64(uint64_t v, uint32_t l, uint64_t x)
+{
+    const uint32_t lo = wlane32((uint32_t)v, l, (uint32_t)x);
+    const uint32_t hi = wlane32((uint32_t)(v >> 32), l, (uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Maximal cliques found by the folded executor are reported in groups of 64:
+// lane i of a pending pair holds the i-th clique's key sum plus |C| * gamma
+// (the argument of h) and its size; a full group is hashed on all 64 lanes at
+// once.  Per-lane hash sums are reduced into the workgroup's total when the
+// executor returns.
+struct LeafGroup {
+    uint64_t pre;   // per lane: sum of keys + |C| * gamma
+    uint32_t size;  // per lane: |C|
+    uint32_t n;     // pending cliques (wave-uniform), < 64
+    uint64_t hsum;  // per lane: sum of hashed cliques
+};
+
+__device__ __forceinline__ void leaf_group_flush(const Params& p_arg, Wg& w, LeafGroup& g)
+{
+    const Params& p = kparams();
+    (void)p_arg;
+    const uint32_t lane = lane_id();
+    const uint32_t n = g.n;
+    if (n == 0) return;
+    const bool on = lane < n;
+    const uint64_t h = on ? fmix64(g.pre) : 0ull;
+    g.hsum += h;
+    const uint32_t sz = on ? g.size : 0u;
+    if (on) {
+        if (sz < (uint32_t)kHistLds) atomicAdd(&S.hist[sz], 1u);
+        else atomicAdd(&p.ghist[(uint64_t)w.cur_gid * p.hist_len + min(sz, p.hist_len - 1)], 1ull);
+    }
+    w.hmax = max(w.hmax, wave_max(sz));
+    w.count += n;
+    if (p.flags & MCE_F_ROOT_STATS) {
+        uint32_t lo = (uint32_t)h, hi = (uint32_t)(h >> 32);
+        // 64-bit wave sum as two 32-bit sums of 32-bit halves (carries from the low half added back)
+        uint64_t slo = 0, shi = 0;
+        for (uint32_t t = 0; t < n; ++t) {
+            slo += rl32(lo, t);
+            shi += rl32(hi, t);
+        }
+        stat_add(S_CTASK, n);
+        stat_add(S_HTASK, slo + (shi << 32));
+    }
+    g.n = 0;
+    // keep the per-size LDS counters (32-bit) far from overflow within one task
+    if (w.count > (1ull << 30)) flush_graph(p, w);
+}
+
+__device__ __forceinline__ void leaf_group_close(const Params& p_arg, Wg& w, LeafGroup& g)
+{
+    const Params& p = kparams();
+    (void)p_arg;
+    leaf_group_flush(p, w, g);
+    uint64_t v = g.hsum;
+    for (int off = 32; off > 0; off >>= 1) v += shfl64(v, lane_id() ^ (uint32_t)off);
+    w.hash += uni64(v);
+    g.hsum = 0;
+}
+
 // Universe of m <= 64 vertices (lane k: rank su, key skey, rowP over the
 // universe, rowX over the folded X set); folded X set of up to 64 vertices
 // (lane j: rank xrank, xrowP = its adjacency over the universe).  X_X (L <= 64
 // entries, lane j holds entry xj) is folded from the X rows first.
-__device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root, const SmallJob& j)
+// The wave-uniform state of a level is P, X_P, X_X (bitmasks over the lanes),
+// the branches B still to visit and kg = (sum of keys of R) + |R| * gamma; the
+// stack keeps them in lane d of a VGPR for level d.
+__device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t root, const SmallJob& j)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
-    const uint32_t m = j.m, L = j.L;
-    const bool valid = lane < m;
+    // wave-uniform inputs are made visibly uniform, so they stay in scalar registers
+    const uint32_t m = uni(j.m), L = uni(j.L);
     const bool vx = lane < L;
     const uint32_t su = j.su;
     const uint64_t skey = j.skey, rowP = j.rowP;
-    const uint32_t xrank = vx ? w.xr[j.xj] : 0u;
+    const uint32_t xrank = vx ? w.xr()[j.xj] : 0u;
     const uint64_t xrowP = L ? fold_xrow(w, vx, j.xj, j.oidx, m) : 0ull;
     uint64_t rowX = 0;
     for (uint32_t t = 0; t < L; ++t) {
         uint64_t wt = rl64(xrowP, t);
         if ((wt >> lane) & 1ull) rowX |= 1ull << t;
     }
-    uint64_t P = j.P, XP = j.XP, XX = low_mask(L), ks = j.ks;
-    uint32_t rs = j.rs;
-    const uint32_t rs0 = j.rs;  // rs = rs0 + depth throughout
-    bool anc = j.anc;
+    const bool stream = (p.flags & MCE_F_STREAM) != 0;
+    const uint32_t don_min = uni(w.don_min);
+    const uint32_t rs0 = uni(j.rs);  // |R| at depth 0; |R| = rs0 + depth
+    const bool anc0 = uni(j.anc ? 1u : 0u) != 0;
+    uint64_t P = uni64(j.P), XP = uni64(j.XP), XX = low_mask(L), B = 0;
+    uint64_t kg = uni64(j.ks) + (uint64_t)rs0 * kGamma;
     uint32_t depth = 0;  // < m <= 64: the stack fits one lane per level
-    uint64_t B = 0;
     uint64_t sP = 0, sXP = 0, sXX = 0, sB = 0, sK = 0;
-    uint32_t sA = 0;
-    // R[rs0 + d] for d < depth lives in lane d of sV; it is written to w.R only
-    // when a donation or the clique stream needs it (no store per descent)
+    // R[rs0 + d] for d < depth lives in lane d of sV; it is written to w.R() only
+    // when a donation or the clique stream needs it
     uint32_t sV = 0;
-    // one natural loop: a node's pivot step runs at the top of the iteration after a descent
+    uint32_t nodes = 0, next_check = 4096;  // the watchdog is read every 4096 nodes
+    LeafGroup lg;
+    lg.pre = 0;
+    lg.size = 0;
+    lg.n = 0;
+    lg.hsum = 0;
     bool at_node = true;
     while (true) {
+        // ---- a node: Tomita pivot over P u X_P and the folded X_X
         if (at_node) {
             at_node = false;
-            ++w.nodes;
-            uint64_t cp = P | XP;
-            uint32_t key = 0;
-            if (valid && ((cp >> lane) & 1ull)) key = ((uint32_t)__popcll(P & rowP) << 8) | (255u - lane);
-            if ((XX >> lane) & 1ull) key = max(key, ((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane));
-            uint32_t best = wave_max(key);
-            uint32_t idx = 255u - (best & 255u);
-            uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
+            ++nodes;
+            const uint64_t cp = P | XP;
+            uint32_t key = ((cp >> lane) & 1ull) ? (((uint32_t)__popcll(P & rowP) << 8) | (255u - lane)) : 0u;
+            const uint32_t kx = ((XX >> lane) & 1ull) ? (((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane)) : 0u;
+            const uint32_t best = wave_max(max(key, kx));
+            const uint32_t idx = 255u - (best & 255u);
+            const uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
             B = P & ~rowpiv;
         }
-        if (B == 0) {
-            if (depth == 0) return;
-            --depth;
-            P = rl64(sP, depth);
-            XP = rl64(sXP, depth);
-            XX = rl64(sXX, depth);
-            B = rl64(sB, depth);
-            ks = rl64(sK, depth);
-            anc = rl32(sA, depth) != 0;
-            --rs;
-            continue;
-        }
-        if ((++w.poll & 4095u) == 0 && check_deadline(p, w)) return;
-        uint32_t bb = (uint32_t)__builtin_ctzll(B);
-        B &= B - 1;
-        uint64_t rp = rl64(rowP, bb);
-        uint64_t Pc = P & rp;
-        uint64_t XPc = XP & rp;
-        uint64_t XXc = XX & rl64(rowX, bb);
-        P &= ~(1ull << bb);
-        XP |= 1ull << bb;
-        uint32_t vb = rl32(su, bb);
-        uint64_t ksc = ks + rl64(skey, bb);
-        if (Pc == 0) {
-            ++w.nodes;
-            if ((XPc | XXc) == 0) {
-                if (p.flags & MCE_F_STREAM) {
-                    if (lane < depth) w.R[rs0 + lane] = sV;
-                    if (lane == 0) w.R[rs] = vb;
-                    wave_mem_sync();
+        // ---- its children, in ascending lane order; returns land here too
+        {
+            if (B == 0) {
+                if (depth == 0) {
+                    leaf_group_close(p, w, lg);
+                    w.nodes += nodes;
+                    return;
                 }
-                report(p, w, rs + 1, ksc);
-            }
-            continue;
-        }
-        uint32_t npc = (uint32_t)__popcll(Pc);
-        if (donation_wanted(p, w, npc, B != 0, anc || depth > 0, depth)) {
-            uint32_t r = wl_try_pop(p, w);
-            if (r != kNoWorkgroup) {
-                // the child keeps this universe and the members of X_X
-                Wg d = wg_view(p, r);
-                put_fold_frame(d, m, Pc, XPc, su, skey, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc), xrank,
-                               xrowP);
-                if (lane < depth) w.R[rs0 + lane] = sV;
-                wave_mem_sync();
-                publish_task(p, w, r, root, rs, vb, ksc, m, 0, (uint32_t)__popcll(XXc), kMboxFold);
+                --depth;
+                P = rl64(sP, depth);
+                XP = rl64(sXP, depth);
+                XX = rl64(sXX, depth);
+                B = rl64(sB, depth);
+                kg = rl64(sK, depth);
                 continue;
             }
+            const uint32_t bb = (uint32_t)__builtin_ctzll(B);
+            B &= B - 1;
+            const uint64_t bit = 1ull << bb;
+            const uint64_t rp = rl64(rowP, bb);
+            const uint64_t Pc = P & rp;
+            const uint64_t XPc = XP & rp;
+            const uint64_t XXc = XX & rl64(rowX, bb);
+            P &= ~bit;
+            XP |= bit;
+            const uint64_t kgc = kg + rl64(skey, bb) + kGamma;
+            if (Pc == 0) {
+                ++nodes;
+                if ((XPc | XXc) == 0) {
+                    if (stream) {
+                        if (lane < depth) w.R()[rs0 + lane] = sV;
+                        if (lane == 0) w.R()[rs0 + depth] = rl32(su, bb);
+                        wave_mem_sync();
+                        const uint32_t rsize = rs0 + depth + 1;
+                        report(p, w, rsize, kgc - (uint64_t)rsize * kGamma);
+                    } else {
+                        lg.pre = wlane64(lg.pre, lg.n, kgc);
+                        lg.size = wlane32(lg.size, lg.n, rs0 + depth + 1);
+                        if (++lg.n == 64) leaf_group_flush(p, w, lg);
+                    }
+                }
+                continue;
+            }
+            if (nodes >= next_check) {
+                next_check = nodes + 4096;
+                if (check_deadline(p, w)) {
+                    leaf_group_close(p, w, lg);
+                    w.nodes += nodes;
+                    return;
+                }
+            }
+            const uint32_t vb = rl32(su, bb);
+            const uint32_t npc = (uint32_t)__popcll(Pc);
+            if (npc >= don_min && donation_wanted(p, w, npc, B != 0, anc0 || depth > 0, depth)) {
+                uint32_t r = wl_try_pop(p, w);
+                if (r != kNoWorkgroup) {
+                    // the child keeps this universe and the members of X_X
+                    Wg d = wg_view(p, r);
+                    put_fold_frame(d, m, Pc, XPc, su, skey, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc),
+                                   xrank, xrowP);
+                    if (lane < depth) w.R()[rs0 + lane] = sV;
+                    wave_mem_sync();
+                    const uint32_t rs = rs0 + depth;
+                    publish_task(p, w, r, root, rs, vb, kgc - (uint64_t)(rs + 1) * kGamma, m, 0,
+                                 (uint32_t)__popcll(XXc), kMboxFold);
+                    continue;
+                }
+            }
+            // descend
+            sP = wlane64(sP, depth, P);
+            sXP = wlane64(sXP, depth, XP);
+            sXX = wlane64(sXX, depth, XX);
+            sB = wlane64(sB, depth, B);
+            sK = wlane64(sK, depth, kg);
+            sV = wlane32(sV, depth, vb);
+            ++depth;
+            P = Pc;
+            XP = XPc;
+            XX = XXc;
+            kg = kgc;
+            at_node = true;
         }
-        sP = wl64(sP, depth, P);
-        sXP = wl64(sXP, depth, XP);
-        sXX = wl64(sXX, depth, XX);
-        sB = wl64(sB, depth, B);
-        sK = wl64(sK, depth, ks);
-        sA = wl32(sA, depth, anc ? 1u : 0u);
-        sV = wl32(sV, depth, vb);
-        anc = anc || (B != 0);
-        ++depth;
-        ++rs;
-        P = Pc;
-        XP = XPc;
-        XX = XXc;
-        ks = ksc;
-        at_node = true;
     }
 }
 
@@ -730,9 +874,11 @@ __device__ __forceinline__ void run_folded(const Params& p, Wg& w, uint32_t root
 // stay untouched while a folded child runs); X_X stays the index list.
 // (c, C): at depth 0 descend only into branches t with t % C == c.  Returns
 // kYieldFold with j updated to a child for the folded executor, or kDone.
-__device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t root, bool resume, SmallJob& j,
+__device__ __forceinline__ uint32_t run_list(const Params& p_arg, Wg& w, uint32_t root, bool resume, SmallJob& j,
                                              uint32_t c, uint32_t C)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     const uint32_t m = j.m;
     const bool valid = lane < m;
@@ -744,7 +890,7 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
     bool anc;
     // register stack (lane d = level d < m <= 64); spilled to LDS while a
     // folded child runs.  R[rs0 + d] for d < depth lives in lane d of sV and is
-    // written to w.R only for a donation, the clique stream or a suspension.
+    // written to w.R() only for a donation, the clique stream or a suspension.
     uint64_t sP, sXP, sB, sK;
     uint32_t sL, sA, sR, sV, rs0;
     // one natural loop: a node's pivot step runs at the top of the iteration
@@ -764,7 +910,7 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
         sA = S.lA[lane];
         sR = S.lR[lane];
         rs0 = S.frame[4];
-        sV = lane < depth ? w.R[rs0 + lane] : 0u;
+        sV = lane < depth ? w.R()[rs0 + lane] : 0u;
     } else {
         sP = sXP = sB = sK = 0;
         sL = sA = sR = sV = 0;
@@ -821,8 +967,8 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
             ++w.nodes;
             if (XPc == 0 && !xx_any(p, w, L, bidx, vb)) {
                 if (p.flags & MCE_F_STREAM) {
-                    if (lane < depth) w.R[rs0 + lane] = sV;
-                    if (lane == 0) w.R[rs] = vb;
+                    if (lane < depth) w.R()[rs0 + lane] = sV;
+                    if (lane == 0) w.R()[rs] = vb;
                     wave_mem_sync();
                 }
                 report(p, w, rs + 1, ksc);
@@ -835,21 +981,21 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
             uint32_t r = wl_try_pop(p, w);
             if (r != kNoWorkgroup) {
                 Wg d = wg_view(p, r);
-                if (lane < depth) w.R[rs0 + lane] = sV;
+                if (lane < depth) w.R()[rs0 + lane] = sV;
                 if (Lc <= 64 && (can_fold || Lc == 0)) {
                     // fold frame over this universe; X_X members' rows gathered from the X rows
                     wave_mem_sync();
                     const bool xin = lane < Lc;
-                    const uint32_t xj = xin ? w.xx[lane] : 0u;
+                    const uint32_t xj = xin ? w.xx()[lane] : 0u;
                     const uint64_t xrowP = Lc ? fold_xrow(w, xin, xj, oidx, m) : 0ull;
-                    put_fold_frame(d, m, Pc, XPc, su, skey, rowP, xin, lane, xin ? w.xr[xj] : 0u, xrowP);
+                    put_fold_frame(d, m, Pc, XPc, su, skey, rowP, xin, lane, xin ? w.xr()[xj] : 0u, xrowP);
                     wave_mem_sync();
                     publish_task(p, w, r, root, rs, vb, ksc, m, 0, Lc, kMboxFold);
                     continue;
                 }
-                if (valid && ((Pc >> lane) & 1ull)) d.mP[prefix_popc(Pc)] = su;
-                if (valid && ((XPc >> lane) & 1ull)) d.mXP[prefix_popc(XPc)] = su;
-                for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                if (valid && ((Pc >> lane) & 1ull)) d.mP()[prefix_popc(Pc)] = su;
+                if (valid && ((XPc >> lane) & 1ull)) d.mXP()[prefix_popc(XPc)] = su;
+                for (uint32_t i = lane; i < Lc; i += 64) d.xr()[i] = w.xr()[w.xx()[i]];
                 wave_mem_sync();
                 publish_task(p, w, r, root, rs, vb, ksc, npc, (uint32_t)__popcll(XPc), Lc, kMboxLists);
                 continue;
@@ -868,7 +1014,7 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
         if (Lc <= 64 && (can_fold || Lc == 0)) {
             // suspend: the folded child runs next, then this level is popped
             wave_mem_sync();
-            j.xj = lane < Lc ? w.xx[lane] : 0u;
+            j.xj = lane < Lc ? w.xx()[lane] : 0u;
             j.P = Pc;
             j.XP = XPc;
             j.L = Lc;
@@ -883,7 +1029,7 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
             S.lA[lane] = sA;
             S.lR[lane] = sR;
             // the folded child reads R[0, rs + 1) from memory when it donates
-            if (lane < depth) w.R[rs0 + lane] = sV;
+            if (lane < depth) w.R()[rs0 + lane] = sV;
             if (lane == 0) {
                 S.frame[2] = depth;
                 S.frame[3] = t0;
@@ -904,7 +1050,7 @@ __device__ __forceinline__ uint32_t run_list(const Params& p, Wg& w, uint32_t ro
 
 // ---------------------------------------------------------------- mid executor
 // Members of a bitmap X_X (lane-per-word, w.Wx words) as indices into xr, in
-// ascending order.  to_list: written to w.xx[0, count); otherwise (count <= 64)
+// ascending order.  to_list: written to w.xx()[0, count); otherwise (count <= 64)
 // lane j returns the j-th member.
 __device__ __forceinline__ uint32_t xx_members(Wg& w, uint64_t XX, bool to_list)
 {
@@ -915,7 +1061,7 @@ __device__ __forceinline__ uint32_t xx_members(Wg& w, uint64_t XX, bool to_list)
         uint64_t word = rl64(XX, t);
         if ((word >> lane) & 1ull) {
             uint32_t pos = base + prefix_popc(word);
-            if (to_list) w.xx[pos] = t * 64 + lane;
+            if (to_list) w.xx()[pos] = t * 64 + lane;
             else S.sxj[pos] = t * 64 + lane;
         }
         base += (uint32_t)__popcll(word);
@@ -980,17 +1126,19 @@ __device__ __forceinline__ SmallView compact_child(const uint64_t* rows, uint32_
 // not built, the partitioned index list of Section III-E.  The DFS stack lives
 // in this workgroup's HBM scratch.  A child whose P u X_P fits 64 vertices is
 // re-indexed into j and handed over (kYieldFold / kYieldList).
-__device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t root, uint32_t nu, const uint64_t* rows,
+__device__ __forceinline__ uint32_t run_mid(const Params& p_arg, Wg& w, uint32_t root, uint32_t nu, const uint64_t* rows,
                                             uint32_t ws, bool resume, SmallJob& j, uint32_t L0, uint32_t c,
                                             uint32_t C)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     const uint32_t W = w.W;
     const bool xb = w.have_xrows;
     const uint32_t Wx = xb ? w.Wx : 0u;
     const uint32_t gws = p.wg;
     const uint32_t lvl_words = 3 * gws + p.wgx;
-    const uint32_t* U = w.uarr;
+    const uint32_t* U = w.uarr();
     uint32_t depth, t0, rs, L;
     uint64_t P, XP, XX, B, ks;
     bool anc;
@@ -1048,16 +1196,16 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
             if (depth == 0) return kDone;
             pop_first = false;
             --depth;
-            const uint64_t* lvl = w.gstack + (uint64_t)depth * lvl_words;
+            const uint64_t* lvl = w.gstack() + (uint64_t)depth * lvl_words;
             if (lane < W) {
                 P = lvl[lane];
                 XP = lvl[gws + lane];
                 B = lvl[2 * gws + lane];
             }
             if (lane < Wx) XX = lvl[3 * gws + lane];
-            uint64_t meta = w.gmeta[3 * depth];
-            ks = w.gmeta[3 * depth + 1];
-            rs = (uint32_t)w.gmeta[3 * depth + 2];
+            uint64_t meta = w.gmeta()[3 * depth];
+            ks = w.gmeta()[3 * depth + 1];
+            rs = (uint32_t)w.gmeta()[3 * depth + 2];
             L = (uint32_t)meta;
             anc = (meta >> 32) != 0;
             continue;
@@ -1068,7 +1216,7 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
         uint32_t bit = (uint32_t)__builtin_ctzll(word);
         uint32_t bb = w0 * 64 + bit;
         uint64_t rowb = lane < W ? rows[(uint64_t)bb * ws + lane] : 0ull;
-        uint64_t colb = lane < Wx ? w.xcols[(uint64_t)bb * Wx + lane] : 0ull;
+        uint64_t colb = lane < Wx ? w.xcols()[(uint64_t)bb * Wx + lane] : 0ull;
         uint64_t Pc = P & rowb;
         uint64_t XPc = XP & rowb;
         uint64_t XXc = XX & colb;
@@ -1081,7 +1229,7 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
             if ((t0++ % C) != c) continue;
         }
         uint32_t vb = U[bb];
-        uint64_t ksc = ks + w.ukey[bb];
+        uint64_t ksc = ks + w.ukey()[bb];
         uint32_t npc = wave_sum((uint32_t)__popcll(Pc));
         uint32_t nxc = wave_sum((uint32_t)__popcll(XPc));
         bool more_here = __ballot(B != 0) != 0;
@@ -1090,7 +1238,7 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
             bool xhit = xb ? __ballot(XXc != 0) != 0 : (nxc == 0 && xx_any(p, w, L, bb, vb));
             if (nxc == 0 && !xhit) {
                 if (p.flags & MCE_F_STREAM) {
-                    if (lane == 0) w.R[rs] = vb;
+                    if (lane == 0) w.R()[rs] = vb;
                     wave_mem_sync();
                 }
                 report(p, w, rs + 1, ksc);
@@ -1118,8 +1266,8 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
                         xj = xx_members(w, XXc, false);
                         xrowP = fold_xrow(w, xin, xj, cv.o, cv.msz);
                     }
-                    put_fold_frame(d, cv.msz, cv.P, cv.XP, valid ? U[cv.o] : 0u, valid ? w.ukey[cv.o] : 0ull, cv.row,
-                                   xin, lane, xin ? w.xr[xj] : 0u, xrowP);
+                    put_fold_frame(d, cv.msz, cv.P, cv.XP, valid ? U[cv.o] : 0u, valid ? w.ukey()[cv.o] : 0ull, cv.row,
+                                   xin, lane, xin ? w.xr()[xj] : 0u, xrowP);
                     wave_mem_sync();
                     publish_task(p, w, r, root, rs, vb, ksc, cv.msz, 0, Lc, kMboxFold);
                     continue;
@@ -1128,8 +1276,8 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
                 for (uint32_t t = 0; t < W; ++t) {
                     uint64_t pw_ = rl64(Pc, t), xw_ = rl64(XPc, t);
                     uint32_t u = t * 64 + lane;
-                    if ((pw_ >> lane) & 1ull) d.mP[bp + prefix_popc(pw_)] = U[u];
-                    if ((xw_ >> lane) & 1ull) d.mXP[bx + prefix_popc(xw_)] = U[u];
+                    if ((pw_ >> lane) & 1ull) d.mP()[bp + prefix_popc(pw_)] = U[u];
+                    if ((xw_ >> lane) & 1ull) d.mXP()[bx + prefix_popc(xw_)] = U[u];
                     bp += (uint32_t)__popcll(pw_);
                     bx += (uint32_t)__popcll(xw_);
                 }
@@ -1137,18 +1285,18 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
                     uint32_t bq = 0;
                     for (uint32_t t = 0; t < Wx; ++t) {
                         uint64_t xxw = rl64(XXc, t);
-                        if ((xxw >> lane) & 1ull) d.xr[bq + prefix_popc(xxw)] = w.xr[t * 64 + lane];
+                        if ((xxw >> lane) & 1ull) d.xr()[bq + prefix_popc(xxw)] = w.xr()[t * 64 + lane];
                         bq += (uint32_t)__popcll(xxw);
                     }
                 } else {
-                    for (uint32_t i = lane; i < Lc; i += 64) d.xr[i] = w.xr[w.xx[i]];
+                    for (uint32_t i = lane; i < Lc; i += 64) d.xr()[i] = w.xr()[w.xx()[i]];
                 }
                 publish_task(p, w, r, root, rs, vb, ksc, npc, nxc, Lc, kMboxLists);
                 continue;
             }
         }
         // push this level (also when the child is handed to a smaller executor)
-        uint64_t* lvl = w.gstack + (uint64_t)depth * lvl_words;
+        uint64_t* lvl = w.gstack() + (uint64_t)depth * lvl_words;
         if (lane < W) {
             lvl[lane] = P;
             lvl[gws + lane] = XP;
@@ -1156,10 +1304,10 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
         }
         if (lane < Wx) lvl[3 * gws + lane] = XX;
         // every lane stores the same meta words, so each later reads its own store
-        w.gmeta[3 * depth] = ((uint64_t)(anc ? 1u : 0u) << 32) | L;
-        w.gmeta[3 * depth + 1] = ks;
-        w.gmeta[3 * depth + 2] = rs;
-        if (lane == 0) w.R[rs] = vb;
+        w.gmeta()[3 * depth] = ((uint64_t)(anc ? 1u : 0u) << 32) | L;
+        w.gmeta()[3 * depth + 1] = ks;
+        w.gmeta()[3 * depth + 2] = rs;
+        if (lane == 0) w.R()[rs] = vb;
         const bool canc = anc || more_here || depth > 0;
         ++depth;
         if (npc + nxc <= 64) {
@@ -1168,7 +1316,7 @@ __device__ __forceinline__ uint32_t run_mid(const Params& p, Wg& w, uint32_t roo
             const bool valid = lane < cv.msz;
             j.m = cv.msz;
             j.su = valid ? U[cv.o] : 0u;
-            j.skey = valid ? w.ukey[cv.o] : 0ull;
+            j.skey = valid ? w.ukey()[cv.o] : 0ull;
             j.oidx = cv.o;
             j.rowP = cv.row;
             j.P = cv.P;
@@ -1219,11 +1367,13 @@ __device__ __forceinline__ void set_pair(uint64_t* rows, uint64_t* cols, int mod
         atomicOr((unsigned long long*)&cols[(uint64_t)a * cws + (r >> 6)], 1ull << (r & 63));
 }
 
-__device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uint32_t cnt, uint32_t nu, uint64_t* rows,
+__device__ __forceinline__ void scan_lists(const Params& p_arg, Wg& w, int mode, uint32_t cnt, uint32_t nu, uint64_t* rows,
                                            uint32_t ws, uint64_t* cols, uint32_t cws)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
-    const uint32_t* U = w.uarr;
+    const uint32_t* U = w.uarr();
     if (nu == 0) return;  // no entry can be found in an empty universe
     const uint32_t umin = U[0], umax = U[nu - 1];
     const uint32_t ustep = 1u << (31 - __builtin_clz(nu));  // largest power of two <= nu
@@ -1231,7 +1381,7 @@ __device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uin
         uint32_t i = g0 + lane;
         uint32_t beg = 0, len = 0;
         if (i < cnt) {
-            uint32_t v = mode == 0 ? U[i] : w.xr[i];
+            uint32_t v = mode == 0 ? U[i] : w.xr()[i];
             beg = p.op[v];
             len = p.op[v + 1] - beg;
         }
@@ -1272,8 +1422,10 @@ __device__ __forceinline__ void scan_lists(const Params& p, Wg& w, int mode, uin
 }
 
 // ---------------------------------------------------------------- tasks
-__device__ inline void begin_task(const Params& p, Wg& w, uint32_t root)
+__device__ inline void begin_task(const Params& p_arg, Wg& w, uint32_t root)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     uint32_t g = p.gid ? uni(p.gid[root]) : 0u;
     if (g != w.cur_gid) {
         flush_graph(p, w);
@@ -1289,9 +1441,11 @@ __device__ inline void begin_task(const Params& p, Wg& w, uint32_t root)
     w.nodes_t0 = w.nodes;
 }
 
-__device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint32_t rs, uint32_t c,
+__device__ __forceinline__ void finish_task(const Params& p_arg, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint32_t rs, uint32_t c,
                             uint32_t C)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     stat_add(S_TASKS, 1);
     // keep the per-size LDS counters (32-bit) far from overflow
     if (w.count > (1ull << 30)) flush_graph(p, w);
@@ -1322,21 +1476,23 @@ __device__ __forceinline__ void finish_task(const Params& p, Wg& w, uint32_t roo
     }
 }
 
-// Bitmaps of a task whose universe U (ascending ranks) is in w.uarr[0, nu),
+// Bitmaps of a task whose universe U (ascending ranks) is in w.uarr()[0, nu),
 // with P and X_P as bitmasks in S.pw / S.xw and the initial X_X ranks in
-// w.xr[0, L): universe rows (LDS, or HBM beyond the LDS cap) and, within the
+// w.xr()[0, L): universe rows (LDS, or HBM beyond the LDS cap) and, within the
 // X budgets, X rows and X columns.  Returns the first executor; a universe of
 // at most 64 vertices is set up in j.
-__device__ __forceinline__ uint32_t build_task(const Params& p, Wg& w, uint32_t nu, uint32_t L, uint64_t ks,
+__device__ __forceinline__ uint32_t build_task(const Params& p_arg, Wg& w, uint32_t nu, uint32_t L, uint64_t ks,
                                                uint32_t rs, uint32_t C, SmallJob& j, const uint64_t*& rows,
                                                uint32_t& ws)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     const uint32_t W = (nu + 63) >> 6;
     const uint64_t tb0 = now_ticks();
     w.W = W;
-    for (uint32_t i = lane; i < nu; i += 64) w.ukey[i] = p.vkey[w.uarr[i]];
-    for (uint32_t i = lane; i < L; i += 64) w.xx[i] = i;
+    for (uint32_t i = lane; i < nu; i += 64) w.ukey()[i] = p.vkey[w.uarr()[i]];
+    for (uint32_t i = lane; i < L; i += 64) w.xx()[i] = i;
     const uint32_t Wx = (L + 63) >> 6;
     w.have_xrows = L > 0 && nu >= p.xrow_min_u && (uint64_t)L * W <= p.xrow_budget &&
                    (uint64_t)nu * Wx <= p.xcol_budget && Wx <= p.wgx && L <= p.xrow_ratio * max(nu, 64u);
@@ -1345,22 +1501,22 @@ __device__ __forceinline__ uint32_t build_task(const Params& p, Wg& w, uint32_t 
         // X rows (per X entry, over U) for the register executors; X columns
         // (per universe vertex, over X) for the mid executor
         const bool cols = nu > 64;
-        for (uint64_t i = lane; i < (uint64_t)L * W; i += 64) w.xrows[i] = 0;
+        for (uint64_t i = lane; i < (uint64_t)L * W; i += 64) w.xrows()[i] = 0;
         if (cols)
-            for (uint64_t i = lane; i < (uint64_t)nu * Wx; i += 64) w.xcols[i] = 0;
+            for (uint64_t i = lane; i < (uint64_t)nu * Wx; i += 64) w.xcols()[i] = 0;
         wave_mem_sync();
-        scan_lists(p, w, 1, L, nu, w.xrows, W, cols ? w.xcols : nullptr, Wx);
+        scan_lists(p, w, 1, L, nu, w.xrows(), W, cols ? w.xcols() : nullptr, Wx);
         stat_add(S_XROW, 1);
     }
     uint64_t* brows;
     if (nu <= 64) {
-        brows = w.lrows;
+        brows = w.lrows();
         ws = 1;
     } else if (nu <= p.lds_cap) {
-        brows = w.lrows;
+        brows = w.lrows();
         ws = W | 1u;
     } else {
-        brows = w.grows;
+        brows = w.grows();
         ws = W | 1u;
         stat_add(S_HBM, 1);
     }
@@ -1375,8 +1531,8 @@ __device__ __forceinline__ uint32_t build_task(const Params& p, Wg& w, uint32_t 
     if (nu > 64) return kExMid;
     const bool valid = lane < nu;
     j.m = nu;
-    j.su = valid ? w.uarr[lane] : 0u;
-    j.skey = valid ? w.ukey[lane] : 0ull;
+    j.su = valid ? w.uarr()[lane] : 0u;
+    j.skey = valid ? w.ukey()[lane] : 0ull;
     j.oidx = lane;
     j.rowP = valid ? brows[lane] : 0ull;
     j.P = S.pw[0];
@@ -1388,17 +1544,19 @@ __device__ __forceinline__ uint32_t build_task(const Params& p, Wg& w, uint32_t 
 }
 
 // Run a task: a built one (build_task), or a fold frame received ready (fj,
-// with its X_X rows and ranks already in w.xrows / w.xr).
-__device__ __forceinline__ void run_task(const Params& p, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks,
+// with its X_X rows and ranks already in w.xrows() / w.xr()).
+__device__ __forceinline__ void run_task(const Params& p_arg, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks,
                                          uint32_t rs, uint32_t c, uint32_t C, bool frame, const SmallJob& fj)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     // dispatcher: one instance of each executor; a suspended executor resumes
     // when the one it handed a child to has finished
     SmallJob j;
     uint32_t ex;
     bool mid_susp = false, list_susp = false;
     uint32_t lc = c, lC = C;
-    const uint64_t* rows = w.lrows;
+    const uint64_t* rows = w.lrows();
     uint32_t ws = 1;
     if (frame) {
         w.W = 1;
@@ -1442,15 +1600,17 @@ struct TaskArgs {
 
 // First-level subtree of root v (Algorithm 3): P = later neighbours, X =
 // earlier neighbours; with a split (c, C) only level-1 branches t % C == c.
-__device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t v, uint32_t split)
+__device__ __forceinline__ TaskArgs setup_root(const Params& p_arg, Wg& w, uint32_t v, uint32_t split)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     uint32_t beg = p.op[v], nu = p.op[v + 1] - beg;
     uint32_t ib = p.ip[v], L = p.ip[v + 1] - ib;
-    for (uint32_t i = lane; i < nu; i += 64) w.uarr[i] = p.oc[beg + i];
-    for (uint32_t i = lane; i < L; i += 64) w.xr[i] = p.ic[ib + i];
+    for (uint32_t i = lane; i < nu; i += 64) w.uarr()[i] = p.oc[beg + i];
+    for (uint32_t i = lane; i < L; i += 64) w.xr()[i] = p.ic[ib + i];
     stat_add(S_ROOTW, nu + L);
-    if (lane == 0) w.R[0] = v;
+    if (lane == 0) w.R()[0] = v;
     const uint32_t W = (nu + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
         S.pw[q] = low_mask(nu - q * 64);
@@ -1476,8 +1636,10 @@ __device__ __forceinline__ TaskArgs setup_root(const Params& p, Wg& w, uint32_t 
 // X = the common neighbours ordered before u (earlier neighbours of v, and
 // later ones before u, that have u as a later neighbour).  Every X vertex is
 // an earlier neighbour of u, so |X| <= the in-degree bound of the scratch.
-__device__ __forceinline__ TaskArgs setup_l2(const Params& p, Wg& w, uint32_t v, uint32_t e)
+__device__ __forceinline__ TaskArgs setup_l2(const Params& p_arg, Wg& w, uint32_t v, uint32_t e)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     const uint32_t u = p.oc[e];
     const uint32_t beg = p.op[v], end = p.op[v + 1];
@@ -1488,10 +1650,10 @@ __device__ __forceinline__ TaskArgs setup_l2(const Params& p, Wg& w, uint32_t v,
         bool in = false;
         if (i < end) {
             x = p.oc[i];
-            in = has_later(p, u, x, w.probes);
+            in = has_later(p, u, x);
         }
         const uint64_t m = __ballot(in);
-        if (in) w.uarr[np + prefix_popc(m)] = x;
+        if (in) w.uarr()[np + prefix_popc(m)] = x;
         np += (uint32_t)__popcll(m);
     }
     const uint32_t ib = p.ip[v], ni = p.ip[v + 1] - ib;
@@ -1503,16 +1665,16 @@ __device__ __forceinline__ TaskArgs setup_l2(const Params& p, Wg& w, uint32_t v,
         bool in = false;
         if (i < total) {
             x = i < ni ? p.ic[ib + i] : p.oc[beg + (i - ni)];
-            in = has_later(p, x, u, w.probes);
+            in = has_later(p, x, u);
         }
         const uint64_t m = __ballot(in);
-        if (in) w.xr[nx + prefix_popc(m)] = x;
+        if (in) w.xr()[nx + prefix_popc(m)] = x;
         nx += (uint32_t)__popcll(m);
     }
     stat_add(S_ROOTW, (end - e - 1) + total);
     if (lane == 0) {
-        w.R[0] = v;
-        w.R[1] = u;
+        w.R()[0] = v;
+        w.R()[1] = u;
     }
     const uint32_t W = (np + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
@@ -1536,10 +1698,12 @@ __device__ __forceinline__ TaskArgs setup_l2(const Params& p, Wg& w, uint32_t v,
 // mailbox.  Returns false when the mailbox is not a task this kernel could have
 // written (a size beyond its capacity, a rank >= n): nothing is read through
 // such values.
-__device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs& t, SmallJob& fj)
+__device__ __forceinline__ bool setup_received(const Params& p_arg, Wg& w, TaskArgs& t, SmallJob& fj)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
-    MboxHdr h = *w.mbox;
+    MboxHdr h = *w.mbox();
     uint32_t np = uni(h.np), nxp = uni(h.nxp);
     t.root = uni(h.root);
     t.L = uni(h.nxx);
@@ -1553,7 +1717,7 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
         if (t.root >= p.nv || m == 0 || m > 64 || nxp != 0 || L > 64 || L > p.xcap || (L && L > p.xrow_budget) ||
             t.rs == 0 || t.rs + 2 > p.rcap)
             return false;
-        const uint64_t* f = w.fr;
+        const uint64_t* f = w.fr();
         const uint32_t* f32 = reinterpret_cast<const uint32_t*>(f + kFrU32);
         const bool valid = lane < m, vx = lane < L;
         fj.m = m;
@@ -1566,11 +1730,11 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
         const uint32_t xrank = vx ? f32[64 + lane] : 0u;
         const uint64_t xrow = vx ? f[kFrXRow + lane] : 0ull;
         bool bad = (valid && fj.su >= p.nv) || (vx && xrank >= p.nv);
-        for (uint32_t i = lane; i < t.rs; i += 64) bad |= w.R[i] >= p.nv;
+        for (uint32_t i = lane; i < t.rs; i += 64) bad |= w.R()[i] >= p.nv;
         if (__ballot(bad) != 0 || ((fj.P | fj.XP) & ~low_mask(m)) != 0) return false;
         if (vx) {
-            w.xr[lane] = xrank;
-            w.xrows[lane] = xrow;
+            w.xr()[lane] = xrank;
+            w.xrows()[lane] = xrow;
         }
         fj.oidx = lane;
         fj.xj = lane;
@@ -1587,10 +1751,10 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
         t.rs + 2 > p.rcap)
         return false;
     bool bad = false;
-    for (uint32_t i = lane; i < t.L; i += 64) bad |= w.xr[i] >= p.nv;
-    for (uint32_t i = lane; i < t.rs; i += 64) bad |= w.R[i] >= p.nv;
-    for (uint32_t i = lane; i < np; i += 64) bad |= w.mP[i] >= p.nv;
-    for (uint32_t i = lane; i < nxp; i += 64) bad |= w.mXP[i] >= p.nv;
+    for (uint32_t i = lane; i < t.L; i += 64) bad |= w.xr()[i] >= p.nv;
+    for (uint32_t i = lane; i < t.rs; i += 64) bad |= w.R()[i] >= p.nv;
+    for (uint32_t i = lane; i < np; i += 64) bad |= w.mP()[i] >= p.nv;
+    for (uint32_t i = lane; i < nxp; i += 64) bad |= w.mXP()[i] >= p.nv;
     if (__ballot(bad) != 0) return false;
     uint32_t W = (t.nu + 63) >> 6;
     for (uint32_t q = lane; q < W; q += 64) {
@@ -1600,27 +1764,27 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
     wave_mem_sync();
     // merge the two ascending lists into U; mark P / X_P membership
     for (uint32_t i = lane; i < np; i += 64) {
-        uint32_t x = w.mP[i];
+        uint32_t x = w.mP()[i];
         uint32_t lo = 0, hi = nxp;
         while (lo < hi) {
             uint32_t mid = (lo + hi) >> 1;
-            if (w.mXP[mid] < x) lo = mid + 1;
+            if (w.mXP()[mid] < x) lo = mid + 1;
             else hi = mid;
         }
         uint32_t pos = i + lo;
-        w.uarr[pos] = x;
+        w.uarr()[pos] = x;
         atomicOr((unsigned long long*)&S.pw[pos >> 6], 1ull << (pos & 63));
     }
     for (uint32_t i = lane; i < nxp; i += 64) {
-        uint32_t x = w.mXP[i];
+        uint32_t x = w.mXP()[i];
         uint32_t lo = 0, hi = np;
         while (lo < hi) {
             uint32_t mid = (lo + hi) >> 1;
-            if (w.mP[mid] < x) lo = mid + 1;
+            if (w.mP()[mid] < x) lo = mid + 1;
             else hi = mid;
         }
         uint32_t pos = i + lo;
-        w.uarr[pos] = x;
+        w.uarr()[pos] = x;
         atomicOr((unsigned long long*)&S.xw[pos >> 6], 1ull << (pos & 63));
     }
     wave_mem_sync();
@@ -1629,8 +1793,10 @@ __device__ __forceinline__ bool setup_received(const Params& p, Wg& w, TaskArgs&
 
 // Next unit of work: a (root, split) entry of the queue in phase 1, a donated
 // branch in phase 2.  Returns false when the kernel is done for this workgroup.
-__device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, TaskArgs& t, SmallJob& fj)
+__device__ __forceinline__ bool next_task(const Params& p_arg, Wg& w, bool& phase1, TaskArgs& t, SmallJob& fj)
 {
+    const Params& p = kparams();
+    (void)p_arg;
     const uint32_t lane = lane_id();
     const uint32_t me = w.me;
     if (phase1) {
@@ -1701,28 +1867,12 @@ __device__ __forceinline__ bool next_task(const Params& p, Wg& w, bool& phase1, 
     return false;
 }
 
-__global__ void __launch_bounds__(64) k_enumerate(Params p)
+__global__ void __launch_bounds__(64, 3) k_enumerate(Params p)
 {
-    extern __shared__ __align__(16) unsigned char lds[];
     const uint32_t lane = lane_id();
     const uint32_t me = blockIdx.x;
-    Wg w = wg_view(p, me);
-    uint8_t* base = p.scratch + (uint64_t)me * p.stride;
-    w.xx = reinterpret_cast<uint32_t*>(base + p.off_xx);
-    w.xflag = reinterpret_cast<uint64_t*>(base + p.off_flag);
-    w.hpos = reinterpret_cast<uint32_t*>(base + p.off_hpos);
-    w.spos = reinterpret_cast<uint32_t*>(base + p.off_spos);
-    w.grows = reinterpret_cast<uint64_t*>(base + p.off_rows);
-    w.xrows = reinterpret_cast<uint64_t*>(base + p.off_xrows);
-    w.xcols = reinterpret_cast<uint64_t*>(base + p.off_xcols);
-    w.gstack = reinterpret_cast<uint64_t*>(base + p.off_stack);
-    w.gmeta = reinterpret_cast<uint64_t*>(base + p.off_meta);
-    unsigned char* l = lds;
-    w.ukey = reinterpret_cast<uint64_t*>(l);
-    l += (size_t)p.ucap * 8;
-    w.uarr = reinterpret_cast<uint32_t*>(l);
-    l += (size_t)((p.ucap + 3) & ~3u) * 4;
-    w.lrows = reinterpret_cast<uint64_t*>(l);
+    Wg& w = SW;
+    w.me = me;
     for (uint32_t k = lane; k < (uint32_t)kHistLds; k += 64) S.hist[k] = 0;
     for (uint32_t k = lane; k < (uint32_t)S_COUNT + 4; k += 64) S.stat[k] = 0;
     wave_mem_sync();
@@ -1732,7 +1882,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
     w.task_t0 = 0;
     w.nodes = w.nodes_t0 = 0;
     w.don_t0 = 0;
-    w.probes = 0;
+    S.probes[lane] = 0;
     w.wl_tick = w.wl_seen = w.poll = w.pops = 0;
     w.don_min = (p.flags & MCE_F_WORKER_LIST) ? p.donate_min_p : 0xFFFFFFFFu;
     w.me = me;
@@ -1755,7 +1905,7 @@ __global__ void __launch_bounds__(64) k_enumerate(Params p)
         finish_task(p, w, t.root, t.nu, t.L, t.rs, t.c, t.C);
     }
     flush_graph(p, w);
-    uint32_t pl = wave_sum(w.probes);
+    uint32_t pl = wave_sum(S.probes[lane]);
     if (lane == 0) {
         atomicAdd(&p.acc[2 + MCE_STAT_PROBES], (unsigned long long)pl);
         atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)S.stat[S_ROOTW]);

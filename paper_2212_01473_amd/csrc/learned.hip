@@ -35,108 +35,111 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 
 // ---------------------------------------------------------------- features
 // Per root v (rank): log1p(degree), log1p(core), log1p(2-hop count = sum of
-// neighbour degrees), and the edge density of its later-neighbour set P
-// (edges inside P / C(|P|, 2); 0 when |P| < 2).  One wave per root; P is
-// staged in LDS (cap entries per wave, cap > the largest |P|); the later
-// lists of all P vertices are scanned as one concatenated sequence (lanes
-// take consecutive entries, so loads are independent) and each entry is
-// searched in P.
+// neighbour degrees), and the edge density of its later-neighbour set P.  The
+// density is exact (edges inside P / C(|P|, 2); 0 when |P| < 2) when P has at
+// most kDensityPairs pairs, else the fraction of adjacent pairs among
+// kDensityPairs pairs of positions drawn from SplitMix64 seeded with the
+// root's vertex key: x_t = output t, a = (x_t mod 2^32) mod |P|,
+// b = (x_t >> 32) mod (|P| - 1) moved past a; the pair (P[min], P[max]) is
+// adjacent iff P[max] is among the later neighbours of P[min].  One wave per
+// root; its lanes test pairs (binary searches in the later-neighbour lists).
 constexpr int kFeatWaves = 4;
-constexpr int kFeatCap = 4096;
+constexpr uint32_t kDensityPairs = 256;
+constexpr uint32_t kExactMaxP = 23;  // C(23, 2) = 253 <= kDensityPairs < C(24, 2)
+static_assert(kExactMaxP * (kExactMaxP - 1) / 2 <= kDensityPairs &&
+                  (kExactMaxP + 1) * kExactMaxP / 2 > kDensityPairs,
+              "exact density exactly when C(|P|, 2) <= kDensityPairs");
+
+__device__ inline uint64_t fmix64(uint64_t z)
+{
+    // SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014).
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Is x among the sorted later neighbours oc[beg, end)?
+__device__ inline bool sorted_contains(const uint32_t* __restrict__ oc, uint32_t beg, uint32_t end, uint32_t x)
+{
+    while (beg < end) {
+        const uint32_t mid = (beg + end) >> 1;
+        const uint32_t y = oc[mid];
+        if (y == x) return true;
+        if (y < x) beg = mid + 1;
+        else end = mid;
+    }
+    return false;
+}
 
 __global__ void __launch_bounds__(64 * kFeatWaves) k_features(const uint32_t* __restrict__ op,
                                                              const uint32_t* __restrict__ oc,
                                                              const uint32_t* __restrict__ ip,
                                                              const uint32_t* __restrict__ ic,
                                                              const uint32_t* __restrict__ core_r,
+                                                             const uint32_t* __restrict__ deg,
+                                                             const uint64_t* __restrict__ vkey,
                                                              const uint32_t* __restrict__ roots, uint32_t nr,
-                                                             uint32_t cap, float* __restrict__ feat)
+                                                             float* __restrict__ feat)
 {
-    extern __shared__ uint32_t fbuf[];
-    __shared__ uint32_t soff[kFeatWaves][64], sbeg[kFeatWaves][64];
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x >> 6;
-    uint32_t* P = fbuf + (size_t)wv * cap;
     for (size_t k = (size_t)blockIdx.x * kFeatWaves + wv; k < nr; k += (size_t)gridDim.x * kFeatWaves) {
-        uint32_t v = roots[k];
-        uint32_t pb = op[v], np = op[v + 1] - pb;
-        uint32_t xb = ip[v], nx = ip[v + 1] - xb;
+        const uint32_t v = roots[k];
+        const uint32_t pb = op[v], np = op[v + 1] - pb;
+        const uint32_t xb = ip[v], nx = ip[v + 1] - xb;
         // 2-hop count
         uint64_t two = 0;
         for (uint32_t i = lane; i < np + nx; i += 64) {
-            uint32_t u = i < np ? oc[pb + i] : ic[xb + i - np];
-            two += (uint64_t)(op[u + 1] - op[u]) + (ip[u + 1] - ip[u]);
+            const uint32_t u = i < np ? oc[pb + i] : ic[xb + i - np];
+            two += deg[u];
         }
-        // edges inside P: for each P vertex u (position a), its later
-        // neighbours found in P (they sit after a, since P is ascending)
-        uint64_t tri = 0;
-        if (np >= 2) {
-            for (uint32_t i = lane; i < np; i += 64) P[i] = oc[pb + i];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            const uint32_t pmax = P[np - 1];
-            const uint32_t pstep = 1u << (31 - __builtin_clz(np));  // largest power of two <= np
-            for (uint32_t a0 = 0; a0 < np; a0 += 64) {
-                uint32_t a = a0 + lane, beg = 0, len = 0;
-                if (a < np) {
-                    uint32_t u = P[a];
-                    beg = op[u];
-                    len = op[u + 1] - beg;
+        // adjacent pairs inside P: all of them, or the sampled ones; a pair
+        // (P[i], P[j]), i < j, is adjacent iff P[j] is a later neighbour of P[i]
+        uint32_t hits = 0;
+        if (np >= 2 && np <= kExactMaxP) {
+            const uint32_t pairs = np * (np - 1) / 2;
+            for (uint32_t t = lane; t < pairs; t += 64) {
+                uint32_t i = 0, rem = t;  // pair t in row-major order over i
+                while (rem >= np - 1 - i) {
+                    rem -= np - 1 - i;
+                    ++i;
                 }
-                // exclusive prefix of len over the wave
-                uint32_t off = len;
-                for (int d = 1; d < 64; d <<= 1) {
-                    uint32_t y = (uint32_t)__shfl_up((int)off, d, 64);
-                    if ((int)lane >= d) off += y;
-                }
-                uint32_t total = (uint32_t)__shfl((int)off, 63, 64);
-                off -= len;
-                soff[wv][lane] = off;
-                sbeg[wv][lane] = beg;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                const uint32_t nrows = min(64u, np - a0);
-                // two entries per lane and step (f and f + 64); both searches are
-                // binary liftings with the same trip count in every lane, so the
-                // two chains of LDS loads and the list loads overlap
-                for (uint32_t t = 0; t < total; t += 128) {
-                    const uint32_t fA = t + lane, fB = fA + 64;
-                    const bool okA = fA < total, okB = fB < total;
-                    uint32_t rA = 0, rB = 0;  // last row with soff <= f
-                    for (uint32_t step = 32; step; step >>= 1) {
-                        if (rA + step < nrows && soff[wv][rA + step] <= fA) rA += step;
-                        if (rB + step < nrows && soff[wv][rB + step] <= fB) rB += step;
-                    }
-                    const uint32_t xA = okA ? oc[sbeg[wv][rA] + (fA - soff[wv][rA])] : 0u;
-                    const uint32_t xB = okB ? oc[sbeg[wv][rB] + (fB - soff[wv][rB])] : 0u;
-                    const bool inA = okA && xA <= pmax, inB = okB && xB <= pmax;
-                    if (inA || inB) {
-                        uint32_t aA = 0, aB = 0;  // entries of P below x
-                        for (uint32_t step = pstep; step; step >>= 1) {
-                            if (aA + step <= np && P[aA + step - 1] < xA) aA += step;
-                            if (aB + step <= np && P[aB + step - 1] < xB) aB += step;
-                        }
-                        // a later neighbour of P[a] found in P lies after position a
-                        tri += inA && aA < np && P[aA] == xA;
-                        tri += inB && aB < np && P[aB] == xB;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
+                const uint32_t u = oc[pb + i], w = oc[pb + i + 1 + rem];
+                hits += sorted_contains(oc, op[u], op[u + 1], w);
+            }
+        } else if (np > kExactMaxP) {
+            const uint64_t seed = vkey[v];
+            for (uint32_t t = lane; t < kDensityPairs; t += 64) {
+                const uint64_t x = fmix64(seed + (uint64_t)(t + 1) * kGamma);
+                const uint32_t a = (uint32_t)x % np;
+                uint32_t b = (uint32_t)(x >> 32) % (np - 1);
+                if (b >= a) ++b;
+                const uint32_t lo = min(a, b), hi = max(a, b);
+                const uint32_t u = oc[pb + lo], w = oc[pb + hi];
+                hits += sorted_contains(oc, op[u], op[u + 1], w);
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
             two += __shfl_xor(two, off, 64);
-            tri += __shfl_xor(tri, off, 64);
+            hits += (uint32_t)__shfl_xor((int)hits, off, 64);
         }
         if (lane == 0) {
             float* f = feat + (size_t)k * 4;
             f[0] = log1pf((float)(np + nx));
             f[1] = log1pf((float)core_r[v]);
             f[2] = log1pf((float)two);
-            f[3] = np >= 2 ? (float)((double)tri / (0.5 * (double)np * (double)(np - 1))) : 0.f;
+            const double pairs = np <= kExactMaxP ? 0.5 * (double)np * (double)(np - 1) : (double)kDensityPairs;
+            f[3] = np >= 2 ? (float)((double)hits / pairs) : 0.f;
         }
-        __builtin_amdgcn_wave_barrier();
     }
+}
+
+// Degree of every vertex (later + earlier neighbours), by rank.
+__global__ void k_degrees(const uint32_t* __restrict__ op, const uint32_t* __restrict__ ip, uint32_t n,
+                          uint32_t* __restrict__ deg)
+{
+    for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x)
+        deg[v] = (op[v + 1] - op[v]) + (ip[v + 1] - ip[v]);
 }
 
 // Input ids to ranks; an id >= nv sets *err and maps to rank 0 (the call then
@@ -544,15 +547,17 @@ __global__ void k_gather(const T* __restrict__ src, const uint32_t* __restrict__
 mce_status root_features(const Oriented& g, const uint32_t* roots_rank, uint32_t nr, float* feat, hipStream_t s)
 {
     if (nr == 0) return MCE_OK;
-    if (g.max_out >= (uint32_t)kFeatCap) {
-        set_error("first-level P too large for the feature kernel");
-        return MCE_ERR_UNSUPPORTED;
-    }
-    const uint32_t cap = (g.max_out + 4) & ~3u;  // > max |P|
-    k_features<<<blocks_for(nr, kFeatWaves, 65536), 64 * kFeatWaves, (size_t)kFeatWaves * cap * 4, s>>>(
-        g.op.as<uint32_t>(), g.oc.as<uint32_t>(), g.ip.as<uint32_t>(), g.ic.as<uint32_t>(), g.core_r.as<uint32_t>(),
-        roots_rank, nr, cap, feat);
+    DevBuf deg;
+    mce_status st;
+    if ((st = deg.alloc((size_t)(g.n ? g.n : 1) * 4)) != MCE_OK) return st;
+    k_degrees<<<blocks_for(g.n, 256, 8192), 256, 0, s>>>(g.op.as<uint32_t>(), g.ip.as<uint32_t>(), g.n,
+                                                         deg.as<uint32_t>());
     MCE_HIP_TRY(hipGetLastError());
+    k_features<<<blocks_for(nr, kFeatWaves, 65536), 64 * kFeatWaves, 0, s>>>(
+        g.op.as<uint32_t>(), g.oc.as<uint32_t>(), g.ip.as<uint32_t>(), g.ic.as<uint32_t>(), g.core_r.as<uint32_t>(),
+        deg.as<uint32_t>(), g.vkey.as<uint64_t>(), roots_rank, nr, feat);
+    MCE_HIP_TRY(hipGetLastError());
+    MCE_HIP_TRY(hipStreamSynchronize(s));  // before the degree array is released
     return MCE_OK;
 }
 

@@ -109,6 +109,57 @@ def test_features_closed_forms():
     assert np.isclose(f[0, 3], 9 / 15)
 
 
+def test_splitmix64_matches_published_outputs():
+    # the published first outputs of SplitMix64 seeded with 0
+    from conftest import read_golden_lines
+
+    exp = [int(x, 16) for x in read_golden_lines("splitmix64_seed0.txt")]
+    assert [mlp.splitmix64(c) for c in range(len(exp))] == exp
+    # a seeded stream continues the seed-0 stream: seed = k * gamma skips k outputs
+    assert [mlp.splitmix64(c, seed=2 * 0x9E3779B97F4A7C15) for c in range(len(exp) - 2)] == exp[2:]
+
+
+def test_sampled_pairs_are_distinct_and_cover_positions():
+    k = 40
+    pairs = [mlp.sampled_pair(7, t, k) for t in range(mlp.DENSITY_PAIRS)]
+    assert all(0 <= a < b < k for a, b in pairs)
+    # 256 draws over 40 positions: every position appears (a miss would point
+    # at a biased mapping of the two halves of the output)
+    assert {x for p in pairs for x in p} == set(range(k))
+    # the mapping is uniform on ordered pairs: both orientations occur
+    raw = [mlp.splitmix64(t, seed=mlp.splitmix64(7)) for t in range(mlp.DENSITY_PAIRS)]
+    a = [(x & 0xFFFFFFFF) % k for x in raw]
+    b = [(x >> 32) % (k - 1) for x in raw]
+    assert any(bb >= aa for aa, bb in zip(a, b)) and any(bb < aa for aa, bb in zip(a, b))
+
+
+def test_sampled_density_closed_forms_and_estimate():
+    import oracle
+
+    # K_30: P of the first root has 29 vertices (406 pairs > 256): every
+    # sampled pair is adjacent, density exactly 1
+    g = I.complete_graph(30)
+    order, _ = oracle.sync_order(g)
+    f = mlp.features(g, [int(order[0])], order)
+    assert f[0, 3] == 1.0
+    # star with 40 leaves: the centre's P (if it is a root with P) has no edges
+    g = I.star_graph(40)
+    order, _ = oracle.sync_order(g)
+    f = mlp.features(g, list(range(g.n)), order)
+    assert (f[:, 3] == 0).all()
+    # Moon-Moser with 12 parts of 3: P of the first vertex is 33 vertices of
+    # the other 11 parts, an exact density 1 - 11 * 3 / C(33, 2) = 0.9375; the
+    # 256-pair estimate stays within 5 standard deviations of it
+    g = I.moon_moser(12)
+    order, _ = oracle.sync_order(g)
+    v = int(order[0])
+    f = mlp.features(g, [v], order)
+    p = 1 - 11 * 3 / (33 * 32 / 2)
+    sd = (p * (1 - p) / mlp.DENSITY_PAIRS) ** 0.5
+    assert abs(f[0, 3] - p) <= 5 * sd
+    assert f[0, 3] * mlp.DENSITY_PAIRS == round(f[0, 3] * mlp.DENSITY_PAIRS)  # a count of pairs
+
+
 def _hand_theta():
     """A network whose hidden units are partly inactive on x = (1, 2, 0, 0):
     layer 1  z = (x0, -x0, x1 - 5, x1 + 0.5)            -> h = (1, 0, 0, 2.5)
