@@ -43,7 +43,7 @@ namespace {
 
 constexpr uint32_t kFlagIdle = 0u, kFlagTask = 1u, kFlagTerm = 2u;
 constexpr uint32_t kNoWorkgroup = 0xFFFFFFFFu;
-constexpr int kHistLds = 256;
+constexpr int kHistLds = 128;
 constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
 // The counters that every workgroup updates with device-scope atomics each sit
@@ -100,7 +100,7 @@ struct Params {
     uint64_t stride;
     uint64_t off_fr;
     uint64_t off_P, off_XP, off_R, off_xr, off_xx, off_flag, off_hpos, off_spos, off_rows, off_xrows, off_xcols, off_stack,
-        off_meta;
+        off_meta, off_ukey, off_susp;
     uint64_t xrow_budget;      // words of X rows per workgroup
     uint64_t xcol_budget;      // words of X columns per workgroup
     uint32_t xrow_ratio;       // build X rows when |X| <= ratio * max(|U|, 64)
@@ -175,25 +175,29 @@ __device__ inline uint32_t row_ror(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + N, 0xF, 0xF, false);
 }
-// Wave-wide sum / max: DPP rotations inside each 16-lane row, then readlane
-// across the four rows (no LDS round trips).
+// Wave-wide sum / max without LDS round trips (see wave_max).
 __device__ inline uint32_t wave_sum(uint32_t v)
 {
     v += row_ror<1>(v);
     v += row_ror<2>(v);
     v += row_ror<4>(v);
     v += row_ror<8>(v);
-    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
-           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
+// Wave-wide maximum: DPP rotations give every lane its 16-lane row's maximum;
+// two row broadcasts (lane 15 into row 1, lane 47 into row 3, then lane 31 into
+// rows 2 and 3) leave the maximum of all four rows in lane 63.
 __device__ inline uint32_t wave_max(uint32_t v)
 {
     v = max(v, row_ror<1>(v));
     v = max(v, row_ror<2>(v));
     v = max(v, row_ror<4>(v));
     v = max(v, row_ror<8>(v));
-    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ inline uint32_t wave_excl_scan(uint32_t v)
 {
@@ -232,9 +236,7 @@ enum : int {
 // Fixed-size LDS of a workgroup (static offsets: no pointer registers).
 struct LdsFixed {
     uint64_t pw[64], xw[64];
-    uint64_t lP[64], lXP[64], lB[64], lK[64];  // list executor stack while suspended (lane = level)
     uint64_t stat[S_COUNT + 4];  // + snapshots at task start: (unused), donations, build time
-    uint32_t lL[64], lA[64], lR[64];
     uint32_t frame[6];  // suspended executors: mid depth, mid split counter, list depth, list split
                         // counter, list R offset
     uint32_t hist[kHistLds];
@@ -276,15 +278,14 @@ struct Wg {
     __device__ __forceinline__ uint64_t* xcols() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_xcols); }
     __device__ __forceinline__ uint64_t* gstack() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_stack); }
     __device__ __forceinline__ uint64_t* gmeta() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_meta); }
-    __device__ __forceinline__ uint64_t* ukey() const { return reinterpret_cast<uint64_t*>(lds_dyn); }
-    __device__ __forceinline__ uint32_t* uarr() const
-    {
-        return reinterpret_cast<uint32_t*>(lds_dyn + (size_t)kparams().ucap * 8);
-    }
+    __device__ __forceinline__ uint64_t* ukey() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_ukey); }
+    // list executor registers while a folded child runs: 4 x 64 words, then 3 x 64 u32
+    __device__ __forceinline__ uint64_t* susp64() const { return reinterpret_cast<uint64_t*>(base() + kparams().off_susp); }
+    __device__ __forceinline__ uint32_t* susp32() const { return reinterpret_cast<uint32_t*>(susp64() + 4 * 64); }
+    __device__ __forceinline__ uint32_t* uarr() const { return reinterpret_cast<uint32_t*>(lds_dyn); }
     __device__ __forceinline__ uint64_t* lrows() const
     {
-        const uint32_t ucap = kparams().ucap;
-        return reinterpret_cast<uint64_t*>(lds_dyn + (size_t)ucap * 8 + (size_t)((ucap + 3) & ~3u) * 4);
+        return reinterpret_cast<uint64_t*>(lds_dyn + (size_t)((kparams().ucap + 3) & ~3u) * 4);
     }
     // current task
     uint32_t W;         // words of the task's universe
@@ -902,13 +903,13 @@ __device__ __forceinline__ uint32_t run_list(const Params& p_arg, Wg& w, uint32_
         rs = L = 0;
         P = XP = ks = B = 0;
         anc = false;
-        sP = S.lP[lane];
-        sXP = S.lXP[lane];
-        sB = S.lB[lane];
-        sK = S.lK[lane];
-        sL = S.lL[lane];
-        sA = S.lA[lane];
-        sR = S.lR[lane];
+        sP = w.susp64()[lane];
+        sXP = w.susp64()[64 + lane];
+        sB = w.susp64()[128 + lane];
+        sK = w.susp64()[192 + lane];
+        sL = w.susp32()[lane];
+        sA = w.susp32()[64 + lane];
+        sR = w.susp32()[128 + lane];
         rs0 = S.frame[4];
         sV = lane < depth ? w.R()[rs0 + lane] : 0u;
     } else {
@@ -1021,13 +1022,13 @@ __device__ __forceinline__ uint32_t run_list(const Params& p_arg, Wg& w, uint32_
             j.ks = ksc;
             j.rs = rs + 1;
             j.anc = canc;
-            S.lP[lane] = sP;
-            S.lXP[lane] = sXP;
-            S.lB[lane] = sB;
-            S.lK[lane] = sK;
-            S.lL[lane] = sL;
-            S.lA[lane] = sA;
-            S.lR[lane] = sR;
+            w.susp64()[lane] = sP;
+            w.susp64()[64 + lane] = sXP;
+            w.susp64()[128 + lane] = sB;
+            w.susp64()[192 + lane] = sK;
+            w.susp32()[lane] = sL;
+            w.susp32()[64 + lane] = sA;
+            w.susp32()[128 + lane] = sR;
             // the folded child reads R[0, rs + 1) from memory when it donates
             if (lane < depth) w.R()[rs0 + lane] = sV;
             if (lane == 0) {
@@ -1867,7 +1868,7 @@ __device__ __forceinline__ bool next_task(const Params& p_arg, Wg& w, bool& phas
     return false;
 }
 
-__global__ void __launch_bounds__(64, 3) k_enumerate(Params p)
+__global__ void __launch_bounds__(64, 4) k_enumerate(Params p)
 {
     const uint32_t lane = lane_id();
     const uint32_t me = blockIdx.x;
@@ -2162,7 +2163,6 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     lds_cap = std::max(64u, std::min(lds_cap, std::max(ucap, 64u)));
     const uint32_t ws_l = lds_cap <= 64 ? 1u : (((lds_cap + 63) / 64) | 1u);
     size_t lds_bytes = 0;                                      // dynamic part (static LdsFixed comes first)
-    lds_bytes += (size_t)ucap * 8;                             // ukey
     lds_bytes += (size_t)((ucap + 3) & ~3u) * 4;               // uarr
     lds_bytes += (size_t)std::max(lds_cap * ws_l, 64u) * 8;    // rows
     if (lds_bytes + sizeof(LdsFixed) > 160 * 1024) {
@@ -2200,6 +2200,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint64_t off_xcols = off; off = align_up(off + xcol_words * 8 + 8, 256);
     const uint64_t off_stack = off; off = align_up(off + (uint64_t)(ucap + 2) * (3 * wg_words + wgx_words) * 8, 256);
     const uint64_t off_meta = off; off = align_up(off + (uint64_t)(ucap + 2) * 24, 256);
+    const uint64_t off_ukey = off; off = align_up(off + (uint64_t)ucap * 8, 256);
+    const uint64_t off_susp = off; off = align_up(off + 64 * 4 * 8 + 64 * 3 * 4, 256);
     const uint64_t stride = off;
     const uint64_t budget = 32ull << 30;
     if ((uint64_t)G * stride > budget) G = (uint32_t)std::max<uint64_t>(1, budget / stride);
@@ -2317,6 +2319,8 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     p.off_xcols = off_xcols;
     p.off_stack = off_stack;
     p.off_meta = off_meta;
+    p.off_ukey = off_ukey;
+    p.off_susp = off_susp;
     p.xrow_budget = xrow_words;
     p.xcol_budget = xcol_words;
     p.xrow_ratio = cfg.xrow_ratio;

@@ -78,6 +78,23 @@ def test_batch4096_every_graph_matches_oracle(gpu_lib, form):
     assert sum(r.count for r in res) == sum(e[0] for e in exp["graphs"])
 
 
+@pytest.mark.parametrize("form", ["plain", "learned"])
+def test_rmat22_window_matches_oracle(gpu_lib, form):
+    """The whole R-MAT 22 window c = 425 (2.5e9 maximal cliques) against the
+    oracle's count, hash and histogram, in the plain form and with the learned
+    order and split."""
+    exp = GOLD["rmat22_c425"]
+    g = I.workload("rmat22")
+    assert g.sha256() == exp["sha256"]
+    kw = dict(model=_untrained_model(), split=True) if form == "learned" else {}
+    with gpu_lib.load_graph(g) as dg:
+        r = gpu_lib.enumerate_cliques(dg, max_root_core=exp["window"], hist_len=dg.info().degeneracy + 2,
+                                      timeout_ms=300000, **kw)
+    assert r.count == exp["count"]
+    assert f"{r.hash:#018x}" == exp["hash"]
+    assert _hist_dict(r.hist) == exp["hist"]
+
+
 def test_rmat22_sampled_roots_match_oracle(gpu_lib):
     """Per-root counts and hashes of the window's roots (attributed in the
     synchronous-peel order) summed over the oracle's root sample, and the
