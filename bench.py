@@ -203,7 +203,7 @@ def result_key(res):
     return tuple((r.count, r.hash, tuple(r.hist.tolist())) for r in res)
 
 
-def graph_steps(name, c, knobs, forms):
+def graph_steps(name, c, knobs, forms, load_kw=None):
     """Step callables of a single-graph workload for the requested forms."""
     import torch
 
@@ -225,7 +225,7 @@ def graph_steps(name, c, knobs, forms):
 
     def graph_step(extra):
         def step():
-            dg = mce.load_csr(rp, ci, g.n)
+            dg = mce.load_csr(rp, ci, g.n, **(load_kw or {}))
             info = dg.info()
             r = mce.enumerate_cliques(dg, max_root_core=c, hist_len=info.degeneracy + 2, **knobs, **extra)
             dg.free()
@@ -346,6 +346,9 @@ def main():
     ap.add_argument("--donate-min-p", type=int, default=0)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-sample-mod", type=int, default=0, help="0: the workload's default sample")
+    ap.add_argument("--peel-steps", action="store_true",
+                    help="peel with graph-replayed step kernels instead of one cooperative launch "
+                         "(for profilers that do not follow cooperative launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch one elementwise kernel that reads and writes 1 GiB each, as the "
                          "reference for scaling hardware byte counters")
@@ -379,7 +382,8 @@ def main():
         log("[bench] calibration kernel: 1 GiB read + 1 GiB written")
 
     if spec["kind"] == "graph":
-        g, steps = graph_steps(args.workload, c, knobs, [form] + compare)
+        g, steps = graph_steps(args.workload, c, knobs, [form] + compare,
+                               load_kw=dict(peel_steps=True) if args.peel_steps else None)
         units = g.n
     else:
         g, steps, _ = batch_steps(knobs, [form] + compare)

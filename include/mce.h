@@ -133,7 +133,9 @@ mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t
 
 /* ---- enumeration flags */
 #define MCE_F_WORKER_LIST   0x01u  /* donate branches to idle wavefronts (Section III-C) */
-#define MCE_F_LEARNED_ORDER 0x02u  /* order roots by descending cost predicted by opt->model */
+#define MCE_F_LEARNED_ORDER 0x02u  /* order roots with at least 16 later neighbours by descending
+                                      cost predicted by opt->model, then the rest in degeneracy
+                                      order */
 #define MCE_F_SPLIT         0x04u  /* with LEARNED_ORDER: split the costliest roots into groups of
                                       level-1 branches (group c of C takes branches t, t % C == c) */
 #define MCE_F_STATS         0x08u  /* fill mce_result.stats */
@@ -155,16 +157,18 @@ typedef struct {
     uint32_t max_root_core;     /* core window c; UINT32_MAX = full enumeration */
     uint32_t wg_per_cu;         /* persistent workgroups per compute unit; 0 = occupancy limit */
     uint32_t bitmap_max_p;      /* largest subtree universe whose bitmap rows live in LDS;
-                                   larger ones use HBM rows; 0 = 128 (smaller LDS per
-                                   workgroup, more resident workgroups) */
+                                   larger ones use HBM rows; 0 = the largest up to 128 whose
+                                   LDS still lets the register-limited number of workgroups
+                                   per compute unit be resident */
     uint32_t donate_min_p;      /* donate a branch only if its |P| >= this; 0 = 24 (Section III-C
                                    uses 10; a donated branch here is rebuilt from the CSR by
                                    its receiver, so smaller ones cost more than they save) */
     uint32_t donate_max_depth;  /* donate only at depth <= this; 0 = unlimited */
-    uint32_t split_top;         /* MCE_F_SPLIT: the costliest roots by predicted rank, each split
-                                   into 64 groups if predicted at least 4x the mean cost;
-                                   0 = workgroups / 32.  Any root predicted above 1/(4 x
-                                   workgroups) of the total is split in proportion too. */
+    uint32_t split_top;         /* MCE_F_SPLIT: a root predicted above 1/workgroups of the total
+                                   predicted cost is split in proportion (at most 64 groups);
+                                   besides, the split_top costliest roots by predicted rank are
+                                   split into 64 groups if predicted at least 4x the mean cost
+                                   (0 = none) */
     const void* model;          /* MCE_F_LEARNED_ORDER: device pointer to mce_model weights */
     void* stream;               /* hipStream_t or NULL */
     uint64_t timeout_ms;        /* watchdog; 0 = 600000 */

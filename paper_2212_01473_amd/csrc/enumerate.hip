@@ -1868,7 +1868,7 @@ __device__ __forceinline__ bool next_task(const Params& p_arg, Wg& w, bool& phas
     return false;
 }
 
-__global__ void __launch_bounds__(64, 4) k_enumerate(Params p)
+__global__ void __launch_bounds__(64, 5) k_enumerate(Params p)
 {
     const uint32_t lane = lane_id();
     const uint32_t me = blockIdx.x;
@@ -2158,25 +2158,53 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint32_t wgx_words = std::min<uint32_t>(64u, (xcap + 63) / 64);  // X_X bitmaps: |X| <= 4096
     const uint32_t ws_g = wg_words | 1u;
 
-    // LDS budget for bitmap rows (universes up to 64 always fit)
-    uint32_t lds_cap = cfg.bitmap_max_p ? cfg.bitmap_max_p : kDefaultBitmapMaxP;
-    lds_cap = std::max(64u, std::min(lds_cap, std::max(ucap, 64u)));
-    const uint32_t ws_l = lds_cap <= 64 ? 1u : (((lds_cap + 63) / 64) | 1u);
-    size_t lds_bytes = 0;                                      // dynamic part (static LdsFixed comes first)
-    lds_bytes += (size_t)((ucap + 3) & ~3u) * 4;               // uarr
-    lds_bytes += (size_t)std::max(lds_cap * ws_l, 64u) * 8;    // rows
-    if (lds_bytes + sizeof(LdsFixed) > 160 * 1024) {
+    int dev = 0;
+    MCE_HIP_TRY(hipGetDevice(&dev));
+    int cus = 0, lds_cu = 0;
+    MCE_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds_cu <= 0)
+        lds_cu = 160 * 1024;
+    hipFuncAttributes fa;
+    MCE_HIP_TRY(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_enumerate)));
+    const size_t lds_static = std::max<size_t>(fa.sharedSizeBytes, sizeof(LdsFixed) + sizeof(Wg));
+    // workgroups per CU that the registers allow, and that a workgroup's LDS
+    // allows: gfx950 allocates a workgroup's static plus dynamic LDS in
+    // 1280-byte granules (160 KiB = 128 granules), which the occupancy query
+    // does not model
+    int per_cu_regs = 0;
+    MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_regs, reinterpret_cast<const void*>(k_enumerate),
+                                                             64, 0));
+    if (per_cu_regs <= 0) per_cu_regs = 1;
+    const size_t uarr_bytes = (size_t)((ucap + 3) & ~3u) * 4;
+    auto rows_words = [](uint32_t cap) {
+        const uint32_t ws = cap <= 64 ? 1u : (((cap + 63) / 64) | 1u);
+        return (size_t)std::max(cap * ws, 64u);
+    };
+    auto per_cu_lds = [&](size_t dyn) {
+        const size_t granule = 1280;
+        return (int)((size_t)lds_cu / ((lds_static + dyn + granule - 1) / granule * granule));
+    };
+    // LDS budget for bitmap rows (universes up to 64 always fit): the given
+    // cap, else the largest up to the default that keeps the register-limited
+    // number of workgroups resident
+    uint32_t lds_cap;
+    if (cfg.bitmap_max_p) {
+        lds_cap = std::max(64u, std::min(cfg.bitmap_max_p, std::max(ucap, 64u)));
+    } else {
+        lds_cap = std::max(64u, std::min(kDefaultBitmapMaxP, std::max(ucap, 64u)));
+        while (lds_cap > 64 && per_cu_lds(uarr_bytes + rows_words(lds_cap) * 8) < per_cu_regs)
+            lds_cap = std::max(64u, lds_cap - 8);
+    }
+    const size_t lds_bytes = uarr_bytes + rows_words(lds_cap) * 8;  // dynamic part (uarr, then rows)
+    if (lds_bytes + lds_static > (size_t)lds_cu) {
         set_error("LDS budget exceeded; lower bitmap_max_p");
         return MCE_ERR_INVALID_ARG;
     }
-
-    int dev = 0;
-    MCE_HIP_TRY(hipGetDevice(&dev));
-    int cus = 0;
-    MCE_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 0;
     MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_enumerate), 64,
                                                              lds_bytes));
+    per_cu = std::min(per_cu, per_cu_lds(lds_bytes));
     if (per_cu <= 0) per_cu = 1;
     if (cfg.wg_per_cu) per_cu = std::min<int>(per_cu, (int)cfg.wg_per_cu);
     uint32_t G = (uint32_t)(per_cu * cus);
@@ -2404,7 +2432,7 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     out.stats[MCE_STAT_IDLE_NS] = acc[2 + MCE_STAT_IDLE_NS] * 10;  // 100 MHz ticks -> ns
     out.stats[MCE_STAT_BUSY_NS] = acc[2 + MCE_STAT_BUSY_NS] * 10;
     out.stats[MCE_STAT_MAX_TASK_NS] = acc[2 + MCE_STAT_MAX_TASK_NS] * 10;
-    out.stats[MCE_STAT_LDS_BYTES] = lds_bytes + sizeof(LdsFixed);
+    out.stats[MCE_STAT_LDS_BYTES] = lds_bytes + lds_static;
     out.stats[MCE_STAT_BUILD_NS] = acc[2 + MCE_STAT_BUILD_TICKS] * 10;
     out.stats[MCE_STAT_TASK_LOG] = ctrl.tlog_n;
     out.stats[MCE_STAT_DONATE_NS] = acc[2 + MCE_STAT_DONATE_NS] * 10;

@@ -502,12 +502,36 @@ __global__ void k_pred_total(const double* __restrict__ part, int nparts, double
     }
 }
 
-// Number of groups each queued root (in descending predicted cost) is split
-// into.  The model ranks roots well but its scale is unreliable outside its
-// training range, so two rules combine: the first `top` roots get kMaxSplit
-// groups when predicted at least `floor_nodes`, and every root gets predicted
-// nodes / target groups, capped.
+// Number of groups each scored root (in descending predicted cost) is split
+// into: predicted nodes / target, capped, where target is the projected
+// makespan (total predicted nodes over the workgroups), so only a root that
+// alone would outlast the launch is split; the first `top` roots (a caller's
+// request) get kMaxSplit groups when predicted at least `floor_nodes`.
 constexpr uint32_t kMaxSplit = 64;
+
+// Roots with at least minp later neighbours are scored by the model.
+constexpr uint32_t kScoreMinP = 16;
+
+__global__ void k_score_flags(const uint32_t* __restrict__ roots, uint32_t n, const uint32_t* __restrict__ op,
+                              uint32_t minp, uint32_t* __restrict__ flag)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t r = roots[i];
+        flag[i] = (op[r + 1] - op[r]) >= minp ? 1u : 0u;
+    }
+}
+
+// Stable partition of the queue: flagged roots to heavy[pos], the others to
+// light[i - pos] (pos = exclusive prefix sum of the flags).
+__global__ void k_partition_roots(const uint32_t* __restrict__ roots, const uint32_t* __restrict__ flag,
+                                  const uint32_t* __restrict__ pos, uint32_t n, uint32_t* __restrict__ heavy,
+                                  uint32_t* __restrict__ light)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        if (flag[i]) heavy[pos[i]] = roots[i];
+        else light[i - pos[i]] = roots[i];
+    }
+}
 
 __global__ void k_split_counts(const float* __restrict__ score_sorted, uint32_t n, uint32_t top,
                                float floor_nodes, float target, uint32_t* __restrict__ groups)
@@ -813,73 +837,104 @@ mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st
     q.n = nroots;
     if (!nroots) return MCE_OK;
     size_t nn = nroots;
-    if ((rc = q.feat.alloc(nn * 16)) != MCE_OK) return rc;
-    if ((rc = q.score.alloc(nn * 4)) != MCE_OK) return rc;
-    if ((rc = q.keys.alloc(nn * 4)) != MCE_OK) return rc;
-    if ((rc = q.sorted.alloc(nn * 4)) != MCE_OK) return rc;
     uint32_t* roots = st.roots.as<uint32_t>();
-    if ((rc = root_features(g, roots, nroots, q.feat.as<float>(), s)) != MCE_OK) return rc;
-    if ((rc = model_predict(reinterpret_cast<const float*>(cfg.model), q.feat.as<float>(), nroots,
-                            q.score.as<float>(), s)) != MCE_OK)
-        return rc;
-    k_score_keys<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score.as<float>(), nroots, q.keys.as<uint32_t>());
-    MCE_HIP_TRY(hipGetLastError());
-    // sort queue positions 0..n-1 by key; then gather roots and scores
-    iota_u32(q.sorted.as<uint32_t>(), nn, s);
-    {
-        RadixTmp rt;
-        if ((rc = stable_sort_pairs_u32(q.keys.as<uint32_t>(), q.sorted.as<uint32_t>(), nn, 22, rt, s)) != MCE_OK)
-            return rc;
-        MCE_HIP_TRY(hipStreamSynchronize(s));
-    }
-    if ((rc = q.roots.alloc(nn * 4)) != MCE_OK) return rc;
-    if ((rc = q.score_sorted.alloc(nn * 4)) != MCE_OK) return rc;
-    k_gather<uint32_t><<<blocks_for(nn, 256, 8192), 256, 0, s>>>(roots, q.sorted.as<uint32_t>(), nroots,
-                                                                 q.roots.as<uint32_t>());
-    k_gather<float><<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score.as<float>(), q.sorted.as<uint32_t>(), nroots,
-                                                              q.score_sorted.as<float>());
-    MCE_HIP_TRY(hipGetLastError());
-    if (!(cfg.flags & MCE_F_SPLIT)) {
-        q.qroots = q.roots.as<uint32_t>();
-        q.qsplits = nullptr;
-        q.len = nroots;
-        MCE_HIP_TRY(hipStreamSynchronize(s));
-        return MCE_OK;
-    }
-    // split: the costliest roots by rank, and any root predicted above the
-    // target task size (total predicted nodes over 4 tasks per workgroup)
-    if ((rc = q.psum.alloc((kSumBlocks + 1) * 8)) != MCE_OK) return rc;
-    k_pred_partial<<<kSumBlocks, 256, 0, s>>>(q.score_sorted.as<float>(), nroots, q.psum.as<double>());
-    k_pred_total<<<1, 64, 0, s>>>(q.psum.as<double>(), kSumBlocks, q.psum.as<double>() + kSumBlocks);
-    MCE_HIP_TRY(hipGetLastError());
-    double total = 0;
-    MCE_HIP_TRY(hipMemcpyAsync(&total, q.psum.as<double>() + kSumBlocks, 8, hipMemcpyDeviceToHost, s));
-    MCE_HIP_TRY(hipStreamSynchronize(s));
-    float target = (float)std::max(64.0, total / (4.0 * std::max(grid, 1u)));
-    uint32_t top = cfg.split_top ? std::min(cfg.split_top, nroots) : std::max(1u, grid / 32);
-    float floor_nodes = (float)std::max(64.0, 4.0 * total / (double)nroots);
-    if ((rc = q.groups.alloc((nn + 1) * 4)) != MCE_OK) return rc;
+    // roots with at least kScoreMinP later neighbours are scored; the others
+    // (subtrees of at most 3^(kScoreMinP/3) leaves) follow in degeneracy order
+    if ((rc = q.flag.alloc(nn * 4)) != MCE_OK) return rc;
     if ((rc = q.pos.alloc((nn + 1) * 4)) != MCE_OK) return rc;
     if ((rc = q.scan_tmp.alloc(scan_tmp_words(nn + 1) * 8 + 64)) != MCE_OK) return rc;
     if ((rc = q.total.alloc(8)) != MCE_OK) return rc;
-    k_split_counts<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.score_sorted.as<float>(), nroots, top,
-                                                             floor_nodes, target, q.groups.as<uint32_t>());
+    if ((rc = q.heavy.alloc(nn * 4)) != MCE_OK) return rc;
+    if ((rc = q.light.alloc(nn * 4)) != MCE_OK) return rc;
+    k_score_flags<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(roots, nroots, g.op.as<uint32_t>(), kScoreMinP,
+                                                            q.flag.as<uint32_t>());
     MCE_HIP_TRY(hipGetLastError());
-    if ((rc = exclusive_scan_u32(q.groups.as<uint32_t>(), q.pos.as<uint32_t>(), nn, q.total.as<uint32_t>(),
+    if ((rc = exclusive_scan_u32(q.flag.as<uint32_t>(), q.pos.as<uint32_t>(), nn, q.total.as<uint32_t>(),
                                  q.scan_tmp.as<uint64_t>(), s)) != MCE_OK)
         return rc;
-    uint32_t len = 0;
-    MCE_HIP_TRY(hipMemcpyAsync(&len, q.total.p, 4, hipMemcpyDeviceToHost, s));
+    k_partition_roots<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(roots, q.flag.as<uint32_t>(), q.pos.as<uint32_t>(),
+                                                                nroots, q.heavy.as<uint32_t>(),
+                                                                q.light.as<uint32_t>());
+    MCE_HIP_TRY(hipGetLastError());
+    uint32_t nh = 0;
+    MCE_HIP_TRY(hipMemcpyAsync(&nh, q.total.p, 4, hipMemcpyDeviceToHost, s));
     MCE_HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t nl = nroots - nh;
+    q.scored = nh;
+    // order the scored roots by descending predicted cost (stable)
+    const size_t nhs = nh ? nh : 1;
+    if ((rc = q.feat.alloc(nhs * 16)) != MCE_OK) return rc;
+    if ((rc = q.score.alloc(nhs * 4)) != MCE_OK) return rc;
+    if ((rc = q.keys.alloc(nhs * 4)) != MCE_OK) return rc;
+    if ((rc = q.sorted.alloc(nhs * 4)) != MCE_OK) return rc;
+    if ((rc = q.roots.alloc(nhs * 4)) != MCE_OK) return rc;
+    if ((rc = q.score_sorted.alloc(nhs * 4)) != MCE_OK) return rc;
+    if (nh) {
+        const uint32_t* heavy = q.heavy.as<uint32_t>();
+        if ((rc = root_features(g, heavy, nh, q.feat.as<float>(), s)) != MCE_OK) return rc;
+        if ((rc = model_predict(reinterpret_cast<const float*>(cfg.model), q.feat.as<float>(), nh,
+                                q.score.as<float>(), s)) != MCE_OK)
+            return rc;
+        k_score_keys<<<blocks_for(nh, 256, 8192), 256, 0, s>>>(q.score.as<float>(), nh, q.keys.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        iota_u32(q.sorted.as<uint32_t>(), nh, s);
+        {
+            RadixTmp rt;
+            if ((rc = stable_sort_pairs_u32(q.keys.as<uint32_t>(), q.sorted.as<uint32_t>(), nh, 22, rt, s)) != MCE_OK)
+                return rc;
+            MCE_HIP_TRY(hipStreamSynchronize(s));
+        }
+        k_gather<uint32_t><<<blocks_for(nh, 256, 8192), 256, 0, s>>>(heavy, q.sorted.as<uint32_t>(), nh,
+                                                                     q.roots.as<uint32_t>());
+        k_gather<float><<<blocks_for(nh, 256, 8192), 256, 0, s>>>(q.score.as<float>(), q.sorted.as<uint32_t>(), nh,
+                                                                  q.score_sorted.as<float>());
+        MCE_HIP_TRY(hipGetLastError());
+    }
+    // groups per scored root: split only roots predicted above the projected
+    // makespan (total predicted nodes over the workgroups), in proportion, and
+    // the split_top costliest when asked
+    if ((rc = q.groups.alloc(nhs * 4 + 4)) != MCE_OK) return rc;
+    if ((rc = q.gpos.alloc(nhs * 4 + 4)) != MCE_OK) return rc;
+    uint32_t len_h = nh;
+    const bool split = (cfg.flags & MCE_F_SPLIT) != 0 && nh > 0;
+    if (split) {
+        if ((rc = q.psum.alloc((kSumBlocks + 1) * 8)) != MCE_OK) return rc;
+        k_pred_partial<<<kSumBlocks, 256, 0, s>>>(q.score_sorted.as<float>(), nh, q.psum.as<double>());
+        k_pred_total<<<1, 64, 0, s>>>(q.psum.as<double>(), kSumBlocks, q.psum.as<double>() + kSumBlocks);
+        MCE_HIP_TRY(hipGetLastError());
+        double total = 0;
+        MCE_HIP_TRY(hipMemcpyAsync(&total, q.psum.as<double>() + kSumBlocks, 8, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        const float target = (float)std::max(64.0, total / (double)std::max(grid, 1u));
+        const uint32_t top = std::min(cfg.split_top, nh);
+        const float floor_nodes = (float)std::max(64.0, 4.0 * total / (double)nh);
+        k_split_counts<<<blocks_for(nh, 256, 8192), 256, 0, s>>>(q.score_sorted.as<float>(), nh, top, floor_nodes,
+                                                                 target, q.groups.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        if ((rc = exclusive_scan_u32(q.groups.as<uint32_t>(), q.gpos.as<uint32_t>(), nh, q.total.as<uint32_t>(),
+                                     q.scan_tmp.as<uint64_t>(), s)) != MCE_OK)
+            return rc;
+        MCE_HIP_TRY(hipMemcpyAsync(&len_h, q.total.p, 4, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    // the queue: scored roots (expanded into their groups), then the others
+    const uint32_t len = len_h + nl;
     if ((rc = q.sroots.alloc((size_t)len * 4 + 4)) != MCE_OK) return rc;
     if ((rc = q.ssplits.alloc((size_t)len * 4 + 4)) != MCE_OK) return rc;
-    k_split_expand<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(q.roots.as<uint32_t>(), q.groups.as<uint32_t>(),
-                                                             q.pos.as<uint32_t>(), nroots, q.sroots.as<uint32_t>(),
-                                                             q.ssplits.as<uint32_t>());
-    MCE_HIP_TRY(hipGetLastError());
+    if (split) {
+        k_split_expand<<<blocks_for(nh, 256, 8192), 256, 0, s>>>(q.roots.as<uint32_t>(), q.groups.as<uint32_t>(),
+                                                                 q.gpos.as<uint32_t>(), nh, q.sroots.as<uint32_t>(),
+                                                                 q.ssplits.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+    } else if (nh) {
+        MCE_HIP_TRY(hipMemcpyAsync(q.sroots.p, q.roots.p, (size_t)nh * 4, hipMemcpyDeviceToDevice, s));
+    }
+    if (nl) MCE_HIP_TRY(hipMemcpyAsync(q.sroots.as<uint32_t>() + len_h, q.light.p, (size_t)nl * 4,
+                                       hipMemcpyDeviceToDevice, s));
+    if (split) fill_u32(q.ssplits.as<uint32_t>() + len_h, 0u, nl, s);  // one group each
     MCE_HIP_TRY(hipStreamSynchronize(s));
     q.qroots = q.sroots.as<uint32_t>();
-    q.qsplits = q.ssplits.as<uint32_t>();
+    q.qsplits = split ? q.ssplits.as<uint32_t>() : nullptr;
     q.len = len;
     return MCE_OK;
 }

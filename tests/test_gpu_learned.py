@@ -179,13 +179,22 @@ def test_split_every_root_keeps_results(gpu_lib):
         plain = gpu_lib.enumerate_cliques(dg, timeout_ms=60000)
         r = gpu_lib.enumerate_cliques(dg, model=rand, split=True, timeout_ms=60000)
     assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
-    # equal predictions: the target task is 1/(4 * workgroups) of the total, so
-    # every root becomes the same ceil(4 * workgroups / roots) groups (float
-    # rounding of the quotient may add one when it is an integer)
+    # equal predictions: the target task is 1/workgroups of the total, so every
+    # scored root (at least 16 later neighbours) becomes the same
+    # ceil(workgroups / scored) groups (float rounding of the quotient may add
+    # one when it is an integer) and every other root stays whole
+    _, rank = oracle.sync_order(g)
+    later = np.zeros(g.n, dtype=np.int64)
+    for v in range(g.n):
+        nb = g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]
+        later[v] = int(np.count_nonzero(rank[nb] > rank[v]))
+    scored = int(np.count_nonzero(later >= 16))
     n_roots = plain.stats["roots"]
-    assert r.stats["roots"] % n_roots == 0
-    groups = -(-4 * plain.stats["workgroups"] // n_roots)
-    assert r.stats["roots"] // n_roots in (min(groups, 64), min(groups + 1, 64))
+    assert 0 < scored < plain.stats["workgroups"]
+    extra = r.stats["roots"] - n_roots
+    assert extra % scored == 0
+    groups = -(-plain.stats["workgroups"] // scored)
+    assert extra // scored + 1 in (min(groups, 64), min(groups + 1, 64))
     assert r.stats["roots"] > n_roots
 
 
@@ -254,6 +263,11 @@ def test_trained_model_gains_over_degeneracy_order(gpu_lib):
         "out_degree": np.argsort(-outdeg[roots], kind="stable"),
         "model": np.argsort(-pred, kind="stable"),
     }
+    # the library's queue: roots with at least 16 later neighbours by the
+    # model, then the others in degeneracy order
+    scored = outdeg[roots] >= 16
+    idx = np.arange(nr)
+    orders["queue"] = np.concatenate([idx[scored][np.argsort(-pred[scored], kind="stable")], idx[~scored]])
     machines = 256
     lower = max(cost.sum() / machines, cost.max())
     recall = {k: len(heavy & set(o[:top].tolist())) / top for k, o in orders.items()}
@@ -261,3 +275,4 @@ def test_trained_model_gains_over_degeneracy_order(gpu_lib):
     print(f"roots {nr}, top 1% = {top}: recall {recall}; makespan / lower bound {makespan}")
     assert recall["model"] > recall["degeneracy"]
     assert makespan["model"] < makespan["degeneracy"]
+    assert makespan["queue"] < makespan["degeneracy"]

@@ -148,9 +148,9 @@ def test_stat_names_cover_header_indices():
 
 def test_enumeration_kernel_resources():
     """The build records each kernel's resources from the compiler; the DFS
-    kernel must keep 4 wavefronts per SIMD (a silent register-allocation
-    change costs a quarter of the resident workgroups) with at most a few
-    spilled words per lane (they sit outside the search loops)."""
+    kernel must keep 5 wavefronts per SIMD (a silent register-allocation
+    change costs a fifth of the resident workgroups), paid for with at most
+    40 spilled words per lane."""
     import json
 
     from paper_2212_01473_amd import build
@@ -160,7 +160,7 @@ def test_enumeration_kernel_resources():
     res = json.load(open(build.RESOURCES))
     k = [v for name, v in res.items() if "k_enumerate" in name]
     assert len(k) == 1
-    assert k[0]["occupancy"] >= 4 and k[0]["vgprs"] <= 128 and k[0]["scratchsize"] <= 64, k[0]
+    assert k[0]["occupancy"] >= 5 and k[0]["vgprs"] <= 96 and k[0]["scratchsize"] <= 160, k[0]
     for kernel in ("k_mlp_infer_bf16", "k_features", "k_pd_decrement", "scan"):
         for name, v in res.items():
             if kernel in name:
