@@ -82,6 +82,7 @@ __device__ bool row_contains(const uint32_t* __restrict__ rp, const uint32_t* __
 enum CheckMode : int { kCheckShape = 0, kCheckUp = 1, kCheckAll = 2 };
 
 constexpr uint32_t kLongRow = 2048;  // longer rows are deferred to a workgroup each
+constexpr uint32_t kLongBlocks = 2048;  // workgroups of the deferred-row pass (eight per CU)
 
 // Sum two 64-bit counters over the block, one atomic per counter.
 __device__ inline void block_add2(unsigned long long (&a)[2], unsigned long long* counts)
@@ -204,7 +205,13 @@ __global__ void k_peel_init(const uint32_t* __restrict__ rp, uint32_t n, uint32_
 struct PeelBufs {
     uint32_t* alive[2];
     uint32_t* front[2];
+    uint32_t* big[2];  // single-launch peel: the frontier's vertices of degree > kPeelBigDeg
 };
+
+// A frontier vertex with more arcs than this has its arcs removed by every
+// wave of the launch together rather than by one wave, so one hub does not
+// leave its round waiting on a single wave's chain of atomics.
+constexpr uint32_t kPeelBigDeg = 512;
 
 __global__ void k_pd_level_min(PeelBufs b, const uint32_t* __restrict__ deg, const uint32_t* __restrict__ round,
                                PeelState* ps)
@@ -344,10 +351,19 @@ __global__ void k_pd_advance(PeelState* ps, uint32_t n)
 // starts (that slot was last read at the start of round r - 1, before every
 // workgroup reached the barriers of round r - 1).
 struct alignas(256) PeelSlot {
-    uint32_t min_deg, n_front, n_alive, n_next;
+    uint32_t min_deg, n_front, n_alive, n_next, n_bfront, n_bnext;
+};
+// Grid barrier arrivals are counted in two levels (workgroups in groups of
+// kBarrierGroup, then groups), each counter on its own 256-byte line, so the
+// device-scope atomics of one barrier do not queue on a single address.
+constexpr uint32_t kBarrierGroup = 16;
+constexpr uint32_t kMaxBarrierGroups = 64;
+struct alignas(256) BarrierCounter {
+    uint32_t c;
 };
 struct PeelSync {
-    alignas(256) uint32_t count;  // arrivals at the current barrier
+    BarrierCounter grp[kMaxBarrierGroups];  // arrivals per group of workgroups
+    alignas(256) uint32_t count;  // groups arrived at the current barrier
     alignas(256) uint32_t gen;    // barrier generation
     alignas(256) uint32_t err;    // 1: a barrier wait timed out, 2: no remaining vertex, 4: round limit
     PeelSlot slot[3];
@@ -364,8 +380,22 @@ __device__ bool grid_barrier(PeelSync* ps, uint32_t nb, uint64_t deadline)
         uint32_t ok = 1;
         const uint32_t g = __hip_atomic_load(&ps->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t arrived = __hip_atomic_fetch_add(&ps->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nb - 1) {
+        const uint32_t gi = blockIdx.x / kBarrierGroup;
+        const uint32_t ngroups = (nb + kBarrierGroup - 1) / kBarrierGroup;
+        const uint32_t gsize = min(kBarrierGroup, nb - gi * kBarrierGroup);
+        bool last = false;
+        const uint32_t in_group =
+            __hip_atomic_fetch_add(&ps->grp[gi].c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (in_group == gsize - 1) {
+            // the group's last arrival resets its counter (no workgroup adds to
+            // it again before the generation moves on) and arrives for it
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(&ps->grp[gi].c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t arrived = __hip_atomic_fetch_add(&ps->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = arrived == ngroups - 1;
+        }
+        if (last) {
             __hip_atomic_store(&ps->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ps->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -404,7 +434,7 @@ __global__ void __launch_bounds__(256) k_peel_persistent(const uint32_t* __restr
     const size_t wid = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const size_t nwaves = (size_t)nb * (blockDim.x / 64);
     // bookkeeping, identical in every workgroup
-    uint32_t k = 0, r = 0, pa = 0, pf = 0, n_alive = n, n_cur = 0;
+    uint32_t k = 0, r = 0, pa = 0, pf = 0, n_alive = n, n_cur = 0, n_big = 0;
     uint64_t removed = 0;
     bool need_level = n > 0;
     const uint64_t max_rounds = 2 * (uint64_t)n + 4;  // every round removes at least one vertex
@@ -420,6 +450,8 @@ __global__ void __launch_bounds__(256) k_peel_persistent(const uint32_t* __restr
             __hip_atomic_store(&nx->n_front, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&nx->n_alive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&nx->n_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&nx->n_bfront, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&nx->n_bnext, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (need_level) {
             // the minimum remaining degree opens the level
@@ -441,69 +473,137 @@ __global__ void __launch_bounds__(256) k_peel_persistent(const uint32_t* __restr
             // the level's first frontier: every remaining vertex of degree <= k
             uint32_t* A2 = b.alive[pa ^ 1u];
             uint32_t* F = b.front[pf];
-            for (size_t base = (size_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n_alive;
-                 base += nthreads) {
-                const size_t i = base + lane;
-                uint32_t v = 0;
-                bool sel = false, keep = false;
+            uint32_t* Bg = b.big[pf];
+            // each wave takes chunks of cq x 64 entries (cq up to 16, fewer when
+            // the list is short, so every wave has some): it counts its
+            // selected, kept and big vertices first, reserves their places with
+            // one atomic per counter, then decides again and writes (nothing
+            // the decisions read changes in between)
+            const uint32_t cq = (uint32_t)min<size_t>(16, max<size_t>(1, n_alive / (nwaves * 64)));
+            auto decide = [&](size_t i, uint32_t& v, bool& sel, bool& keep, bool& big) {
+                v = 0;
+                sel = keep = big = false;
                 if (i < n_alive) {
                     v = A[i];
                     if (round[v] == kUnset) {
-                        if (deg[v] <= k) sel = true;
-                        else keep = true;
+                        if (deg[v] <= k) {
+                            sel = true;
+                            big = rp[v + 1] - rp[v] > kPeelBigDeg;
+                        } else {
+                            keep = true;
+                        }
                     }
                 }
-                const uint64_t ms = __ballot(sel), mk = __ballot(keep);
-                uint32_t bs = 0, bk = 0;
+            };
+            for (size_t base = wid * (64 * cq); base < n_alive; base += nwaves * (64 * cq)) {
+                uint32_t cs = 0, ck = 0, cb = 0;
+                for (uint32_t q = 0; q < cq; ++q) {
+                    uint32_t v;
+                    bool sel, keep, big;
+                    decide(base + q * 64 + lane, v, sel, keep, big);
+                    cs += (uint32_t)__popcll(__ballot(sel));
+                    ck += (uint32_t)__popcll(__ballot(keep));
+                    cb += (uint32_t)__popcll(__ballot(big));
+                }
+                uint32_t bs = 0, bk = 0, bb = 0;
                 if (lane == 0) {
-                    if (ms) bs = atomicAdd(&sl->n_front, (uint32_t)__popcll(ms));
-                    if (mk) bk = atomicAdd(&sl->n_alive, (uint32_t)__popcll(mk));
+                    if (cs) bs = atomicAdd(&sl->n_front, cs);
+                    if (ck) bk = atomicAdd(&sl->n_alive, ck);
+                    if (cb) bb = atomicAdd(&sl->n_bfront, cb);
                 }
                 bs = __shfl(bs, 0);
                 bk = __shfl(bk, 0);
-                if (sel) {
-                    round[v] = r;
-                    core[v] = k;
-                    F[bs + prefix_popc(ms)] = v;
+                bb = __shfl(bb, 0);
+                for (uint32_t q = 0; q < cq; ++q) {
+                    uint32_t v;
+                    bool sel, keep, big;
+                    decide(base + q * 64 + lane, v, sel, keep, big);
+                    const uint64_t ms = __ballot(sel), mk = __ballot(keep), mb = __ballot(big);
+                    if (sel) {
+                        round[v] = r;
+                        core[v] = k;
+                        F[bs + prefix_popc(ms)] = v;
+                    }
+                    if (big) Bg[bb + prefix_popc(mb)] = v;
+                    if (keep) A2[bk + prefix_popc(mk)] = v;
+                    bs += (uint32_t)__popcll(ms);
+                    bk += (uint32_t)__popcll(mk);
+                    bb += (uint32_t)__popcll(mb);
                 }
-                if (keep) A2[bk + prefix_popc(mk)] = v;
             }
             if (!grid_barrier(ps, nb, deadline)) return;
             n_cur = __hip_atomic_load(&sl->n_front, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            n_big = __hip_atomic_load(&sl->n_bfront, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             n_alive = __hip_atomic_load(&sl->n_alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             pa ^= 1u;
             need_level = false;
         }
         // remove the frontier: a neighbour whose degree falls from k + 1 to k
-        // joins the next round (one wave per frontier vertex)
+        // joins the next round.  One wave per frontier vertex of degree at
+        // most kPeelBigDeg; the larger ones (listed apart) share the launch's
+        // waves evenly, each splitting its arcs over its share.
         {
             const uint32_t* F = b.front[pf];
+            const uint32_t* Bg = b.big[pf];
             uint32_t* F2 = b.front[pf ^ 1u];
+            uint32_t* B2 = b.big[pf ^ 1u];
             const uint32_t r_next = r + 1;
+            // arcs first + q * stride + lane (q < 4) at a time: the four
+            // chains of loads and atomics overlap
+            auto remove_arcs = [&](uint32_t end, uint64_t first, uint64_t stride) {
+                for (uint64_t e0 = first; e0 < end; e0 += 4 * stride) {
+                    uint32_t u[4], rd[4], old[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint64_t e = e0 + q * stride + lane;
+                        u[q] = e < end ? ci[e] : kUnset;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        rd[q] = u[q] != kUnset
+                                    ? __hip_atomic_load(&round[u[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0u;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) old[q] = rd[q] == kUnset ? atomicSub(&deg[u[q]], 1u) : 0u;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool joined = rd[q] == kUnset && old[q] == k + 1;
+                        bool big = false;
+                        if (joined) {
+                            big = rp[u[q] + 1] - rp[u[q]] > kPeelBigDeg;
+                            __hip_atomic_store(&round[u[q]], r_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            core[u[q]] = k;
+                        }
+                        const uint64_t m = __ballot(joined), mb = __ballot(big);
+                        if (m) {
+                            uint32_t bo = 0, bb = 0;
+                            if (lane == 0) bo = atomicAdd(&sl->n_next, (uint32_t)__popcll(m));
+                            if (lane == 0 && mb) bb = atomicAdd(&sl->n_bnext, (uint32_t)__popcll(mb));
+                            bo = __shfl(bo, 0);
+                            bb = __shfl(bb, 0);
+                            if (joined) F2[bo + prefix_popc(m)] = u[q];
+                            if (big) B2[bb + prefix_popc(mb)] = u[q];
+                        }
+                    }
+                }
+            };
             for (size_t f = wid; f < n_cur; f += nwaves) {
                 const uint32_t v = F[f];
                 const uint32_t beg = rp[v], end = rp[v + 1];
-                for (uint32_t e0 = beg; e0 < end; e0 += 64) {
-                    const uint32_t e = e0 + lane;
-                    bool joined = false;
-                    uint32_t u = 0;
-                    if (e < end) {
-                        u = ci[e];
-                        if (__hip_atomic_load(&round[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == kUnset) {
-                            const uint32_t old = atomicSub(&deg[u], 1u);
-                            if (old == k + 1) {
-                                joined = true;
-                                __hip_atomic_store(&round[u], r_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                core[u] = k;
-                            }
-                        }
-                    }
-                    const uint64_t m = __ballot(joined);
-                    uint32_t bo = 0;
-                    if (lane == 0 && m) bo = atomicAdd(&sl->n_next, (uint32_t)__popcll(m));
-                    bo = __shfl(bo, 0);
-                    if (joined) F2[bo + prefix_popc(m)] = u;
+                if (end - beg > kPeelBigDeg) continue;
+                remove_arcs(end, beg, 64);
+            }
+            if (n_big >= nwaves) {
+                for (size_t i = wid; i < n_big; i += nwaves) {
+                    const uint32_t v = Bg[i];
+                    remove_arcs(rp[v + 1], rp[v], 64);
                 }
+            } else if (n_big > 0) {
+                // waves wid = i, i + n_big, i + 2 n_big, ... share big vertex i
+                const size_t i = wid % n_big, j = wid / n_big;
+                const size_t c = (nwaves - 1 - i) / n_big + 1;
+                const uint32_t v = Bg[i];
+                remove_arcs(rp[v + 1], (uint64_t)rp[v] + j * 64, (uint64_t)c * 64);
             }
         }
         if (!grid_barrier(ps, nb, deadline)) return;
@@ -511,6 +611,7 @@ __global__ void __launch_bounds__(256) k_peel_persistent(const uint32_t* __restr
         r += 1;
         pf ^= 1u;
         n_cur = __hip_atomic_load(&sl->n_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        n_big = __hip_atomic_load(&sl->n_bnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (n_cur == 0 && removed < n) need_level = true;
     }
     if (leader) {
@@ -692,8 +793,9 @@ __global__ void k_orient_fill(const uint32_t* __restrict__ rp, const uint32_t* _
     const uint32_t lane = lane_id();
     const size_t waves = (size_t)gridDim.x * (blockDim.x / 64);
     for (size_t v = (size_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += waves) {
-        uint32_t rv = rank[v];
         uint32_t beg = rp[v], end = rp[v + 1];
+        if (end - beg > kLongRow) continue;  // k_orient_fill_long
+        uint32_t rv = rank[v];
         uint32_t po = op[rv], pi = ip[rv];
         for (uint32_t e0 = beg; e0 < end; e0 += 64) {
             uint32_t e = e0 + lane;
@@ -706,6 +808,51 @@ __global__ void k_orient_fill(const uint32_t* __restrict__ rp, const uint32_t* _
             if (earlier) ic[pi + prefix_popc(me)] = ru;
             po += (uint32_t)__popcll(ml);
             pi += (uint32_t)__popcll(me);
+        }
+    }
+}
+
+// The rows longer than kLongRow (listed by k_orient_count), one workgroup per
+// row, 256 arcs at a time; entries keep the input order, as in k_orient_fill.
+__global__ void __launch_bounds__(256) k_orient_fill_long(const uint32_t* __restrict__ rp,
+                                                          const uint32_t* __restrict__ ci,
+                                                          const uint32_t* __restrict__ rank,
+                                                          const uint32_t* __restrict__ op,
+                                                          const uint32_t* __restrict__ ip,
+                                                          uint32_t* __restrict__ oc, uint32_t* __restrict__ ic,
+                                                          const uint32_t* __restrict__ defer,
+                                                          const uint32_t* __restrict__ ndefer)
+{
+    __shared__ uint32_t cnt[2][4];
+    const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+    const uint32_t total = *ndefer;
+    for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+        const uint32_t v = defer[i];
+        const uint32_t beg = rp[v], end = rp[v + 1], rv = rank[v];
+        uint32_t po = op[rv], pi = ip[rv];
+        for (uint64_t e0 = beg; e0 < end; e0 += 256) {
+            const uint64_t e = e0 + threadIdx.x;
+            const bool valid = e < end;
+            const uint32_t ru = valid ? rank[ci[e]] : 0u;
+            const bool later = valid && ru > rv, earlier = valid && ru < rv;
+            const uint64_t ml = __ballot(later), me = __ballot(earlier);
+            if (lane == 0) {
+                cnt[0][wv] = (uint32_t)__popcll(ml);
+                cnt[1][wv] = (uint32_t)__popcll(me);
+            }
+            __syncthreads();
+            uint32_t bl = po, be = pi;
+            for (uint32_t w = 0; w < wv; ++w) {
+                bl += cnt[0][w];
+                be += cnt[1][w];
+            }
+            if (later) oc[bl + prefix_popc(ml)] = ru;
+            if (earlier) ic[be + prefix_popc(me)] = ru;
+            for (uint32_t w = 0; w < 4; ++w) {
+                po += cnt[0][w];
+                pi += cnt[1][w];
+            }
+            __syncthreads();
         }
     }
 }
@@ -774,7 +921,7 @@ mce_status peel_single_launch(const uint32_t* rp, const uint32_t* ci, uint32_t n
                                                              256, 0));
     per_cu = std::min(per_cu, 2);
     if (per_cu < 1) return MCE_OK;
-    const uint32_t nb = (uint32_t)(per_cu * cus);
+    const uint32_t nb = std::min((uint32_t)(per_cu * cus), kBarrierGroup * kMaxBarrierGroups);
     DevBuf sync;
     mce_status st;
     if ((st = sync.alloc(sizeof(PeelSync))) != MCE_OK) return st;
@@ -847,10 +994,11 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
         DevBuf defer;
         if ((st = defer.alloc(((size_t)nnz / kLongRow + 1) * 4)) != MCE_OK) return st;
         uint32_t* ndefer = reinterpret_cast<uint32_t*>(dmisc + 3);
-        k_validate_cols<<<blocks_for(n, 4, 1024), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, kCheckShape,
-                                                                 defer.as<uint32_t>(), ndefer);
+        k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, kCheckShape,
+                                                                  defer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
-        k_validate_long<<<256, 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, kCheckShape, defer.as<uint32_t>(), ndefer);
+        k_validate_long<<<kLongBlocks, 256, 0, s>>>(rp, ci, n, dmisc, dmisc + 1, kCheckShape, defer.as<uint32_t>(),
+                                                    ndefer);
         MCE_HIP_TRY(hipGetLastError());
         MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 24, hipMemcpyDeviceToHost, s));
         MCE_HIP_TRY(hipStreamSynchronize(s));
@@ -860,8 +1008,8 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
             k_validate_cols<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, dmisc, nullptr, kCheckUp,
                                                                      nullptr, nullptr);
             MCE_HIP_TRY(hipGetLastError());
-            k_validate_long<<<256, 256, 0, s>>>(rp, ci, n, dmisc, nullptr, kCheckUp, defer.as<uint32_t>(),
-                                                ndefer);
+            k_validate_long<<<kLongBlocks, 256, 0, s>>>(rp, ci, n, dmisc, nullptr, kCheckUp, defer.as<uint32_t>(),
+                                                        ndefer);
             MCE_HIP_TRY(hipGetLastError());
             MCE_HIP_TRY(hipMemcpyAsync(hmisc, dmisc, 8, hipMemcpyDeviceToHost, s));
             MCE_HIP_TRY(hipStreamSynchronize(s));
@@ -893,13 +1041,17 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     }
 
     // ---- peel
-    DevBuf deg, alive_a, alive_b, front_a, front_b, psb;
+    DevBuf deg, alive_a, alive_b, front_a, front_b, big_a, big_b, psb;
     size_t nn = n ? n : 1;
     if ((st = deg.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = alive_a.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = alive_b.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = front_a.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = front_b.alloc(nn * 4)) != MCE_OK) return st;
+    // at most nnz / (kPeelBigDeg + 1) vertices have more arcs than kPeelBigDeg
+    const size_t nbig = std::min<size_t>(nn, nnz / (kPeelBigDeg + 1) + 1);
+    if ((st = big_a.alloc(nbig * 4)) != MCE_OK) return st;
+    if ((st = big_b.alloc(nbig * 4)) != MCE_OK) return st;
     if ((st = g.core.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = g.round.alloc(nn * 4)) != MCE_OK) return st;
     if ((st = psb.alloc(sizeof(PeelState))) != MCE_OK) return st;
@@ -933,6 +1085,8 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     pb.alive[1] = alive_b.as<uint32_t>();
     pb.front[0] = front_a.as<uint32_t>();
     pb.front[1] = front_b.as<uint32_t>();
+    pb.big[0] = big_a.as<uint32_t>();
+    pb.big[1] = big_b.as<uint32_t>();
     bool peeled = n == 0;
     g.peel_mode = 0;
     if (n && !g.peel_steps) {
@@ -1034,6 +1188,8 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     alive_a.release();
     alive_b.release();
     front_b.release();
+    big_a.release();
+    big_b.release();
 
     // ---- order by (round, id): stable radix sort of ids keyed by round
     DevBuf order, keys;
@@ -1082,12 +1238,12 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     if ((st = odefer.alloc(((size_t)g.nnz / kLongRow + 1) * 4)) != MCE_OK) return st;
     if (n) {
         uint32_t* ndefer = reinterpret_cast<uint32_t*>(dmisc) + 12;
-        k_orient_count<<<blocks_for(n, 4, 1024), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(),
+        k_orient_count<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(),
                                                                 outdeg.as<uint32_t>(), indeg.as<uint32_t>(),
                                                                 reinterpret_cast<unsigned int*>(dmisc),
                                                                 odefer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
-        k_orient_count_long<<<256, 256, 0, s>>>(rp, ci, rank.as<uint32_t>(), outdeg.as<uint32_t>(),
+        k_orient_count_long<<<kLongBlocks, 256, 0, s>>>(rp, ci, rank.as<uint32_t>(), outdeg.as<uint32_t>(),
                                                   indeg.as<uint32_t>(), reinterpret_cast<unsigned int*>(dmisc),
                                                   odefer.as<uint32_t>(), ndefer);
         MCE_HIP_TRY(hipGetLastError());
@@ -1125,6 +1281,11 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
         k_orient_fill<<<blocks_for(n, 4, 16384), 256, 0, s>>>(rp, ci, n, rank.as<uint32_t>(), g.op.as<uint32_t>(),
                                                                g.ip.as<uint32_t>(), g.oc.as<uint32_t>(),
                                                                g.ic.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        k_orient_fill_long<<<kLongBlocks, 256, 0, s>>>(rp, ci, rank.as<uint32_t>(), g.op.as<uint32_t>(),
+                                                       g.ip.as<uint32_t>(), g.oc.as<uint32_t>(), g.ic.as<uint32_t>(),
+                                                       odefer.as<uint32_t>(),
+                                                       reinterpret_cast<uint32_t*>(dmisc) + 12);
         MCE_HIP_TRY(hipGetLastError());
         k_sort_rows<<<blocks_for(n, 1, 65536), 64, 0, s>>>(g.op.as<uint32_t>(), n, g.oc.as<uint32_t>());
         MCE_HIP_TRY(hipGetLastError());
