@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <vector>
 
 namespace mce {
 
@@ -509,8 +510,31 @@ __global__ void k_pred_total(const double* __restrict__ part, int nparts, double
 // request) get kMaxSplit groups when predicted at least `floor_nodes`.
 constexpr uint32_t kMaxSplit = 64;
 
-// Roots with at least minp later neighbours are scored by the model.
+// Roots with at least kScoreMinP later neighbours are scored by the model, at
+// most about kScoreBudget per workgroup of the launch (the roots with the most
+// later neighbours; the features cost grows with the number scored).
 constexpr uint32_t kScoreMinP = 16;
+constexpr uint32_t kScoreBudget = 32;
+constexpr uint32_t kPHistCap = 4097;  // |P| <= 4096 for any root the enumeration accepts
+
+// Histogram of |P| (later neighbours) over the queued roots with |P| >= minp,
+// |P| capped at kPHistCap - 1: per workgroup in LDS, then merged.
+__global__ void __launch_bounds__(256) k_p_hist(const uint32_t* __restrict__ roots, uint32_t n,
+                                                const uint32_t* __restrict__ op, uint32_t minp,
+                                                uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[kPHistCap];
+    for (uint32_t b = threadIdx.x; b < kPHistCap; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t r = roots[i];
+        const uint32_t np = op[r + 1] - op[r];
+        if (np >= minp) atomicAdd(&h[min(np, kPHistCap - 1)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kPHistCap; b += blockDim.x)
+        if (h[b]) atomicAdd(&hist[b], h[b]);
+}
 
 __global__ void k_score_flags(const uint32_t* __restrict__ roots, uint32_t n, const uint32_t* __restrict__ op,
                               uint32_t minp, uint32_t* __restrict__ flag)
@@ -838,15 +862,36 @@ mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st
     if (!nroots) return MCE_OK;
     size_t nn = nroots;
     uint32_t* roots = st.roots.as<uint32_t>();
-    // roots with at least kScoreMinP later neighbours are scored; the others
-    // (subtrees of at most 3^(kScoreMinP/3) leaves) follow in degeneracy order
+    // the roots with the most later neighbours (at least kScoreMinP; subtrees
+    // with fewer have at most 3^(kScoreMinP/3) leaves) are scored; the others
+    // follow in degeneracy order
     if ((rc = q.flag.alloc(nn * 4)) != MCE_OK) return rc;
     if ((rc = q.pos.alloc((nn + 1) * 4)) != MCE_OK) return rc;
     if ((rc = q.scan_tmp.alloc(scan_tmp_words(nn + 1) * 8 + 64)) != MCE_OK) return rc;
     if ((rc = q.total.alloc(8)) != MCE_OK) return rc;
     if ((rc = q.heavy.alloc(nn * 4)) != MCE_OK) return rc;
     if ((rc = q.light.alloc(nn * 4)) != MCE_OK) return rc;
-    k_score_flags<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(roots, nroots, g.op.as<uint32_t>(), kScoreMinP,
+    // the |P| threshold: the smallest t >= kScoreMinP with at most the budget of
+    // roots at or above it (ties at t all go in)
+    uint32_t minp = kScoreMinP;
+    {
+        const uint32_t cap = kPHistCap;  // bins 0 .. cap - 1
+        std::vector<uint32_t> hh(cap, 0u);
+        if ((rc = q.phist.alloc((size_t)cap * 4)) != MCE_OK) return rc;
+        fill_u32(q.phist.as<uint32_t>(), 0u, cap, s);
+        k_p_hist<<<blocks_for(nn, 256, 512), 256, 0, s>>>(roots, nroots, g.op.as<uint32_t>(), kScoreMinP,
+                                                          q.phist.as<uint32_t>());
+        MCE_HIP_TRY(hipGetLastError());
+        MCE_HIP_TRY(hipMemcpyAsync(hh.data(), q.phist.p, (size_t)cap * 4, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        const uint64_t budget = (uint64_t)kScoreBudget * std::max(grid, 1u);
+        uint64_t above = 0;
+        uint32_t t = cap;  // count of bins t .. cap - 1 is `above`
+        while (t > kScoreMinP && above + hh[t - 1] <= budget) above += hh[--t];
+        minp = std::max(kScoreMinP, t == cap ? cap - 1 : t);
+    }
+    q.min_p = minp;
+    k_score_flags<<<blocks_for(nn, 256, 8192), 256, 0, s>>>(roots, nroots, g.op.as<uint32_t>(), minp,
                                                             q.flag.as<uint32_t>());
     MCE_HIP_TRY(hipGetLastError());
     if ((rc = exclusive_scan_u32(q.flag.as<uint32_t>(), q.pos.as<uint32_t>(), nn, q.total.as<uint32_t>(),

@@ -179,10 +179,10 @@ struct EnumOutput {
 // Work queue built from the learned model.
 struct LearnedQueue {
     DevBuf feat, score, keys, sorted, roots, score_sorted, groups, pos, gpos, scan_tmp, total, sroots, ssplits, psum;
-    DevBuf flag, heavy, light;
+    DevBuf flag, heavy, light, phist;
     const uint32_t* qroots = nullptr;
     const uint32_t* qsplits = nullptr;
-    uint32_t n = 0, len = 0, scored = 0;
+    uint32_t n = 0, len = 0, scored = 0, min_p = 0;
 };
 
 // One graph's enumeration state kept across calls (scratch sized to the graph).
