@@ -811,19 +811,53 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
             P &= ~bit;
             XP |= bit;
             const uint64_t kgc = kg + rl64(skey, bb) + kGamma;
+            // a maximal clique R + {vb} + the `extra` universe vertices e1, e2,
+            // with key sum plus |R| gamma kfull
+            auto emit = [&](uint64_t kfull, uint32_t extra, uint32_t e1, uint32_t e2) {
+                const uint32_t rsize = rs0 + depth + 1 + extra;
+                if (stream) {
+                    if (lane < depth) w.R()[rs0 + lane] = sV;
+                    if (lane == 0) {
+                        w.R()[rs0 + depth] = rl32(su, bb);
+                        if (extra > 0) w.R()[rs0 + depth + 1] = rl32(su, e1);
+                        if (extra > 1) w.R()[rs0 + depth + 2] = rl32(su, e2);
+                    }
+                    wave_mem_sync();
+                    report(p, w, rsize, kfull - (uint64_t)rsize * kGamma);
+                } else {
+                    lg.pre = wlane64(lg.pre, lg.n, kfull);
+                    lg.size = wlane32(lg.size, lg.n, rsize);
+                    if (++lg.n == 64) leaf_group_flush(p, w, lg);
+                }
+            };
             if (Pc == 0) {
                 ++nodes;
-                if ((XPc | XXc) == 0) {
-                    if (stream) {
-                        if (lane < depth) w.R()[rs0 + lane] = sV;
-                        if (lane == 0) w.R()[rs0 + depth] = rl32(su, bb);
-                        wave_mem_sync();
-                        const uint32_t rsize = rs0 + depth + 1;
-                        report(p, w, rsize, kgc - (uint64_t)rsize * kGamma);
+                if ((XPc | XXc) == 0) emit(kgc, 0, 0, 0);
+                continue;
+            }
+            const uint64_t Pc2 = Pc & (Pc - 1);  // the child's P without its first vertex
+            if ((Pc2 & (Pc2 - 1)) == 0) {
+                // the child's P has one or two vertices: it pivots on its first
+                // vertex a without scoring (any pivot in P u X is valid), and its
+                // subtree is finished here: with P = {a}, or P = {a, c} and a ~ c,
+                // the one branch a (then c); with a and c non-adjacent, the
+                // branches a and c, each a leaf
+                const uint32_t a = (uint32_t)__builtin_ctzll(Pc);
+                const uint64_t ra = rl64(rowP, a), xa = rl64(rowX, a);
+                const uint64_t ka = kgc + rl64(skey, a) + kGamma;
+                if (Pc2 == 0) {
+                    nodes += 2;
+                    if (((XPc & ra) | (XXc & xa)) == 0) emit(ka, 1, a, 0);
+                } else {
+                    const uint32_t c = (uint32_t)__builtin_ctzll(Pc2);
+                    const uint64_t rc = rl64(rowP, c), xc = rl64(rowX, c);
+                    const uint64_t kc = rl64(skey, c) + kGamma;
+                    nodes += 3;
+                    if ((ra >> c) & 1ull) {
+                        if (((XPc & ra & rc) | (XXc & xa & xc)) == 0) emit(ka + kc, 2, a, c);
                     } else {
-                        lg.pre = wlane64(lg.pre, lg.n, kgc);
-                        lg.size = wlane32(lg.size, lg.n, rs0 + depth + 1);
-                        if (++lg.n == 64) leaf_group_flush(p, w, lg);
+                        if (((XPc & ra) | (XXc & xa)) == 0) emit(ka, 1, a, 0);
+                        if (((XPc & rc) | (XXc & xc)) == 0) emit(kgc + kc, 1, c, 0);
                     }
                 }
                 continue;
@@ -1908,23 +1942,27 @@ __global__ void __launch_bounds__(64, 5) k_enumerate(Params p)
     flush_graph(p, w);
     uint32_t pl = wave_sum(S.probes[lane]);
     if (lane == 0) {
-        atomicAdd(&p.acc[2 + MCE_STAT_PROBES], (unsigned long long)pl);
-        atomicAdd(&p.acc[2 + MCE_STAT_ROOT_WORDS], (unsigned long long)S.stat[S_ROOTW]);
-        atomicAdd(&p.acc[2 + MCE_STAT_BUSY_NS], (unsigned long long)S.stat[S_BUSY]);
-        atomicMax(&p.acc[2 + MCE_STAT_MAX_TASK_NS], (unsigned long long)S.stat[S_MAXTASK]);
-        atomicAdd(&p.acc[2 + MCE_STAT_NODES], (unsigned long long)w.nodes);
-        atomicAdd(&p.acc[2 + MCE_STAT_DONATIONS], (unsigned long long)S.stat[S_DONATIONS]);
-        atomicAdd(&p.acc[2 + MCE_STAT_TASKS], (unsigned long long)S.stat[S_TASKS]);
-        atomicAdd(&p.acc[2 + MCE_STAT_XTESTS], (unsigned long long)S.stat[S_XTESTS]);
-        atomicAdd(&p.acc[2 + MCE_STAT_BUILD_EDGES], (unsigned long long)S.stat[S_EDGES]);
-        atomicAdd(&p.acc[2 + MCE_STAT_HBM_ROWS], (unsigned long long)S.stat[S_HBM]);
-        atomicAdd(&p.acc[2 + MCE_STAT_IDLE_NS], (unsigned long long)S.stat[S_IDLE]);
-        atomicAdd(&p.acc[2 + MCE_STAT_XROW_TASKS], (unsigned long long)S.stat[S_XROW]);
-        atomicAdd(&p.acc[2 + MCE_STAT_BUILD_TICKS], (unsigned long long)S.stat[S_BUILD]);
-        atomicAdd(&p.acc[2 + MCE_STAT_DONATE_NS], (unsigned long long)S.stat[S_DONATE]);
-        atomicAdd(&p.acc[2 + MCE_STAT_POP_FAILS], (unsigned long long)S.stat[S_POPFAIL]);
-        atomicAdd(&p.acc[2 + MCE_STAT_XCOL_WORDS], (unsigned long long)S.stat[S_XCOLW]);
-        atomicAdd(&p.acc[2 + MCE_STAT_FOLD_DONATIONS], (unsigned long long)S.stat[S_FOLDDON]);
+        // idle workgroups of a small launch have nothing to add: skip zero adds
+        auto add = [&](int k, unsigned long long v) {
+            if (v) atomicAdd(&p.acc[2 + k], v);
+        };
+        add(MCE_STAT_PROBES, (unsigned long long)pl);
+        add(MCE_STAT_ROOT_WORDS, (unsigned long long)S.stat[S_ROOTW]);
+        add(MCE_STAT_BUSY_NS, (unsigned long long)S.stat[S_BUSY]);
+        if (S.stat[S_MAXTASK]) atomicMax(&p.acc[2 + MCE_STAT_MAX_TASK_NS], (unsigned long long)S.stat[S_MAXTASK]);
+        add(MCE_STAT_NODES, (unsigned long long)w.nodes);
+        add(MCE_STAT_DONATIONS, (unsigned long long)S.stat[S_DONATIONS]);
+        add(MCE_STAT_TASKS, (unsigned long long)S.stat[S_TASKS]);
+        add(MCE_STAT_XTESTS, (unsigned long long)S.stat[S_XTESTS]);
+        add(MCE_STAT_BUILD_EDGES, (unsigned long long)S.stat[S_EDGES]);
+        add(MCE_STAT_HBM_ROWS, (unsigned long long)S.stat[S_HBM]);
+        add(MCE_STAT_IDLE_NS, (unsigned long long)S.stat[S_IDLE]);
+        add(MCE_STAT_XROW_TASKS, (unsigned long long)S.stat[S_XROW]);
+        add(MCE_STAT_BUILD_TICKS, (unsigned long long)S.stat[S_BUILD]);
+        add(MCE_STAT_DONATE_NS, (unsigned long long)S.stat[S_DONATE]);
+        add(MCE_STAT_POP_FAILS, (unsigned long long)S.stat[S_POPFAIL]);
+        add(MCE_STAT_XCOL_WORDS, (unsigned long long)S.stat[S_XCOLW]);
+        add(MCE_STAT_FOLD_DONATIONS, (unsigned long long)S.stat[S_FOLDDON]);
     }
 }
 
