@@ -101,7 +101,7 @@ struct Oriented {
     uint32_t max_out = 0, max_in = 0;
     uint64_t n_isolated = 0;
     bool peel_steps = false;  // in: run the peel as step kernels replayed from a graph
-    uint32_t peel_mode = 0;   // out: 1 = one cooperative launch, 2 = step kernels
+    uint32_t peel_mode = 0;   // out: 1 = one cooperative launch, 2 = step kernels, 3 = per member
     // rank space
     DevBuf op, oc;    // out CSR: later neighbours, sorted ascending by rank
     DevBuf ip, ic;    // in CSR: earlier neighbours (unsorted)
@@ -116,10 +116,11 @@ struct Oriented {
 // rp/ci are device pointers (input space).  validate: run the graph-rule checks.
 // gid_in / voff (device, optional): graph of each input vertex and first vertex
 // of each graph, for a batch loaded as one disjoint union (keys then use the
-// vertex id local to its graph).
+// vertex id local to its graph).  max_member_n: the largest member's vertex
+// count (a batch whose members are all small peels each member on its own).
 mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t nnz,
                             bool validate, hipStream_t s, Oriented& g, const uint32_t* gid_in = nullptr,
-                            const uint32_t* voff = nullptr, uint32_t ngraphs = 1);
+                            const uint32_t* voff = nullptr, uint32_t ngraphs = 1, uint32_t max_member_n = 0);
 
 // Build the union CSR of a batch on the device (host inputs) and preprocess it.
 mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, const uint64_t* row_off,

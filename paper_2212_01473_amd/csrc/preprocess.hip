@@ -621,6 +621,96 @@ __global__ void __launch_bounds__(256) k_peel_persistent(const uint32_t* __restr
     }
 }
 
+// ---- per-member peel of a batch -------------------------------------------------------
+// A batch loaded as one disjoint union peels every member graph on its own, one
+// workgroup per member, with the member's remaining degrees, marks and frontier
+// lists in LDS: the same synchronous rounds as above, but with each member's
+// own levels, so a member takes its own number of rounds (the union's shared
+// levels would make thousands of nearly empty rounds, each a grid-wide step).
+// Round numbers restart at 0 in every member; core numbers are the member's.
+// out[0] = largest number of rounds, out[1] = largest level.
+constexpr uint32_t kMemberPeelCap = 8192;  // vertices per member (degrees then fit below 2^13)
+
+__global__ void __launch_bounds__(512) k_peel_members(const uint32_t* __restrict__ rp,
+                                                      const uint32_t* __restrict__ ci,
+                                                      const uint32_t* __restrict__ voff, uint32_t ng,
+                                                      uint32_t* __restrict__ round, uint32_t* __restrict__ core,
+                                                      unsigned int* __restrict__ out)
+{
+    __shared__ uint32_t deg[kMemberPeelCap];
+    __shared__ uint8_t mark[kMemberPeelCap];
+    __shared__ uint16_t lst[2][kMemberPeelCap];
+    __shared__ uint32_t cnt[2];
+    __shared__ uint32_t red[16];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wv = tid >> 6, nw = blockDim.x >> 6;
+    for (uint32_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+        const uint32_t base = voff[gi], n = voff[gi + 1] - base;
+        if (n == 0) continue;
+        for (uint32_t i = tid; i < n; i += blockDim.x) {
+            deg[i] = rp[base + i + 1] - rp[base + i];
+            mark[i] = 0;
+        }
+        __syncthreads();
+        uint32_t k = 0, r = 0, removed = 0, ncur = 0, pc = 0;
+        while (removed < n) {
+            if (ncur == 0) {
+                // a new level: the smallest remaining degree, then every remaining
+                // vertex of degree <= k
+                uint32_t m = kUnset;
+                for (uint32_t i = tid; i < n; i += blockDim.x)
+                    if (!mark[i]) m = min(m, deg[i]);
+                for (int off = 32; off > 0; off >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, off));
+                if (lane == 0) red[wv] = m;
+                if (tid == 0) cnt[pc] = 0;
+                __syncthreads();
+                m = kUnset;
+                for (uint32_t w = 0; w < nw; ++w) m = min(m, red[w]);
+                k = max(k, m);
+                for (uint32_t i = tid; i < n; i += blockDim.x)
+                    if (!mark[i] && deg[i] <= k) {
+                        mark[i] = 1;
+                        lst[pc][atomicAdd(&cnt[pc], 1u)] = (uint16_t)i;
+                        round[base + i] = r;
+                        core[base + i] = k;
+                    }
+                __syncthreads();
+                ncur = cnt[pc];
+            }
+            // remove the frontier: a neighbour whose degree falls from k + 1 to k
+            // joins the next round (one wave per frontier vertex)
+            if (tid == 0) cnt[pc ^ 1u] = 0;
+            __syncthreads();
+            for (uint32_t f = wv; f < ncur; f += nw) {
+                const uint32_t v = lst[pc][f];
+                const uint32_t beg = rp[base + v], end = rp[base + v + 1];
+                for (uint32_t e = beg + lane; e < end; e += 64) {
+                    const uint32_t u = ci[e] - base;
+                    if (u < n && !mark[u]) {  // u >= n only in an unvalidated, invalid batch
+                        const uint32_t old = atomicSub(&deg[u], 1u);
+                        if (old == k + 1) {
+                            mark[u] = 1;
+                            lst[pc ^ 1u][atomicAdd(&cnt[pc ^ 1u], 1u)] = (uint16_t)u;
+                            round[base + u] = r + 1;
+                            core[base + u] = k;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            removed += ncur;
+            r += 1;
+            pc ^= 1u;
+            ncur = cnt[pc];
+            __syncthreads();  // every thread has read cnt[pc] before it is reset
+        }
+        if (tid == 0) {
+            atomicMax(&out[0], r);
+            atomicMax(&out[1], k);
+        }
+        __syncthreads();  // the LDS arrays are reused by the next member
+    }
+}
+
 // ---- orientation -------------------------------------------------------------------
 // rank[], core by rank, key by rank (key of the id local to the vertex's graph),
 // and the graph of each rank when a batch is loaded as one disjoint union.
@@ -961,7 +1051,7 @@ mce_status peel_single_launch(const uint32_t* rp, const uint32_t* ci, uint32_t n
 
 mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, uint64_t nnz,
                             bool validate, hipStream_t s, Oriented& g, const uint32_t* gid_in,
-                            const uint32_t* voff, uint32_t ngraphs)
+                            const uint32_t* voff, uint32_t ngraphs, uint32_t max_member_n)
 {
     mce_status st;
     g.n = n;
@@ -1089,7 +1179,25 @@ mce_status preprocess_graph(const uint32_t* rp, const uint32_t* ci, uint32_t n, 
     pb.big[1] = big_b.as<uint32_t>();
     bool peeled = n == 0;
     g.peel_mode = 0;
-    if (n && !g.peel_steps) {
+    if (n && !g.peel_steps && voff && ngraphs > 1 && max_member_n <= kMemberPeelCap) {
+        // a batch of small graphs: every member peels on its own, one workgroup each
+        int dev = 0, cus = 0;
+        MCE_HIP_TRY(hipGetDevice(&dev));
+        MCE_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        MCE_HIP_TRY(hipMemcpyAsync(dmisc + 16, hmisc_zero(), 8, hipMemcpyHostToDevice, s));
+        unsigned int* mout = reinterpret_cast<unsigned int*>(dmisc + 16);
+        k_peel_members<<<std::max(1u, std::min(ngraphs, 2u * (uint32_t)std::max(cus, 1))), 512, 0, s>>>(
+            rp, ci, voff, ngraphs, dround, dcore, mout);
+        MCE_HIP_TRY(hipGetLastError());
+        unsigned int hout[2] = {0, 0};
+        MCE_HIP_TRY(hipMemcpyAsync(hout, mout, 8, hipMemcpyDeviceToHost, s));
+        MCE_HIP_TRY(hipStreamSynchronize(s));
+        hs.r = hout[0];
+        hs.k = hout[1];
+        peeled = true;
+        g.peel_mode = 3;
+    }
+    if (!peeled && !g.peel_steps) {
         // one launch with grid barriers; falls back to the step kernels when the
         // device cannot run it (no cooperative launch, or a barrier timed out)
         if ((st = peel_single_launch(rp, ci, n, pb, deg.as<uint32_t>(), dround, dcore, s, hs, peeled)) != MCE_OK)
@@ -1447,7 +1555,8 @@ mce_status preprocess_batch(const uint32_t* rp_cat, const uint32_t* ci_cat, cons
         return MCE_ERR_INVALID_GRAPH;
     }
     st = preprocess_graph(urp.as<uint32_t>(), uci.as<uint32_t>(), (uint32_t)N, NNZ, validate, s, g,
-                          d_gid.as<uint32_t>(), d_voff.as<uint32_t>(), ng);
+                          d_gid.as<uint32_t>(), d_voff.as<uint32_t>(), ng,
+                          ng ? *std::max_element(nloc.begin(), nloc.end()) : 0u);
     if (st != MCE_OK) return st;
     for (uint32_t i = 0; i < ng; ++i) {
         g.meta[i].n = nloc[i];

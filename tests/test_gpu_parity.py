@@ -440,14 +440,17 @@ def test_batch_union_matches_per_graph_oracle(gpu_lib):
         res = gpu_lib.enumerate_batch(dg)
         info = [dg.info(i) for i in range(len(graphs))]
         core, rnd, order = dg.order_arrays(3)
+        assert dg.info().peel_mode == 3
     for i, (g, r) in enumerate(zip(graphs, res)):
         exp = oracle_result(g)
         assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist)), i
         assert info[i].n == g.n and info[i].degeneracy == exp.degeneracy
-    # core numbers of a member graph are its own (the union does not mix graphs)
-    c3, _, _ = oracle.sync_peel(graphs[3])
-    assert (core == c3).all()
-    assert sorted(order.tolist()) == list(range(graphs[3].n))
+    # every member peels on its own: its core numbers, rounds and order are those
+    # of the oracle's simulation of its own synchronous peel
+    c3, r3, _ = oracle.sync_peel(graphs[3])
+    o3, _ = oracle.sync_order(graphs[3])
+    assert (core == c3).all() and (rnd == r3).all()
+    assert order.tolist() == o3.tolist()
 
 
 def test_no_x_rows_variant(gpu_lib):
