@@ -134,7 +134,7 @@ mce_status mce_graph_copy_order(const mce_graph* g, uint32_t graph_idx, uint32_t
 /* ---- enumeration flags */
 #define MCE_F_WORKER_LIST   0x01u  /* donate branches to idle wavefronts (Section III-C) */
 #define MCE_F_LEARNED_ORDER 0x02u  /* order the roots with the most later neighbours (at least 16;
-                                      about 16 per workgroup at most) by descending cost predicted
+                                      about 8 per workgroup at most) by descending cost predicted
                                       by opt->model, then the rest in degeneracy order */
 #define MCE_F_SPLIT         0x04u  /* with LEARNED_ORDER: split the costliest roots into groups of
                                       level-1 branches (group c of C takes branches t, t % C == c) */

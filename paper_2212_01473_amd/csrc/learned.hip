@@ -514,7 +514,7 @@ constexpr uint32_t kMaxSplit = 64;
 // most about kScoreBudget per workgroup of the launch (the roots with the most
 // later neighbours; the features cost grows with the number scored).
 constexpr uint32_t kScoreMinP = 16;
-constexpr uint32_t kScoreBudget = 16;
+constexpr uint32_t kScoreBudget = 8;
 constexpr uint32_t kPHistCap = 4097;  // |P| <= 4096 for any root the enumeration accepts
 
 // Histogram of |P| (later neighbours) over the queued roots with |P| >= minp,
