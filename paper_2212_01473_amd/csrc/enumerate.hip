@@ -132,6 +132,9 @@ struct Params {
 // from the constant cache) instead of keeping every field in scalar registers
 // for the whole persistent loop.
 typedef const __attribute__((address_space(4))) Params* ParamsK;
+// Only valid where inlined into the kernel: a called (outlined) function has no
+// kernel-argument pointer, so every function that reads the parameters through
+// it is force-inlined, and a build test checks that the kernel makes no calls.
 __device__ __forceinline__ const Params& kparams()
 {
     ParamsK k = (ParamsK)__builtin_amdgcn_kernarg_segment_ptr();
@@ -140,43 +143,43 @@ __device__ __forceinline__ const Params& kparams()
 }
 
 // ---------------------------------------------------------------- wave helpers
-__device__ inline uint32_t lane_id() { return __lane_id(); }
-__device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline uint64_t uni64(uint64_t v)
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
 {
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
-__device__ inline uint64_t rl64(uint64_t v, uint32_t l)
+__device__ __forceinline__ uint64_t rl64(uint64_t v, uint32_t l)
 {
     uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
     uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
     return ((uint64_t)hi << 32) | lo;
 }
-__device__ inline uint32_t rl32(uint32_t v, uint32_t l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t rl32(uint32_t v, uint32_t l) { return __builtin_amdgcn_readlane(v, l); }
 // Register stacks: lane d of a VGPR holds the value of DFS level d; a push
 // replaces lane l's value with the wave-uniform x.
-__device__ inline uint64_t wl64(uint64_t v, uint32_t l, uint64_t x) { return __lane_id() == l ? x : v; }
-__device__ inline uint32_t wl32(uint32_t v, uint32_t l, uint32_t x) { return __lane_id() == l ? x : v; }
-__device__ inline uint64_t shfl64(uint64_t v, uint32_t src)
+__device__ __forceinline__ uint64_t wl64(uint64_t v, uint32_t l, uint64_t x) { return __lane_id() == l ? x : v; }
+__device__ __forceinline__ uint32_t wl32(uint32_t v, uint32_t l, uint32_t x) { return __lane_id() == l ? x : v; }
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src)
 {
     uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, 64);
     uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src, 64);
     return ((uint64_t)hi << 32) | lo;
 }
-__device__ inline uint32_t prefix_popc(uint64_t m)
+__device__ __forceinline__ uint32_t prefix_popc(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 // Row rotation through DPP (row_ror:N within rows of 16 lanes).
 template <int N>
-__device__ inline uint32_t row_ror(uint32_t v)
+__device__ __forceinline__ uint32_t row_ror(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x120 + N, 0xF, 0xF, false);
 }
 // Wave-wide sum / max without LDS round trips (see wave_max).
-__device__ inline uint32_t wave_sum(uint32_t v)
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
     v += row_ror<1>(v);
     v += row_ror<2>(v);
@@ -189,7 +192,7 @@ __device__ inline uint32_t wave_sum(uint32_t v)
 // Wave-wide maximum: DPP rotations give every lane its 16-lane row's maximum;
 // two row broadcasts (lane 15 into row 1, lane 47 into row 3, then lane 31 into
 // rows 2 and 3) leave the maximum of all four rows in lane 63.
-__device__ inline uint32_t wave_max(uint32_t v)
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
     v = max(v, row_ror<1>(v));
     v = max(v, row_ror<2>(v));
@@ -199,7 +202,7 @@ __device__ inline uint32_t wave_max(uint32_t v)
     v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
     return __builtin_amdgcn_readlane(v, 63);
 }
-__device__ inline uint32_t wave_excl_scan(uint32_t v)
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v)
 {
     uint32_t x = v;
     for (int off = 1; off < 64; off <<= 1) {
@@ -209,14 +212,14 @@ __device__ inline uint32_t wave_excl_scan(uint32_t v)
     return x - v;
 }
 // Cross-lane visibility of global/LDS stores within the single-wave workgroup.
-__device__ inline void wave_mem_sync()
+__device__ __forceinline__ void wave_mem_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_s_barrier();
 }
-__device__ inline uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
-__device__ inline uint64_t fmix64(uint64_t z)
+__device__ __forceinline__ uint64_t fmix64(uint64_t z)
 {
     // SplitMix64 output finaliser (Steele, Lea and Flood, OOPSLA 2014).
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -224,7 +227,7 @@ __device__ inline uint64_t fmix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-__device__ inline uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
+__device__ __forceinline__ uint64_t low_mask(uint32_t n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
 
 // ---------------------------------------------------------------- per-workgroup state
 // Statistics counters kept in LDS (updated by lane 0) to spare scalar registers.
@@ -246,7 +249,7 @@ struct LdsFixed {
 __shared__ LdsFixed S;
 
 // LDS atomics without return: no wait on the search's critical path
-__device__ inline void stat_add(int k, uint64_t v)
+__device__ __forceinline__ void stat_add(int k, uint64_t v)
 {
     if (__lane_id() == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&S.stat[k]), (unsigned long long)v);
 }
@@ -308,7 +311,7 @@ struct Wg {
 __shared__ Wg SW;
 
 // Is b among the later neighbours of x?  (x precedes b in the order.)
-__device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b)
+__device__ __forceinline__ bool has_later(const Params& p, uint32_t x, uint32_t b)
 {
     uint32_t lo = p.op[x], hi = p.op[x + 1], probes = 0;
     bool found = false;
@@ -329,7 +332,7 @@ __device__ inline bool has_later(const Params& p, uint32_t x, uint32_t b)
 
 // Adjacency of X_X entry j (index into xr) to the universe vertex with index
 // bidx and rank brank.
-__device__ inline bool xtest(const Params& p, Wg& w, uint32_t j, uint32_t bidx, uint32_t brank)
+__device__ __forceinline__ bool xtest(const Params& p, Wg& w, uint32_t j, uint32_t bidx, uint32_t brank)
 {
     if (w.have_xrows) return (w.xrows()[(uint64_t)j * w.W + (bidx >> 6)] >> (bidx & 63)) & 1ull;
     return has_later(p, w.xr()[j], brank);
@@ -418,7 +421,7 @@ __device__ __forceinline__ void flush_graph(const Params& p_arg, Wg& w)
     w.hmax = 0;
 }
 
-__device__ void report(const Params& p_arg, Wg& w, uint32_t rsize, uint64_t ks)
+__device__ __forceinline__ void report(const Params& p_arg, Wg& w, uint32_t rsize, uint64_t ks)
 {
     const Params& p = kparams();
     (void)p_arg;
@@ -455,7 +458,7 @@ __device__ void report(const Params& p_arg, Wg& w, uint32_t rsize, uint64_t ks)
     if (w.count > (1ull << 30)) flush_graph(p, w);
 }
 
-__device__ inline bool check_deadline(const Params& p_arg, Wg& w)
+__device__ __forceinline__ bool check_deadline(const Params& p_arg, Wg& w)
 {
     const Params& p = kparams();
     (void)p_arg;
@@ -468,7 +471,7 @@ __device__ inline bool check_deadline(const Params& p_arg, Wg& w)
 }
 
 // ---------------------------------------------------------------- worker list
-__device__ inline Wg wg_view(const Params& p, uint32_t g)
+__device__ __forceinline__ Wg wg_view(const Params& p, uint32_t g)
 {
     (void)p;
     Wg w;
@@ -483,7 +486,7 @@ __device__ inline Wg wg_view(const Params& p, uint32_t g)
 // at different words and bits, so claims rarely collide.  The bitmap carries
 // no task data: all accesses are relaxed; the task is published with
 // release/acquire on the receiver's flag.
-__device__ uint32_t wl_try_pop(const Params& p_arg, Wg& w)
+__device__ __forceinline__ uint32_t wl_try_pop(const Params& p_arg, Wg& w)
 {
     const Params& p = kparams();
     (void)p_arg;
@@ -543,7 +546,7 @@ __device__ uint32_t wl_try_pop(const Params& p_arg, Wg& w)
 // branches with |P| >= donate_min_p, with unexplored siblings at this level and
 // unexplored branches at an earlier level.  The waiting count read here was
 // loaded at the previous check, so its latency overlaps the search.
-__device__ inline bool donation_wanted(const Params& p_arg, Wg& w, uint32_t np_child, bool more_here, bool anc,
+__device__ __forceinline__ bool donation_wanted(const Params& p_arg, Wg& w, uint32_t np_child, bool more_here, bool anc,
                                        uint32_t depth)
 {
     const Params& p = kparams();
@@ -562,7 +565,7 @@ __device__ inline bool donation_wanted(const Params& p_arg, Wg& w, uint32_t np_c
 // Finish a donation to r: R (this workgroup's R[0, rs) plus vb), header, one
 // release fence, then the flag.  The caller wrote the branch itself: the P,
 // X_P and X_X lists (kMboxLists) or a fold frame (kMboxFold).
-__device__ void publish_task(const Params& p_arg, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
+__device__ __forceinline__ void publish_task(const Params& p_arg, Wg& w, uint32_t r, uint32_t root, uint32_t rs, uint32_t vb,
                              uint64_t ks, uint32_t np, uint32_t nxp, uint32_t nxx, uint32_t kind)
 {
     const Params& p = kparams();
@@ -663,11 +666,11 @@ enum : uint32_t { kExDone = 0, kExFold = 1, kExList = 2, kExMid = 3 };
 // The compiler offers no builtin for it; the declaration binds the LLVM
 // intrinsic, so hazards are still handled by the backend.
 extern "C" __device__ int mce_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-__device__ inline uint32_t wlane32(uint32_t v, uint32_t l, uint32_t x)
+__device__ __forceinline__ uint32_t wlane32(uint32_t v, uint32_t l, uint32_t x)
 {
     return (uint32_t)mce_writelane_i32((int)x, (int)l, (int)v);
 }
-__device__ inline uint64_t wlane64(uint64_t v, uint32_t l, uint64_t x)
+__device__ __forceinline__ uint64_t wlane64(uint64_t v, uint32_t l, uint64_t x)
 {
     const uint32_t lo = wlane32((uint32_t)v, l, (uint32_t)x);
     const uint32_t hi = wlane32((uint32_t)(v >> 32), l, (uint32_t)(x >> 32));
@@ -1457,7 +1460,7 @@ __device__ __forceinline__ void scan_lists(const Params& p_arg, Wg& w, int mode,
 }
 
 // ---------------------------------------------------------------- tasks
-__device__ inline void begin_task(const Params& p_arg, Wg& w, uint32_t root)
+__device__ __forceinline__ void begin_task(const Params& p_arg, Wg& w, uint32_t root)
 {
     const Params& p = kparams();
     (void)p_arg;

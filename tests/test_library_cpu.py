@@ -165,3 +165,25 @@ def test_enumeration_kernel_resources():
         for name, v in res.items():
             if kernel in name:
                 assert v["scratchsize"] == 0, name
+
+
+def test_enumeration_kernel_makes_no_calls(tmp_path):
+    """The enumeration kernel's helpers read the kernel parameters through the
+    kernel-argument pointer, which only the kernel itself has: an outlined
+    (called) helper would read them from address zero.  Every such helper is
+    force-inlined; the device assembly must contain no call."""
+    import shutil
+    import subprocess
+
+    from paper_2212_01473_amd import build
+
+    if not os.path.exists(build.HIPCC):
+        pytest.skip("hipcc not available")
+    src = os.path.join(build.CSRC, "enumerate.hip")
+    out = tmp_path / "enumerate.s"
+    flags = [f for f in build.FLAGS if f not in ("-shared", "-fPIC", "-Rpass-analysis=kernel-resource-usage")]
+    subprocess.run([build.HIPCC, *flags, "--cuda-device-only", "-S", src, "-o", str(out)], check=True,
+                   capture_output=True, timeout=600)
+    text = out.read_text()
+    assert "s_swappc_b64" not in text and "s_setpc_b64" not in text
+    shutil.rmtree(tmp_path, ignore_errors=True)
