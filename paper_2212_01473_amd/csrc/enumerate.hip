@@ -782,7 +782,8 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
             ++nodes;
             const uint64_t cp = P | XP;
             uint32_t key = ((cp >> lane) & 1ull) ? (((uint32_t)__popcll(P & rowP) << 8) | (255u - lane)) : 0u;
-            const uint32_t kx = ((XX >> lane) & 1ull) ? (((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane)) : 0u;
+            // X_X is often empty deep in the tree: skip its scores then
+            const uint32_t kx = XX && ((XX >> lane) & 1ull) ? (((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane)) : 0u;
             const uint32_t best = wave_max(max(key, kx));
             const uint32_t idx = 255u - (best & 255u);
             const uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
@@ -810,7 +811,7 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
             const uint64_t rp = rl64(rowP, bb);
             const uint64_t Pc = P & rp;
             const uint64_t XPc = XP & rp;
-            const uint64_t XXc = XX & rl64(rowX, bb);
+            const uint64_t XXc = XX ? XX & rl64(rowX, bb) : 0ull;
             P &= ~bit;
             XP |= bit;
             const uint64_t kgc = kg + rl64(skey, bb) + kGamma;
@@ -846,14 +847,14 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                 // the one branch a (then c); with a and c non-adjacent, the
                 // branches a and c, each a leaf
                 const uint32_t a = (uint32_t)__builtin_ctzll(Pc);
-                const uint64_t ra = rl64(rowP, a), xa = rl64(rowX, a);
+                const uint64_t ra = rl64(rowP, a), xa = XXc ? rl64(rowX, a) : 0ull;
                 const uint64_t ka = kgc + rl64(skey, a) + kGamma;
                 if (Pc2 == 0) {
                     nodes += 2;
                     if (((XPc & ra) | (XXc & xa)) == 0) emit(ka, 1, a, 0);
                 } else {
                     const uint32_t c = (uint32_t)__builtin_ctzll(Pc2);
-                    const uint64_t rc = rl64(rowP, c), xc = rl64(rowX, c);
+                    const uint64_t rc = rl64(rowP, c), xc = XXc ? rl64(rowX, c) : 0ull;
                     const uint64_t kc = rl64(skey, c) + kGamma;
                     nodes += 3;
                     if ((ra >> c) & 1ull) {
