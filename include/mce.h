@@ -69,7 +69,9 @@ typedef struct {
     uint32_t max_in_degree;  /* largest |X| of a first-level subtree (<= Delta) */
     uint32_t n_graphs;       /* graphs in the handle (1 unless batch-loaded) */
     uint32_t peel_mode;      /* how the peel ran: 1 = one cooperative launch with grid
-                                barriers, 2 = step kernels replayed from a captured graph */
+                                barriers, 2 = step kernels replayed from a captured graph,
+                                3 = a batch whose member graphs each peeled on their own
+                                (one workgroup per member; members of at most 8192 vertices) */
 } mce_graph_info;
 
 /* ---- load flags */
