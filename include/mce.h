@@ -118,7 +118,11 @@ mce_status mce_load_csr_batch(const uint32_t* row_ptr_cat, const uint32_t* col_i
                               const uint64_t* row_off, const uint64_t* col_off,
                               uint32_t n_graphs, uint32_t flags, void* stream, mce_graph** out);
 
-/* Describe graph graph_idx of the handle (0 for a single graph). */
+/* Describe graph graph_idx of the handle (0 for a single graph), or with
+ * graph_idx = MCE_GRAPH_WHOLE the whole handle: for a batch, the disjoint union
+ * of its graphs (n and nnz summed, degrees and degeneracy the largest of any
+ * member), e.g. to size one histogram length that serves every member. */
+#define MCE_GRAPH_WHOLE 0xFFFFFFFFu
 mce_status mce_graph_get_info(const mce_graph* g, uint32_t graph_idx, mce_graph_info* out);
 
 /*

@@ -195,6 +195,20 @@ mce_status mce_graph_get_info(const mce_graph* g, uint32_t graph_idx, mce_graph_
 {
     if (!g || !out) return fail(MCE_ERR_INVALID_ARG, "NULL argument");
     const Oriented& o = *g->graphs[0];
+    if (graph_idx == MCE_GRAPH_WHOLE) {
+        // the whole handle: for a batch, its disjoint union
+        out->n = o.n;
+        out->nnz = o.nnz;
+        out->max_degree = o.max_degree;
+        out->degeneracy = o.degeneracy;
+        out->n_isolated = o.n_isolated;
+        out->peel_rounds = o.rounds;
+        out->max_out_degree = o.max_out;
+        out->max_in_degree = o.max_in;
+        out->n_graphs = o.ngraphs;
+        out->peel_mode = o.peel_mode;
+        return MCE_OK;
+    }
     if (graph_idx >= o.meta.size()) return fail(MCE_ERR_INVALID_ARG, "graph_idx out of range");
     fill_info(o, graph_idx, out);
     return MCE_OK;

@@ -8,6 +8,7 @@ library is missing, ``load_library`` raises.
 from __future__ import annotations
 
 import ctypes as C
+from collections.abc import Sequence
 import os
 from dataclasses import dataclass, field
 
@@ -34,6 +35,7 @@ MCE_LOAD_PEEL_STEPS = 0x4
 F_WORKER_LIST = 0x01
 F_LEARNED_ORDER = 0x02
 F_SPLIT = 0x04
+GRAPH_WHOLE = 0xFFFFFFFF
 F_STATS = 0x08
 F_STREAM = 0x10
 F_ROOT_STATS = 0x20
@@ -374,21 +376,57 @@ def enumerate_cliques(g: Graph, hist_len: int | None = None, options: Options | 
     return _to_result(r, hist, st)
 
 
-def enumerate_batch(g: Graph, options: Options | None = None, **kw):
+# numpy view of an array of mce_result (same layout as Result), so a batch's
+# results are marshalled without a Python loop over the graphs
+_RESULT_DTYPE = np.dtype({
+    "names": ["count", "hash", "max_clique_size", "hist_len", "hist", "stats"],
+    "formats": [np.uint64, np.uint64, np.uint32, np.uint32, np.uint64, (np.uint64, 24)],
+    "offsets": [Result.count.offset, Result.hash.offset, Result.max_clique_size.offset, Result.hist_len.offset,
+                Result.hist.offset, Result.stats.offset],
+    "itemsize": C.sizeof(Result)})
+
+
+class BatchResults(Sequence):
+    """The per-graph results of mce_enumerate_batch: graph i's EnumResult is
+    built when indexed; counts, hashes and the histogram matrix are arrays."""
+
+    def __init__(self, rec: np.ndarray, hist: np.ndarray, status: int):
+        self._rec, self._hist, self._status = rec, hist, status
+
+    def __len__(self) -> int:
+        return len(self._rec)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        r = self._rec[i]
+        top = int(r["max_clique_size"])
+        stats = {name: int(r["stats"][k]) for k, name in enumerate(STAT_NAMES)}
+        return EnumResult(count=int(r["count"]), hash=int(r["hash"]), hist=self._hist[i, : top + 1].copy(),
+                          max_size=top, stats=stats, status=self._status)
+
+    @property
+    def counts(self) -> np.ndarray:
+        return self._rec["count"].copy()
+
+    @property
+    def hashes(self) -> np.ndarray:
+        return self._rec["hash"].copy()
+
+
+def enumerate_batch(g: Graph, options: Options | None = None, **kw) -> BatchResults:
     lib = load_library()
-    ng = g.info().n_graphs
+    info = g.info(GRAPH_WHOLE)
+    ng = info.n_graphs
     opt = options if options is not None else make_options(**kw)
-    results = (Result * ng)()
-    hists = []
-    for i in range(ng):
-        hl = g.info(i).degeneracy + 2
-        h = np.zeros(hl, dtype=np.uint64)
-        hists.append(h)
-        results[i].hist_len = hl
-        results[i].hist = h.ctypes.data_as(C.POINTER(C.c_uint64))
-    st = lib.mce_enumerate_batch(g.handle, C.byref(opt), results, ng)
+    hl = info.degeneracy + 2  # the largest member degeneracy + 2 serves every member
+    hist = np.zeros((ng, hl), dtype=np.uint64)
+    rec = np.zeros(ng, dtype=_RESULT_DTYPE)
+    rec["hist_len"] = hl
+    rec["hist"] = hist.ctypes.data + np.arange(ng, dtype=np.uint64) * np.uint64(hl * 8)
+    st = lib.mce_enumerate_batch(g.handle, C.byref(opt), C.cast(rec.ctypes.data, C.POINTER(Result)), ng)
     _check(st, "mce_enumerate_batch")
-    return [_to_result(results[i], hists[i], st) for i in range(ng)]
+    return BatchResults(rec, hist, st)
 
 
 def autotune(g: Graph, passes: int = 1, repeats: int = 1, options: Options | None = None, **kw):

@@ -34,6 +34,8 @@ def test_header_constants_match_binding():
     assert m and int(m.group(1)) == mce.MCE_NOALLOC_MAX_SAMPLES
     m = re.search(r"#define MCE_MODEL_FLOATS (\d+)", text)
     assert m and int(m.group(1)) == mce.MODEL_FLOATS
+    m = re.search(r"#define MCE_GRAPH_WHOLE (0x[0-9A-Fa-f]+)u", text)
+    assert m and int(m.group(1), 16) == mce.GRAPH_WHOLE
 
 
 def test_struct_layout_matches_header(tmp_path):
