@@ -427,9 +427,37 @@ def test_batch_api(gpu_lib):
     graphs = [I.erdos_renyi(50 + 30 * i, 0.1 + 0.05 * i, i) for i in range(6)]
     with gpu_lib.load_batch(graphs) as dg:
         res = gpu_lib.enumerate_batch(dg)
+        whole = dg.info(gpu_lib.GRAPH_WHOLE)
+        members = [dg.info(i) for i in range(len(graphs))]
+    # the whole-handle info describes the union
+    assert whole.n_graphs == len(graphs) and whole.n == sum(g.n for g in graphs)
+    assert whole.nnz == sum(len(g.col_idx) for g in graphs)
+    assert whole.degeneracy == max(m.degeneracy for m in members)
+    assert whole.max_degree == max(m.max_degree for m in members)
+    exps = [oracle.mce(g) for g in graphs]
+    for g, r, exp in zip(graphs, res, exps):
+        assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
+    # the result sequence: length, slices, negative indices and the array views agree
+    assert len(res) == len(graphs)
+    assert [r.count for r in res[1:4]] == [e.count for e in exps[1:4]]
+    assert res[-1].hash == exps[-1].hash
+    assert res.counts.tolist() == [e.count for e in exps]
+    assert res.hashes.tolist() == [e.hash for e in exps]
+
+
+def test_batch_with_a_large_member_peels_as_one_union(gpu_lib):
+    # a member above the per-member peel's 8,192 vertices: the union peels as one
+    # graph, with the same per-graph results
+    graphs = [I.erdos_renyi(9000, 0.001, 3), I.complete_graph(12), I.erdos_renyi(200, 0.1, 4)]
+    with gpu_lib.load_batch(graphs) as dg:
+        res = gpu_lib.enumerate_batch(dg)
+        assert dg.info().peel_mode in (1, 2)
+        core, _, _ = dg.order_arrays(2)
     for g, r in zip(graphs, res):
         exp = oracle.mce(g)
         assert (r.count, r.hash, _hist_dict(r.hist)) == (exp.count, exp.hash, _hist_dict(exp.hist))
+    c2, _, _ = oracle.sync_peel(graphs[2])
+    assert (core == c2).all()
 
 
 def test_batch_union_matches_per_graph_oracle(gpu_lib):
