@@ -44,6 +44,7 @@ namespace {
 constexpr uint32_t kFlagIdle = 0u, kFlagTask = 1u, kFlagTerm = 2u;
 constexpr uint32_t kNoWorkgroup = 0xFFFFFFFFu;
 constexpr int kHistLds = 128;
+constexpr uint32_t kSixWaveRoots = 256;  // roots per workgroup above which six waves per SIMD run
 constexpr uint32_t kMaxUniverse = 4096;    // W <= 64 words per bitmap row
 
 // The counters that every workgroup updates with device-scope atomics each sit
@@ -1906,7 +1907,11 @@ __device__ __forceinline__ bool next_task(const Params& p_arg, Wg& w, bool& phas
     return false;
 }
 
-__global__ void __launch_bounds__(64, 5) k_enumerate(Params p)
+// Instantiated for five and six wavefronts per SIMD (launch bounds); the host
+// picks six when the queue holds many roots per workgroup (throughput-bound),
+// five otherwise (fewer spills, for launches whose time is a critical path).
+template <int kWaves>
+__global__ void __launch_bounds__(64, kWaves) k_enumerate(Params p)
 {
     const uint32_t lane = lane_id();
     const uint32_t me = blockIdx.x;
@@ -2207,50 +2212,82 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
         lds_cu <= 0)
         lds_cu = 160 * 1024;
-    hipFuncAttributes fa;
-    MCE_HIP_TRY(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_enumerate)));
-    const size_t lds_static = std::max<size_t>(fa.sharedSizeBytes, sizeof(LdsFixed) + sizeof(Wg));
-    // workgroups per CU that the registers allow, and that a workgroup's LDS
-    // allows: gfx950 allocates a workgroup's static plus dynamic LDS in
-    // 1280-byte granules (160 KiB = 128 granules), which the occupancy query
-    // does not model
-    int per_cu_regs = 0;
-    MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_regs, reinterpret_cast<const void*>(k_enumerate),
-                                                             64, 0));
-    if (per_cu_regs <= 0) per_cu_regs = 1;
     const size_t uarr_bytes = (size_t)((ucap + 3) & ~3u) * 4;
     auto rows_words = [](uint32_t cap) {
         const uint32_t ws = cap <= 64 ? 1u : (((cap + 63) / 64) | 1u);
         return (size_t)std::max(cap * ws, 64u);
     };
-    auto per_cu_lds = [&](size_t dyn) {
-        const size_t granule = 1280;
-        return (int)((size_t)lds_cu / ((lds_static + dyn + granule - 1) / granule * granule));
+    // Resident workgroups and LDS layout for one instantiation of the kernel:
+    // the workgroups per CU that the registers allow, and that a workgroup's
+    // LDS allows (gfx950 allocates a workgroup's static plus dynamic LDS in
+    // 1280-byte granules, 160 KiB = 128 granules, which the occupancy query
+    // does not model).  The LDS bitmap cap is the given one, else the largest
+    // up to the default that keeps the register-limited number resident.
+    struct Launch {
+        const void* fn;
+        size_t lds_static = 0, lds_bytes = 0;
+        uint32_t lds_cap = 0, G = 0;
     };
-    // LDS budget for bitmap rows (universes up to 64 always fit): the given
-    // cap, else the largest up to the default that keeps the register-limited
-    // number of workgroups resident
-    uint32_t lds_cap;
-    if (cfg.bitmap_max_p) {
-        lds_cap = std::max(64u, std::min(cfg.bitmap_max_p, std::max(ucap, 64u)));
-    } else {
-        lds_cap = std::max(64u, std::min(kDefaultBitmapMaxP, std::max(ucap, 64u)));
-        while (lds_cap > 64 && per_cu_lds(uarr_bytes + rows_words(lds_cap) * 8) < per_cu_regs)
-            lds_cap = std::max(64u, lds_cap - 8);
+    auto plan = [&](const void* fn, Launch& L) -> mce_status {
+        L.fn = fn;
+        hipFuncAttributes fa;
+        MCE_HIP_TRY(hipFuncGetAttributes(&fa, fn));
+        L.lds_static = std::max<size_t>(fa.sharedSizeBytes, sizeof(LdsFixed) + sizeof(Wg));
+        int per_cu_regs = 0;
+        MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_regs, fn, 64, 0));
+        if (per_cu_regs <= 0) per_cu_regs = 1;
+        auto per_cu_lds = [&](size_t dyn) {
+            const size_t granule = 1280;
+            return (int)((size_t)lds_cu / ((L.lds_static + dyn + granule - 1) / granule * granule));
+        };
+        if (cfg.bitmap_max_p) {
+            L.lds_cap = std::max(64u, std::min(cfg.bitmap_max_p, std::max(ucap, 64u)));
+        } else {
+            L.lds_cap = std::max(64u, std::min(kDefaultBitmapMaxP, std::max(ucap, 64u)));
+            while (L.lds_cap > 64 && per_cu_lds(uarr_bytes + rows_words(L.lds_cap) * 8) < per_cu_regs)
+                L.lds_cap = std::max(64u, L.lds_cap - 8);
+        }
+        L.lds_bytes = uarr_bytes + rows_words(L.lds_cap) * 8;  // dynamic part (uarr, then rows)
+        if (L.lds_bytes + L.lds_static > (size_t)lds_cu) {
+            set_error("LDS budget exceeded; lower bitmap_max_p");
+            return MCE_ERR_INVALID_ARG;
+        }
+        int per_cu = 0;
+        MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, L.lds_bytes));
+        per_cu = std::min(per_cu, per_cu_lds(L.lds_bytes));
+        if (per_cu <= 0) per_cu = 1;
+        if (cfg.wg_per_cu) per_cu = std::min<int>(per_cu, (int)cfg.wg_per_cu);
+        L.G = (uint32_t)(per_cu * cus);
+        if (L.G == 0) L.G = 1;
+        return MCE_OK;
+    };
+    Launch L5, L;
+    if ((rc = plan(reinterpret_cast<const void*>(k_enumerate<5>), L5)) != MCE_OK) return rc;
+
+    hipEvent_t e0, e1, e2;
+    MCE_HIP_TRY(hipEventCreate(&e0));
+    MCE_HIP_TRY(hipEventCreate(&e1));
+    MCE_HIP_TRY(hipEventCreate(&e2));
+    MCE_HIP_TRY(hipEventRecord(e0, s));
+
+    // the queue in processing order (the learned form reorders it below)
+    uint32_t nroots = 0;
+    {
+        EnumConfig qcfg = cfg;
+        if (cfg.flags & MCE_F_LEARNED_ORDER) qcfg.flags &= ~(MCE_F_CUSTOM_ORDER | MCE_F_REVERSE_ORDER);
+        if ((rc = build_root_queue(g, qcfg, st, s, &nroots)) != MCE_OK) return rc;
     }
-    const size_t lds_bytes = uarr_bytes + rows_words(lds_cap) * 8;  // dynamic part (uarr, then rows)
-    if (lds_bytes + lds_static > (size_t)lds_cu) {
-        set_error("LDS budget exceeded; lower bitmap_max_p");
-        return MCE_ERR_INVALID_ARG;
+    // six wavefronts per SIMD when there are at least kSixWaveRoots roots per
+    // workgroup of the five-wavefront launch
+    L = L5;
+    if ((uint64_t)nroots >= (uint64_t)kSixWaveRoots * L5.G) {
+        Launch L6;
+        if ((rc = plan(reinterpret_cast<const void*>(k_enumerate<6>), L6)) != MCE_OK) return rc;
+        if (L6.G > L5.G) L = L6;
     }
-    int per_cu = 0;
-    MCE_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_enumerate), 64,
-                                                             lds_bytes));
-    per_cu = std::min(per_cu, per_cu_lds(lds_bytes));
-    if (per_cu <= 0) per_cu = 1;
-    if (cfg.wg_per_cu) per_cu = std::min<int>(per_cu, (int)cfg.wg_per_cu);
-    uint32_t G = (uint32_t)(per_cu * cus);
-    if (G == 0) G = 1;
+    const size_t lds_static = L.lds_static, lds_bytes = L.lds_bytes;
+    const uint32_t lds_cap = L.lds_cap;
+    uint32_t G = L.G;
 
     // per-workgroup scratch layout
     const uint64_t xrow_words = std::min<uint64_t>(cfg.xrow_budget_words, (uint64_t)xcap * wg_words);
@@ -2273,7 +2310,15 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     const uint64_t off_ukey = off; off = align_up(off + (uint64_t)ucap * 8, 256);
     const uint64_t off_susp = off; off = align_up(off + 64 * 4 * 8 + 64 * 3 * 4, 256);
     const uint64_t stride = off;
-    const uint64_t budget = 32ull << 30;
+    // per-workgroup scratch is sized by the largest in-degree (X lists), so a
+    // hub-heavy graph needs several MB per workgroup: allow up to a quarter of
+    // the free device memory (at least 32 GiB), and fewer workgroups beyond it
+    uint64_t budget = 32ull << 30;
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget = std::max<uint64_t>(budget, free_b / 4);
+        else (void)hipGetLastError();
+    }
     if ((uint64_t)G * stride > budget) G = (uint32_t)std::max<uint64_t>(1, budget / stride);
 
     if ((rc = st.scratch.alloc((size_t)G * stride)) != MCE_OK) return rc;
@@ -2285,12 +2330,6 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     if ((rc = st.idle.alloc((size_t)idle_words * kIdleStride * 8)) != MCE_OK) return rc;
     if ((rc = st.flags.alloc((size_t)G * 4)) != MCE_OK) return rc;
 
-    hipEvent_t e0, e1, e2;
-    MCE_HIP_TRY(hipEventCreate(&e0));
-    MCE_HIP_TRY(hipEventCreate(&e1));
-    MCE_HIP_TRY(hipEventCreate(&e2));
-    MCE_HIP_TRY(hipEventRecord(e0, s));
-
     // reset control state (fill kernels, no memset nodes)
     fill_u64(reinterpret_cast<uint64_t*>(st.ctrl.p), 0, sizeof(Ctrl) / 8, s);
     fill_u64(st.acc.as<uint64_t>(), 0, 32, s);
@@ -2299,21 +2338,17 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     fill_u64(st.idle.as<uint64_t>(), 0, (size_t)idle_words * kIdleStride, s);
     fill_u32(st.flags.as<uint32_t>(), kFlagIdle, G, s);
 
-    uint32_t nroots = 0;
-    const uint32_t* roots = nullptr;
+    const uint32_t* roots = st.roots.as<uint32_t>();
     const uint32_t* splits = nullptr;
     if (cfg.flags & MCE_F_LEARNED_ORDER) {
         if (!cfg.model) {
             set_error("MCE_F_LEARNED_ORDER without a model");
             return MCE_ERR_INVALID_ARG;
         }
-        if ((rc = learned_queue(g, cfg, st, s, G, st.lq)) != MCE_OK) return rc;
+        if ((rc = learned_queue(g, cfg, st, s, G, st.lq, nroots)) != MCE_OK) return rc;
         roots = st.lq.qroots;
         splits = st.lq.qsplits;
         nroots = st.lq.len;
-    } else {
-        if ((rc = build_root_queue(g, cfg, st, s, &nroots)) != MCE_OK) return rc;
-        roots = st.roots.as<uint32_t>();
     }
     const uint32_t* l2v = nullptr;
     const uint32_t* l2e = nullptr;
@@ -2431,7 +2466,10 @@ mce_status enumerate_graph(const Oriented& g, const EnumConfig& cfg, EnumState& 
     }
 
     if (nroots) {
-        k_enumerate<<<G, 64, lds_bytes, s>>>(p);
+        if (L.fn == reinterpret_cast<const void*>(k_enumerate<6>))
+            k_enumerate<6><<<G, 64, lds_bytes, s>>>(p);
+        else
+            k_enumerate<5><<<G, 64, lds_bytes, s>>>(p);
         MCE_HIP_TRY(hipGetLastError());
     }
     MCE_HIP_TRY(hipEventRecord(e2, s));

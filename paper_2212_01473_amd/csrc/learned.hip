@@ -851,13 +851,15 @@ mce_status model_train(float* model, const float* feat, const float* target, uin
 // Work queue from a model: window roots (rank order) -> features -> scores ->
 // stable descending sort -> optional split of the costliest roots.
 mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s, uint32_t grid,
-                         LearnedQueue& q)
+                         LearnedQueue& q, uint32_t built_n)
 {
     mce_status rc;
-    uint32_t nroots = 0;
-    EnumConfig plain = cfg;
-    plain.flags &= ~(MCE_F_CUSTOM_ORDER | MCE_F_REVERSE_ORDER);
-    if ((rc = build_root_queue(g, plain, st, s, &nroots)) != MCE_OK) return rc;
+    uint32_t nroots = built_n;
+    if (built_n == kQueueNotBuilt) {
+        EnumConfig plain = cfg;
+        plain.flags &= ~(MCE_F_CUSTOM_ORDER | MCE_F_REVERSE_ORDER);
+        if ((rc = build_root_queue(g, plain, st, s, &nroots)) != MCE_OK) return rc;
+    }
     q.n = nroots;
     if (!nroots) return MCE_OK;
     size_t nn = nroots;

@@ -216,7 +216,11 @@ mce_status model_loss_grad_noalloc(const float* model, const float* feat, const 
 mce_status model_fit_norm(float* model, const float* feat, uint32_t n, hipStream_t s);
 mce_status model_train(float* model, const float* feat, const float* target, uint32_t n, uint32_t epochs, float lr,
                        float b1, float b2, float eps, bool fit_norm, float* loss_hist, hipStream_t s);
+// The learned queue in st.lq.  built_n: the plain queue's length when
+// build_root_queue has already filled st.roots (degeneracy order, no custom or
+// reverse order), else kQueueNotBuilt.
+constexpr uint32_t kQueueNotBuilt = 0xFFFFFFFFu;
 mce_status learned_queue(const Oriented& g, const EnumConfig& cfg, EnumState& st, hipStream_t s, uint32_t grid,
-                         LearnedQueue& q);
+                         LearnedQueue& q, uint32_t built_n = kQueueNotBuilt);
 
 }  // namespace mce
