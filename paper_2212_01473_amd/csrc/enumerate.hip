@@ -750,7 +750,9 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
     const uint32_t m = uni(j.m), L = uni(j.L);
     const bool vx = lane < L;
     const uint32_t su = j.su;
-    const uint64_t skey = j.skey, rowP = j.rowP;
+    // per lane: the vertex key plus gamma, the increment of (key sum + |R| gamma)
+    // when that vertex joins R
+    const uint64_t skeyg = j.skey + kGamma, rowP = j.rowP;
     const uint32_t xrank = vx ? w.xr()[j.xj] : 0u;
     const uint64_t xrowP = L ? fold_xrow(w, vx, j.xj, j.oidx, m) : 0ull;
     uint64_t rowX = 0;
@@ -807,15 +809,15 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                 continue;
             }
             const uint32_t bb = (uint32_t)__builtin_ctzll(B);
-            B &= B - 1;
             const uint64_t bit = 1ull << bb;
+            B &= ~bit;
             const uint64_t rp = rl64(rowP, bb);
             const uint64_t Pc = P & rp;
             const uint64_t XPc = XP & rp;
             const uint64_t XXc = XX ? XX & rl64(rowX, bb) : 0ull;
             P &= ~bit;
             XP |= bit;
-            const uint64_t kgc = kg + rl64(skey, bb) + kGamma;
+            const uint64_t kgc = kg + rl64(skeyg, bb);
             // a maximal clique R + {vb} + the `extra` universe vertices e1, e2,
             // with key sum plus |R| gamma kfull
             auto emit = [&](uint64_t kfull, uint32_t extra, uint32_t e1, uint32_t e2) {
@@ -840,8 +842,8 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                 if ((XPc | XXc) == 0) emit(kgc, 0, 0, 0);
                 continue;
             }
-            const uint64_t Pc2 = Pc & (Pc - 1);  // the child's P without its first vertex
-            if ((Pc2 & (Pc2 - 1)) == 0) {
+            const uint32_t npc = (uint32_t)__popcll(Pc);
+            if (npc <= 2) {
                 // the child's P has one or two vertices: it pivots on its first
                 // vertex a without scoring (any pivot in P u X is valid), and its
                 // subtree is finished here: with P = {a}, or P = {a, c} and a ~ c,
@@ -849,14 +851,14 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                 // branches a and c, each a leaf
                 const uint32_t a = (uint32_t)__builtin_ctzll(Pc);
                 const uint64_t ra = rl64(rowP, a), xa = XXc ? rl64(rowX, a) : 0ull;
-                const uint64_t ka = kgc + rl64(skey, a) + kGamma;
-                if (Pc2 == 0) {
+                const uint64_t ka = kgc + rl64(skeyg, a);
+                if (npc == 1) {
                     nodes += 2;
                     if (((XPc & ra) | (XXc & xa)) == 0) emit(ka, 1, a, 0);
                 } else {
-                    const uint32_t c = (uint32_t)__builtin_ctzll(Pc2);
+                    const uint32_t c = (uint32_t)__builtin_ctzll(Pc & ~(1ull << a));
                     const uint64_t rc = rl64(rowP, c), xc = XXc ? rl64(rowX, c) : 0ull;
-                    const uint64_t kc = rl64(skey, c) + kGamma;
+                    const uint64_t kc = rl64(skeyg, c);
                     nodes += 3;
                     if ((ra >> c) & 1ull) {
                         if (((XPc & ra & rc) | (XXc & xa & xc)) == 0) emit(ka + kc, 2, a, c);
@@ -876,13 +878,12 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                 }
             }
             const uint32_t vb = rl32(su, bb);
-            const uint32_t npc = (uint32_t)__popcll(Pc);
             if (npc >= don_min && donation_wanted(p, w, npc, B != 0, anc0 || depth > 0, depth)) {
                 uint32_t r = wl_try_pop(p, w);
                 if (r != kNoWorkgroup) {
                     // the child keeps this universe and the members of X_X
                     Wg d = wg_view(p, r);
-                    put_fold_frame(d, m, Pc, XPc, su, skey, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc),
+                    put_fold_frame(d, m, Pc, XPc, su, skeyg - kGamma, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc),
                                    xrank, xrowP);
                     if (lane < depth) w.R()[rs0 + lane] = sV;
                     wave_mem_sync();
