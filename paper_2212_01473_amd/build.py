@@ -28,6 +28,15 @@ FLAGS = [
     "-Rpass-analysis=kernel-resource-usage",
 ]
 
+# Per-source additions.  The enumeration kernel's search loops branch on
+# wave-uniform values only; by default the compiler rewrites every loop into
+# structured, predicated control flow, which costs scalar moves and lane-mask
+# flag updates on each iteration.  This option leaves regions whose branches
+# are all uniform as they are.
+SOURCE_FLAGS = {
+    "enumerate.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+}
+
 RESOURCES = os.path.join(HERE, "_build", "kernel_resources.json")
 _REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|"
                      r"SGPRs Spill|VGPRs Spill|LDS Size \[bytes/block\]):\s+(\S+)")
@@ -57,7 +66,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", src, "-o", obj]
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *SOURCE_FLAGS.get(os.path.basename(src), []),
+               "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -554,10 +554,16 @@ __device__ __forceinline__ bool donation_wanted(const Params& p_arg, Wg& w, uint
     (void)p_arg;
     // w.don_min: donate_min_p, or ~0 without the worker list; almost every
     // branch stops at this one compare
-    if (__builtin_expect(np_child < w.don_min, 1)) return false;
+    // (fields kept in LDS are read through readfirstlane: the branches on them
+    // are then known to be wave-uniform)
+    if (__builtin_expect(np_child < uni(w.don_min), 1)) return false;
     if (!more_here || !anc) return false;
     if (p.donate_max_depth && depth > p.donate_max_depth) return false;
-    if (p.donate_every > 1 && (++w.wl_tick % p.donate_every) != 0) return false;
+    if (p.donate_every > 1) {
+        const uint32_t tick = uni(w.wl_tick) + 1;
+        w.wl_tick = tick;
+        if (tick % p.donate_every != 0) return false;
+    }
     uint32_t prev = w.wl_seen;
     w.wl_seen = __hip_atomic_load(&p.ctrl->waiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return uni(prev) != 0;
@@ -741,6 +747,16 @@ __device__ __forceinline__ void leaf_group_close(const Params& p_arg, Wg& w, Lea
 // The wave-uniform state of a level is P, X_P, X_X (bitmasks over the lanes),
 // the branches B still to visit and kg = (sum of keys of R) + |R| * gamma; the
 // stack keeps them in lane d of a VGPR for level d.
+//
+// The search loop holds wave-uniform branches only; whatever needs per-lane
+// control flow (hashing a full group of cliques, offering a branch to an idle
+// workgroup, the watchdog, the clique stream) leaves the loop with an event,
+// is handled below it, and the loop resumes where it stopped.  Wave-divergent
+// code inside the loop would make the compiler rewrite the loop's uniform
+// branches into predicated flow with state copies on every iteration.
+enum : uint32_t { kEvDone = 0, kEvLeaves = 1, kEvOffer = 2, kEvCheck = 3 };
+
+template <bool kStream>
 __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t root, const SmallJob& j)
 {
     const Params& p = kparams();
@@ -760,7 +776,6 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
         uint64_t wt = rl64(xrowP, t);
         if ((wt >> lane) & 1ull) rowX |= 1ull << t;
     }
-    const bool stream = (p.flags & MCE_F_STREAM) != 0;
     const uint32_t don_min = uni(w.don_min);
     const uint32_t rs0 = uni(j.rs);  // |R| at depth 0; |R| = rs0 + depth
     const bool anc0 = uni(j.anc ? 1u : 0u) != 0;
@@ -777,28 +792,57 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
     lg.size = 0;
     lg.n = 0;
     lg.hsum = 0;
-    bool at_node = true;
+    // the current child (branch vertex lane bb, vertex vb) and its sets
+    uint64_t Pc = 0, XPc = 0, XXc = 0, kgc = 0;
+    uint32_t bb = 0, vb = 0;
+    // clique-stream form: the cliques of one iteration (at most two), each as
+    // key sum plus |C| gamma, the number of universe vertices beyond vb and
+    // those vertices' lanes
+    uint32_t ne = 0, ex0 = 0, ea0 = 0, eb0 = 0, ex1 = 0, ea1 = 0;
+    uint64_t ek0 = 0, ek1 = 0;
+    // at_node: the pivot step is due; push: before it, descend into the
+    // current child
+    bool at_node = true, push = false;
     while (true) {
-        // ---- a node: Tomita pivot over P u X_P and the folded X_X
-        if (at_node) {
-            at_node = false;
-            ++nodes;
-            const uint64_t cp = P | XP;
-            uint32_t key = ((cp >> lane) & 1ull) ? (((uint32_t)__popcll(P & rowP) << 8) | (255u - lane)) : 0u;
-            // X_X is often empty deep in the tree: skip its scores then
-            const uint32_t kx = XX && ((XX >> lane) & 1ull) ? (((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane)) : 0u;
-            const uint32_t best = wave_max(max(key, kx));
-            const uint32_t idx = 255u - (best & 255u);
-            const uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
-            B = P & ~rowpiv;
-        }
-        // ---- its children, in ascending lane order; returns land here too
-        {
+        uint32_t ev;
+        while (true) {
+            if (at_node) {
+                if (nodes >= next_check) {
+                    ev = kEvCheck;
+                    break;
+                }
+                if (push) {
+                    push = false;
+                    sP = wlane64(sP, depth, P);
+                    sXP = wlane64(sXP, depth, XP);
+                    sXX = wlane64(sXX, depth, XX);
+                    sB = wlane64(sB, depth, B);
+                    sK = wlane64(sK, depth, kg);
+                    sV = wlane32(sV, depth, vb);
+                    ++depth;
+                    P = Pc;
+                    XP = XPc;
+                    XX = XXc;
+                    kg = kgc;
+                }
+                // ---- a node: Tomita pivot over P u X_P and the folded X_X
+                at_node = false;
+                ++nodes;
+                const uint64_t cp = P | XP;
+                uint32_t key = ((cp >> lane) & 1ull) ? (((uint32_t)__popcll(P & rowP) << 8) | (255u - lane)) : 0u;
+                // X_X is often empty deep in the tree: skip its scores then
+                const uint32_t kx =
+                    XX && ((XX >> lane) & 1ull) ? (((uint32_t)__popcll(P & xrowP) << 8) | (191u - lane)) : 0u;
+                const uint32_t best = wave_max(max(key, kx));
+                const uint32_t idx = 255u - (best & 255u);
+                const uint64_t rowpiv = idx < 64 ? rl64(rowP, idx) : rl64(xrowP, idx - 64);
+                B = P & ~rowpiv;
+            }
+            // ---- the node's children, in ascending lane order; returns land here too
             if (B == 0) {
                 if (depth == 0) {
-                    leaf_group_close(p, w, lg);
-                    w.nodes += nodes;
-                    return;
+                    ev = kEvDone;
+                    break;
                 }
                 --depth;
                 P = rl64(sP, depth);
@@ -808,42 +852,52 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                 kg = rl64(sK, depth);
                 continue;
             }
-            const uint32_t bb = (uint32_t)__builtin_ctzll(B);
+            bb = (uint32_t)__builtin_ctzll(B);
             const uint64_t bit = 1ull << bb;
             B &= ~bit;
             const uint64_t rp = rl64(rowP, bb);
-            const uint64_t Pc = P & rp;
-            const uint64_t XPc = XP & rp;
-            const uint64_t XXc = XX ? XX & rl64(rowX, bb) : 0ull;
+            Pc = P & rp;
+            XPc = XP & rp;
+            XXc = XX ? XX & rl64(rowX, bb) : 0ull;
             P &= ~bit;
             XP |= bit;
-            const uint64_t kgc = kg + rl64(skeyg, bb);
+            kgc = kg + rl64(skeyg, bb);
             // a maximal clique R + {vb} + the `extra` universe vertices e1, e2,
             // with key sum plus |R| gamma kfull
             auto emit = [&](uint64_t kfull, uint32_t extra, uint32_t e1, uint32_t e2) {
-                const uint32_t rsize = rs0 + depth + 1 + extra;
-                if (stream) {
-                    if (lane < depth) w.R()[rs0 + lane] = sV;
-                    if (lane == 0) {
-                        w.R()[rs0 + depth] = rl32(su, bb);
-                        if (extra > 0) w.R()[rs0 + depth + 1] = rl32(su, e1);
-                        if (extra > 1) w.R()[rs0 + depth + 2] = rl32(su, e2);
+                if (kStream) {
+                    if (ne == 0) {
+                        ek0 = kfull;
+                        ex0 = extra;
+                        ea0 = e1;
+                        eb0 = e2;
+                    } else {
+                        ek1 = kfull;
+                        ex1 = extra;
+                        ea1 = e1;
                     }
-                    wave_mem_sync();
-                    report(p, w, rsize, kfull - (uint64_t)rsize * kGamma);
+                    ++ne;
                 } else {
                     lg.pre = wlane64(lg.pre, lg.n, kfull);
-                    lg.size = wlane32(lg.size, lg.n, rsize);
-                    if (++lg.n == 64) leaf_group_flush(p, w, lg);
+                    lg.size = wlane32(lg.size, lg.n, rs0 + depth + 1 + extra);
+                    ++lg.n;
                 }
             };
             if (Pc == 0) {
                 ++nodes;
                 if ((XPc | XXc) == 0) emit(kgc, 0, 0, 0);
-                continue;
-            }
-            const uint32_t npc = (uint32_t)__popcll(Pc);
-            if (npc <= 2) {
+            } else {
+                // (readfirstlane keeps the small-P tests 32-bit scalar compares)
+                const uint32_t npc = uni((uint32_t)__popcll(Pc));
+                if (npc > 2) {
+                    vb = rl32(su, bb);
+                    if (npc >= don_min && donation_wanted(p, w, npc, B != 0, anc0 || depth > 0, depth)) {
+                        ev = kEvOffer;
+                        break;
+                    }
+                    at_node = push = true;
+                    continue;
+                }
                 // the child's P has one or two vertices: it pivots on its first
                 // vertex a without scoring (any pivot in P u X is valid), and its
                 // subtree is finished here: with P = {a}, or P = {a, c} and a ~ c,
@@ -867,45 +921,64 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
                         if (((XPc & rc) | (XXc & xc)) == 0) emit(kgc + kc, 1, c, 0);
                     }
                 }
-                continue;
             }
-            if (nodes >= next_check) {
-                next_check = nodes + 4096;
-                if (check_deadline(p, w)) {
-                    leaf_group_close(p, w, lg);
-                    w.nodes += nodes;
-                    return;
-                }
+            // an iteration adds at most two cliques: the group is hashed
+            // before it could overflow
+            if (kStream ? ne != 0 : lg.n >= 63) {
+                ev = kEvLeaves;
+                break;
             }
-            const uint32_t vb = rl32(su, bb);
-            if (npc >= don_min && donation_wanted(p, w, npc, B != 0, anc0 || depth > 0, depth)) {
-                uint32_t r = wl_try_pop(p, w);
-                if (r != kNoWorkgroup) {
-                    // the child keeps this universe and the members of X_X
-                    Wg d = wg_view(p, r);
-                    put_fold_frame(d, m, Pc, XPc, su, skeyg - kGamma, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc),
-                                   xrank, xrowP);
-                    if (lane < depth) w.R()[rs0 + lane] = sV;
+        }
+        // ---- events (wave-divergent work).  The event code is hidden from the
+        // optimiser, so the exits of the loop above meet in this one block
+        // rather than each being threaded to its own handler.
+        asm volatile("" : "+s"(ev));
+        if (ev == kEvDone) {
+            leaf_group_close(p, w, lg);
+            w.nodes += nodes;
+            return;
+        }
+        if (ev == kEvCheck) {
+            next_check = nodes + 4096;
+            if (check_deadline(p, w)) {
+                leaf_group_close(p, w, lg);
+                w.nodes += nodes;
+                return;
+            }
+        } else if (ev == kEvLeaves) {
+            if (kStream) {
+                if (lane < depth) w.R()[rs0 + lane] = sV;
+                for (uint32_t e = 0; e < ne; ++e) {
+                    const uint32_t extra = e ? ex1 : ex0;
+                    const uint32_t rsize = rs0 + depth + 1 + extra;
+                    if (lane == 0) {
+                        w.R()[rs0 + depth] = rl32(su, bb);
+                        if (extra > 0) w.R()[rs0 + depth + 1] = rl32(su, e ? ea1 : ea0);
+                        if (extra > 1) w.R()[rs0 + depth + 2] = rl32(su, eb0);
+                    }
                     wave_mem_sync();
-                    const uint32_t rs = rs0 + depth;
-                    publish_task(p, w, r, root, rs, vb, kgc - (uint64_t)(rs + 1) * kGamma, m, 0,
-                                 (uint32_t)__popcll(XXc), kMboxFold);
-                    continue;
+                    report(p, w, rsize, (e ? ek1 : ek0) - (uint64_t)rsize * kGamma);
                 }
+                ne = 0;
+            } else {
+                leaf_group_flush(p, w, lg);
             }
-            // descend
-            sP = wlane64(sP, depth, P);
-            sXP = wlane64(sXP, depth, XP);
-            sXX = wlane64(sXX, depth, XX);
-            sB = wlane64(sB, depth, B);
-            sK = wlane64(sK, depth, kg);
-            sV = wlane32(sV, depth, vb);
-            ++depth;
-            P = Pc;
-            XP = XPc;
-            XX = XXc;
-            kg = kgc;
-            at_node = true;
+        } else {
+            // kEvOffer: an idle workgroup takes the child, or it is descended into
+            const uint32_t r = wl_try_pop(p, w);
+            if (r != kNoWorkgroup) {
+                // the child keeps this universe and the members of X_X
+                Wg d = wg_view(p, r);
+                put_fold_frame(d, m, Pc, XPc, su, skeyg - kGamma, rowP, ((XXc >> lane) & 1ull) != 0, prefix_popc(XXc),
+                               xrank, xrowP);
+                if (lane < depth) w.R()[rs0 + lane] = sV;
+                wave_mem_sync();
+                const uint32_t rs = rs0 + depth;
+                publish_task(p, w, r, root, rs, vb, kgc - (uint64_t)(rs + 1) * kGamma, m, 0, (uint32_t)__popcll(XXc),
+                             kMboxFold);
+            } else {
+                at_node = push = true;
+            }
         }
     }
 }
@@ -1615,7 +1688,10 @@ __device__ __forceinline__ void run_task(const Params& p_arg, Wg& w, uint32_t ro
     }
     while (ex != kExDone && !w.abort) {
         if (ex == kExFold) {
-            run_folded(p, w, root, j);
+            if (p.flags & MCE_F_STREAM)
+                run_folded<true>(p, w, root, j);
+            else
+                run_folded<false>(p, w, root, j);
             ex = list_susp ? kExList : (mid_susp ? kExMid : kExDone);
         } else if (ex == kExList) {
             const uint32_t y = run_list(p, w, root, list_susp, j, lc, lC);

@@ -188,6 +188,7 @@ def test_enumeration_kernel_makes_no_calls(tmp_path):
     src = os.path.join(build.CSRC, "enumerate.hip")
     out = tmp_path / "enumerate.s"
     flags = [f for f in build.FLAGS if f not in ("-shared", "-fPIC", "-Rpass-analysis=kernel-resource-usage")]
+    flags += build.SOURCE_FLAGS.get("enumerate.hip", [])
     subprocess.run([build.HIPCC, *flags, "--cuda-device-only", "-S", src, "-o", str(out)], check=True,
                    capture_output=True, timeout=600)
     text = out.read_text()
