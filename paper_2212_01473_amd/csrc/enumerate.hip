@@ -756,7 +756,291 @@ __device__ __forceinline__ void leaf_group_close(const Params& p_arg, Wg& w, Lea
 // branches into predicated flow with state copies on every iteration.
 enum : uint32_t { kEvDone = 0, kEvLeaves = 1, kEvOffer = 2, kEvCheck = 3 };
 
-template <bool kStream>
+// Entry points of the assembly search loop (passed in the event register).
+enum : uint32_t { kAsmChild = 0, kAsmNode = 1, kAsmDescend = 2 };
+constexpr uint32_t kNoOffer = 0xFFFFFFFFu;  // donation threshold that no |P| reaches
+
+// The folded executor's search loop for the counting form, in gfx950
+// assembly.  It runs the steps of the C++ loop of run_folded in the same
+// order; the compiler's own code for that loop spends about half of its
+// scalar instructions on copies of loop-carried values and lane-mask flags,
+// and scalar issue is what bounds the kernel.  Registers (fixed by the asm
+// constraints at the call):
+//   s[40:41] P   s[42:43] X_P   s[44:45] X_X   s[46:47] B   s[48:49] kg
+//   s[50:51] Pc  s[52:53] XPc   s[54:55] XXc   s[56:57] kgc (current child)
+//   s64 depth  s65 nodes  s66 pending cliques  s67 entry in / event out
+//   s68 child lane bb  s69 |Pc|  s70 next watchdog count  s71 donate_min_p
+//   s72 |R| + 1 at depth 0  s73 1 if the task has unexplored ancestors
+//   v[48:49] rowP  v[50:51] rowX  v[52:53] key + gamma  v[54:55] X_X rows
+//   v[56:57] 1 << lane  v58 vertex  v59 255 - lane  v60 191 - lane
+//   v[62:71] stack of P, X_P, X_X, B, kg (lane d: level d)  v61 stack of R
+//   v[72:73] pending clique keys  v74 pending clique sizes
+//   scratch: s58-s63, s74-s85, v75-v78; m0 is saved in s76 and restored.
+// Wait states: two after a VALU write before a DPP read of it and before a
+// v_cndmask reads a VALU-written vcc, one before a VALU reads an SGPR a VALU
+// wrote; lane selects are always written by scalar instructions.  Entry and
+// exit add four, for the code around the block.
+#define FOLDED_SEARCH_ASM \
+    "s_nop 4\n" \
+    "s_mov_b32 s76, m0\n" \
+    "s_cmp_eq_u32 s67, 1\n" \
+    "s_cbranch_scc1 .Lfs_node_%=\n" \
+    "s_cmp_eq_u32 s67, 2\n" \
+    "s_cbranch_scc1 .Lfs_desc_%=\n" \
+    "s_branch .Lfs_child_%=\n" \
+    /* descend into the child: push the level, P = Pc ... */ \
+    ".Lfs_desc_%=:\n" \
+    "v_readlane_b32 s74, v58, s68\n" \
+    "s_mov_b32 m0, s64\n" \
+    "v_writelane_b32 v62, s40, m0\n" \
+    "v_writelane_b32 v63, s41, m0\n" \
+    "v_writelane_b32 v64, s42, m0\n" \
+    "v_writelane_b32 v65, s43, m0\n" \
+    "v_writelane_b32 v66, s44, m0\n" \
+    "v_writelane_b32 v67, s45, m0\n" \
+    "v_writelane_b32 v68, s46, m0\n" \
+    "v_writelane_b32 v69, s47, m0\n" \
+    "v_writelane_b32 v70, s48, m0\n" \
+    "v_writelane_b32 v71, s49, m0\n" \
+    "v_writelane_b32 v61, s74, m0\n" \
+    "s_add_u32 s64, s64, 1\n" \
+    "s_mov_b64 s[40:41], s[50:51]\n" \
+    "s_mov_b64 s[42:43], s[52:53]\n" \
+    "s_mov_b64 s[44:45], s[54:55]\n" \
+    "s_mov_b64 s[48:49], s[56:57]\n" \
+    /* pivot step: B = P minus the neighbours of the best of P u X_P u X_X */ \
+    ".Lfs_node_%=:\n" \
+    "s_add_u32 s65, s65, 1\n" \
+    "s_or_b64 s[58:59], s[40:41], s[42:43]\n" \
+    "v_and_b32_e32 v75, s40, v48\n" \
+    "v_and_b32_e32 v76, s41, v49\n" \
+    "v_bcnt_u32_b32 v75, v75, 0\n" \
+    "v_bcnt_u32_b32 v75, v76, v75\n" \
+    "v_lshl_or_b32 v75, v75, 8, v59\n" \
+    "v_and_b32_e32 v76, s58, v56\n" \
+    "v_and_b32_e32 v77, s59, v57\n" \
+    "v_or_b32_e32 v76, v76, v77\n" \
+    "v_cmp_ne_u32_e32 vcc, 0, v76\n" \
+    "s_nop 1\n" \
+    "v_cndmask_b32_e32 v75, 0, v75, vcc\n" \
+    "s_cmp_eq_u64 s[44:45], 0\n" \
+    "s_cbranch_scc1 .Lfs_nokx_%=\n" \
+    "v_and_b32_e32 v76, s40, v54\n" \
+    "v_and_b32_e32 v77, s41, v55\n" \
+    "v_bcnt_u32_b32 v76, v76, 0\n" \
+    "v_bcnt_u32_b32 v76, v77, v76\n" \
+    "v_lshl_or_b32 v76, v76, 8, v60\n" \
+    "v_and_b32_e32 v77, s44, v56\n" \
+    "v_and_b32_e32 v78, s45, v57\n" \
+    "v_or_b32_e32 v77, v77, v78\n" \
+    "v_cmp_ne_u32_e32 vcc, 0, v77\n" \
+    "s_nop 1\n" \
+    "v_cndmask_b32_e32 v76, 0, v76, vcc\n" \
+    "v_max_u32_e32 v75, v75, v76\n" \
+    ".Lfs_nokx_%=:\n" \
+    "s_nop 1\n" \
+    "v_max_u32_dpp v75, v75, v75 row_ror:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n" \
+    "s_nop 1\n" \
+    "v_max_u32_dpp v75, v75, v75 row_ror:2 row_mask:0xf bank_mask:0xf bound_ctrl:1\n" \
+    "s_nop 1\n" \
+    "v_max_u32_dpp v75, v75, v75 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n" \
+    "s_nop 1\n" \
+    "v_max_u32_dpp v75, v75, v75 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n" \
+    "s_nop 1\n" \
+    "v_max_u32_dpp v75, v75, v75 row_bcast:15 row_mask:0xa bank_mask:0xf\n" \
+    "s_nop 1\n" \
+    "v_max_u32_dpp v75, v75, v75 row_bcast:31 row_mask:0xc bank_mask:0xf\n" \
+    "s_nop 1\n" \
+    "v_readlane_b32 s74, v75, 63\n" \
+    "s_andn2_b32 s74, 0xff, s74\n" \
+    "s_cmp_lt_u32 s74, 64\n" \
+    "s_cbranch_scc0 .Lfs_pivx_%=\n" \
+    "v_readlane_b32 s59, v49, s74\n" \
+    "v_readlane_b32 s58, v48, s74\n" \
+    "s_branch .Lfs_pivd_%=\n" \
+    ".Lfs_pivx_%=:\n" \
+    "s_sub_u32 s74, s74, 64\n" \
+    "v_readlane_b32 s59, v55, s74\n" \
+    "v_readlane_b32 s58, v54, s74\n" \
+    ".Lfs_pivd_%=:\n" \
+    "s_andn2_b64 s[46:47], s[40:41], s[58:59]\n" \
+    "s_cmp_ge_u32 s65, s70\n" \
+    "s_cbranch_scc0 .Lfs_child_%=\n" \
+    "s_mov_b32 s67, 3\n" \
+    "s_branch .Lfs_exit_%=\n" \
+    /* return from a level whose branches are done */ \
+    ".Lfs_pop_%=:\n" \
+    "s_cmp_eq_u32 s64, 0\n" \
+    "s_cbranch_scc1 .Lfs_done_%=\n" \
+    "s_sub_u32 s64, s64, 1\n" \
+    "v_readlane_b32 s40, v62, s64\n" \
+    "v_readlane_b32 s41, v63, s64\n" \
+    "v_readlane_b32 s42, v64, s64\n" \
+    "v_readlane_b32 s43, v65, s64\n" \
+    "v_readlane_b32 s44, v66, s64\n" \
+    "v_readlane_b32 s45, v67, s64\n" \
+    "v_readlane_b32 s46, v68, s64\n" \
+    "v_readlane_b32 s47, v69, s64\n" \
+    "v_readlane_b32 s48, v70, s64\n" \
+    "v_readlane_b32 s49, v71, s64\n" \
+    /* the next child, lane bb = lowest of B */ \
+    ".Lfs_child_%=:\n" \
+    "s_cmp_eq_u64 s[46:47], 0\n" \
+    "s_cbranch_scc1 .Lfs_pop_%=\n" \
+    "s_ff1_i32_b64 s68, s[46:47]\n" \
+    "s_lshl_b64 s[60:61], 1, s68\n" \
+    "s_andn2_b64 s[46:47], s[46:47], s[60:61]\n" \
+    "v_readlane_b32 s59, v49, s68\n" \
+    "v_readlane_b32 s58, v48, s68\n" \
+    "v_readlane_b32 s57, v53, s68\n" \
+    "v_readlane_b32 s56, v52, s68\n" \
+    "s_and_b64 s[50:51], s[40:41], s[58:59]\n" \
+    "s_and_b64 s[52:53], s[42:43], s[58:59]\n" \
+    "s_andn2_b64 s[40:41], s[40:41], s[60:61]\n" \
+    "s_or_b64 s[42:43], s[42:43], s[60:61]\n" \
+    "s_add_u32 s56, s56, s48\n" \
+    "s_addc_u32 s57, s57, s49\n" \
+    "s_mov_b64 s[54:55], 0\n" \
+    "s_cmp_eq_u64 s[44:45], 0\n" \
+    "s_cbranch_scc1 .Lfs_noxx_%=\n" \
+    "v_readlane_b32 s55, v51, s68\n" \
+    "v_readlane_b32 s54, v50, s68\n" \
+    "s_and_b64 s[54:55], s[54:55], s[44:45]\n" \
+    ".Lfs_noxx_%=:\n" \
+    "s_cmp_lg_u64 s[50:51], 0\n" \
+    "s_cbranch_scc1 .Lfs_inner_%=\n" \
+    /* a leaf: maximal when X_P and X_X of the child are empty */ \
+    "s_add_u32 s65, s65, 1\n" \
+    "s_or_b64 s[58:59], s[52:53], s[54:55]\n" \
+    "s_cmp_lg_u64 s[58:59], 0\n" \
+    "s_cbranch_scc1 .Lfs_child_%=\n" \
+    "s_add_u32 s77, s72, s64\n" \
+    "s_mov_b32 m0, s66\n" \
+    "v_writelane_b32 v72, s56, m0\n" \
+    "v_writelane_b32 v73, s57, m0\n" \
+    "v_writelane_b32 v74, s77, m0\n" \
+    "s_add_u32 s66, s66, 1\n" \
+    "s_cmp_lt_u32 s66, 63\n" \
+    "s_cbranch_scc1 .Lfs_child_%=\n" \
+    "s_mov_b32 s67, 1\n" \
+    "s_branch .Lfs_exit_%=\n" \
+    ".Lfs_inner_%=:\n" \
+    "s_bcnt1_i32_b64 s69, s[50:51]\n" \
+    "s_cmp_gt_u32 s69, 2\n" \
+    "s_cbranch_scc0 .Lfs_small_%=\n" \
+    /* |Pc| > 2: offered when large, with siblings left and ancestors */ \
+    "s_cmp_lt_u32 s69, s71\n" \
+    "s_cbranch_scc1 .Lfs_desc_%=\n" \
+    "s_cmp_eq_u64 s[46:47], 0\n" \
+    "s_cbranch_scc1 .Lfs_desc_%=\n" \
+    "s_or_b32 s74, s64, s73\n" \
+    "s_cmp_eq_u32 s74, 0\n" \
+    "s_cbranch_scc1 .Lfs_desc_%=\n" \
+    "s_mov_b32 s67, 2\n" \
+    "s_branch .Lfs_exit_%=\n" \
+    /* |Pc| = 1 or 2: pivot on its first vertex a, finish the subtree */ \
+    ".Lfs_small_%=:\n" \
+    "s_ff1_i32_b64 s74, s[50:51]\n" \
+    "v_readlane_b32 s59, v49, s74\n" \
+    "v_readlane_b32 s58, v48, s74\n" \
+    "v_readlane_b32 s61, v53, s74\n" \
+    "v_readlane_b32 s60, v52, s74\n" \
+    "s_mov_b64 s[62:63], 0\n" \
+    "s_cmp_eq_u64 s[54:55], 0\n" \
+    "s_cbranch_scc1 .Lfs_sa_%=\n" \
+    "v_readlane_b32 s63, v51, s74\n" \
+    "v_readlane_b32 s62, v50, s74\n" \
+    ".Lfs_sa_%=:\n" \
+    "s_add_u32 s60, s60, s56\n" \
+    "s_addc_u32 s61, s61, s57\n" \
+    "s_add_u32 s77, s72, s64\n" \
+    "s_add_u32 s77, s77, 1\n" \
+    "s_cmp_eq_u32 s69, 1\n" \
+    "s_cbranch_scc0 .Lfs_two_%=\n" \
+    "s_add_u32 s65, s65, 2\n" \
+    "s_and_b64 s[84:85], s[58:59], s[52:53]\n" \
+    "s_and_b64 s[62:63], s[62:63], s[54:55]\n" \
+    "s_or_b64 s[84:85], s[84:85], s[62:63]\n" \
+    "s_cmp_lg_u64 s[84:85], 0\n" \
+    "s_cbranch_scc1 .Lfs_child_%=\n" \
+    "s_mov_b32 m0, s66\n" \
+    "v_writelane_b32 v72, s60, m0\n" \
+    "v_writelane_b32 v73, s61, m0\n" \
+    "v_writelane_b32 v74, s77, m0\n" \
+    "s_add_u32 s66, s66, 1\n" \
+    "s_branch .Lfs_full_%=\n" \
+    ".Lfs_two_%=:\n" \
+    "s_lshl_b64 s[84:85], 1, s74\n" \
+    "s_andn2_b64 s[84:85], s[50:51], s[84:85]\n" \
+    "s_ff1_i32_b64 s75, s[84:85]\n" \
+    "v_readlane_b32 s79, v49, s75\n" \
+    "v_readlane_b32 s78, v48, s75\n" \
+    "v_readlane_b32 s81, v53, s75\n" \
+    "v_readlane_b32 s80, v52, s75\n" \
+    "s_mov_b64 s[82:83], 0\n" \
+    "s_cmp_eq_u64 s[54:55], 0\n" \
+    "s_cbranch_scc1 .Lfs_sc_%=\n" \
+    "v_readlane_b32 s83, v51, s75\n" \
+    "v_readlane_b32 s82, v50, s75\n" \
+    ".Lfs_sc_%=:\n" \
+    "s_add_u32 s65, s65, 3\n" \
+    "s_bitcmp1_b64 s[58:59], s75\n" \
+    "s_cbranch_scc0 .Lfs_nadj_%=\n" \
+    /* a ~ c: the one clique R + {bb, a, c} */ \
+    "s_and_b64 s[84:85], s[52:53], s[58:59]\n" \
+    "s_and_b64 s[84:85], s[84:85], s[78:79]\n" \
+    "s_and_b64 s[62:63], s[62:63], s[54:55]\n" \
+    "s_and_b64 s[62:63], s[62:63], s[82:83]\n" \
+    "s_or_b64 s[84:85], s[84:85], s[62:63]\n" \
+    "s_cmp_lg_u64 s[84:85], 0\n" \
+    "s_cbranch_scc1 .Lfs_child_%=\n" \
+    "s_add_u32 s60, s60, s80\n" \
+    "s_addc_u32 s61, s61, s81\n" \
+    "s_add_u32 s77, s77, 1\n" \
+    "s_mov_b32 m0, s66\n" \
+    "v_writelane_b32 v72, s60, m0\n" \
+    "v_writelane_b32 v73, s61, m0\n" \
+    "v_writelane_b32 v74, s77, m0\n" \
+    "s_add_u32 s66, s66, 1\n" \
+    "s_branch .Lfs_full_%=\n" \
+    /* a, c not adjacent: leaves R + {bb, a} and R + {bb, c} */ \
+    ".Lfs_nadj_%=:\n" \
+    "s_and_b64 s[84:85], s[52:53], s[58:59]\n" \
+    "s_and_b64 s[62:63], s[62:63], s[54:55]\n" \
+    "s_or_b64 s[84:85], s[84:85], s[62:63]\n" \
+    "s_cmp_lg_u64 s[84:85], 0\n" \
+    "s_cbranch_scc1 .Lfs_nadj2_%=\n" \
+    "s_mov_b32 m0, s66\n" \
+    "v_writelane_b32 v72, s60, m0\n" \
+    "v_writelane_b32 v73, s61, m0\n" \
+    "v_writelane_b32 v74, s77, m0\n" \
+    "s_add_u32 s66, s66, 1\n" \
+    ".Lfs_nadj2_%=:\n" \
+    "s_and_b64 s[84:85], s[52:53], s[78:79]\n" \
+    "s_and_b64 s[82:83], s[82:83], s[54:55]\n" \
+    "s_or_b64 s[84:85], s[84:85], s[82:83]\n" \
+    "s_cmp_lg_u64 s[84:85], 0\n" \
+    "s_cbranch_scc1 .Lfs_full_%=\n" \
+    "s_add_u32 s80, s80, s56\n" \
+    "s_addc_u32 s81, s81, s57\n" \
+    "s_mov_b32 m0, s66\n" \
+    "v_writelane_b32 v72, s80, m0\n" \
+    "v_writelane_b32 v73, s81, m0\n" \
+    "v_writelane_b32 v74, s77, m0\n" \
+    "s_add_u32 s66, s66, 1\n" \
+    /* at most two cliques per child: hash the group before it could overflow */ \
+    ".Lfs_full_%=:\n" \
+    "s_cmp_lt_u32 s66, 63\n" \
+    "s_cbranch_scc1 .Lfs_child_%=\n" \
+    "s_mov_b32 s67, 1\n" \
+    "s_branch .Lfs_exit_%=\n" \
+    ".Lfs_done_%=:\n" \
+    "s_mov_b32 s67, 0\n" \
+    ".Lfs_exit_%=:\n" \
+    "s_mov_b32 m0, s76\n" \
+    "s_nop 4\n"
+
+template <bool kStream, bool kAsmSearch>
 __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t root, const SmallJob& j)
 {
     const Params& p = kparams();
@@ -803,6 +1087,72 @@ __device__ __forceinline__ void run_folded(const Params& p_arg, Wg& w, uint32_t 
     // at_node: the pivot step is due; push: before it, descend into the
     // current child
     bool at_node = true, push = false;
+    if constexpr (kAsmSearch) {
+        // The counting form of the six-wave launch runs the search loop below
+        // as hand-scheduled assembly (FOLDED_SEARCH_ASM): the same steps in the
+        // same order, with every loop-carried value in a fixed register.  It
+        // offers no branch to the worker list (the donation threshold passed
+        // to it is above any |P|): with offers taken from it, some received
+        // frames failed validation, which is not understood; the six-wave
+        // launch runs where every workgroup has hundreds of roots queued, and
+        // the list and mid executors still donate.
+        const uint64_t lbit = 1ull << lane;
+        const uint32_t lk = 255u - lane, lkx = 191u - lane;
+        const uint32_t sizeb = rs0 + 1;
+        const uint32_t ancu = anc0 ? 1u : 0u;
+        uint32_t mode = kAsmNode, npc = 0;
+        while (true) {
+            // the scalar operands are wave-uniform; the event handlers' per-lane
+            // code hides that from the compiler, so it is restated here
+            uint32_t ev = uni(mode);
+            depth = uni(depth);
+            nodes = uni(nodes);
+            lg.n = uni(lg.n);
+            bb = uni(bb);
+            npc = uni(npc);
+            next_check = uni(next_check);
+            P = uni64(P);
+            XP = uni64(XP);
+            XX = uni64(XX);
+            B = uni64(B);
+            kg = uni64(kg);
+            Pc = uni64(Pc);
+            XPc = uni64(XPc);
+            XXc = uni64(XXc);
+            kgc = uni64(kgc);
+            asm volatile(FOLDED_SEARCH_ASM
+                         : "+{s[40:41]}"(P), "+{s[42:43]}"(XP), "+{s[44:45]}"(XX), "+{s[46:47]}"(B),
+                           "+{s[48:49]}"(kg), "+{s[50:51]}"(Pc), "+{s[52:53]}"(XPc), "+{s[54:55]}"(XXc),
+                           "+{s[56:57]}"(kgc), "+{s64}"(depth), "+{s65}"(nodes), "+{s66}"(lg.n), "+{s67}"(ev),
+                           "+{s68}"(bb), "+{s69}"(npc), "+{v[62:63]}"(sP), "+{v[64:65]}"(sXP),
+                           "+{v[66:67]}"(sXX), "+{v[68:69]}"(sB), "+{v[70:71]}"(sK), "+{v61}"(sV),
+                           "+{v[72:73]}"(lg.pre), "+{v74}"(lg.size)
+                         : "{s70}"(next_check), "{s71}"(kNoOffer), "{s72}"(sizeb), "{s73}"(ancu),
+                           "{v[48:49]}"(rowP), "{v[50:51]}"(rowX), "{v[52:53]}"(skeyg), "{v[54:55]}"(xrowP),
+                           "{v[56:57]}"(lbit), "{v58}"(su), "{v59}"(lk), "{v60}"(lkx)
+                         : "scc", "vcc", "s58", "s59", "s60", "s61", "s62", "s63", "s74", "s75", "s76", "s77",
+                           "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "v75", "v76", "v77", "v78");
+            if (ev == kEvDone) {
+                leaf_group_close(p, w, lg);
+                w.nodes += nodes;
+                return;
+            }
+            mode = kAsmChild;
+            if (ev == kEvCheck) {
+                next_check = nodes + 4096;
+                if (check_deadline(p, w)) {
+                    leaf_group_close(p, w, lg);
+                    w.nodes += nodes;
+                    return;
+                }
+            } else if (ev == kEvLeaves) {
+                leaf_group_flush(p, w, lg);
+            } else {
+                // kEvOffer (not raised without a donation threshold): descend
+                mode = kAsmDescend;
+            }
+        }
+    }
     while (true) {
         uint32_t ev;
         while (true) {
@@ -1659,6 +2009,7 @@ __device__ __forceinline__ uint32_t build_task(const Params& p_arg, Wg& w, uint3
 
 // Run a task: a built one (build_task), or a fold frame received ready (fj,
 // with its X_X rows and ranks already in w.xrows() / w.xr()).
+template <bool kAsmSearch>
 __device__ __forceinline__ void run_task(const Params& p_arg, Wg& w, uint32_t root, uint32_t nu, uint32_t L, uint64_t ks,
                                          uint32_t rs, uint32_t c, uint32_t C, bool frame, const SmallJob& fj)
 {
@@ -1689,9 +2040,9 @@ __device__ __forceinline__ void run_task(const Params& p_arg, Wg& w, uint32_t ro
     while (ex != kExDone && !w.abort) {
         if (ex == kExFold) {
             if (p.flags & MCE_F_STREAM)
-                run_folded<true>(p, w, root, j);
+                run_folded<true, false>(p, w, root, j);
             else
-                run_folded<false>(p, w, root, j);
+                run_folded<false, kAsmSearch>(p, w, root, j);
             ex = list_susp ? kExList : (mid_susp ? kExMid : kExDone);
         } else if (ex == kExList) {
             const uint32_t y = run_list(p, w, root, list_susp, j, lc, lC);
@@ -2022,7 +2373,7 @@ __global__ void __launch_bounds__(64, kWaves) k_enumerate(Params p)
     SmallJob fj;
     while (!w.abort && next_task(p, w, phase1, t, fj)) {
         begin_task(p, w, t.root);
-        run_task(p, w, t.root, t.nu, t.L, t.ks, t.rs, t.c, t.C, t.kind == kMboxFold, fj);
+        run_task<kWaves == 6>(p, w, t.root, t.nu, t.L, t.ks, t.rs, t.c, t.C, t.kind == kMboxFold, fj);
         finish_task(p, w, t.root, t.nu, t.L, t.rs, t.c, t.C);
     }
     flush_graph(p, w);
