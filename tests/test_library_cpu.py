@@ -194,3 +194,38 @@ def test_enumeration_kernel_makes_no_calls(tmp_path):
     text = out.read_text()
     assert "s_swappc_b64" not in text and "s_setpc_b64" not in text
     shutil.rmtree(tmp_path, ignore_errors=True)
+
+
+def test_search_asm_registers_are_declared():
+    """The folded executor's assembly search loop may only touch registers its
+    asm statement names: operands (pinned with explicit register constraints)
+    or clobbers.  An undeclared register would silently corrupt a value the
+    compiler keeps there."""
+    from paper_2212_01473_amd import build
+
+    src = open(os.path.join(build.CSRC, "enumerate.hip")).read()
+    body = src[src.index("#define FOLDED_SEARCH_ASM"):]
+    body = body[:body.index('"s_nop 4\\n"', body.index(".Lfs_exit_")) + 12]
+    code = "".join(re.findall(r'"([^"]*)\\n"', body))
+
+    def expand(tok):
+        m = re.fullmatch(r"([sv])\[(\d+):(\d+)\]", tok)
+        if m:
+            return {f"{m.group(1)}{i}" for i in range(int(m.group(2)), int(m.group(3)) + 1)}
+        return {tok}
+
+    used = set()
+    for tok in re.findall(r"\b[sv]\[\d+:\d+\]|\b[sv]\d+\b", code):
+        used |= expand(tok)
+    stmt = src[src.index("asm volatile(FOLDED_SEARCH_ASM"):]
+    stmt = stmt[:stmt.index(");")]
+    declared = set()
+    for tok in re.findall(r'"\+?\{([sv]\[\d+:\d+\]|[sv]\d+)\}"', stmt):
+        declared |= expand(tok)
+    for tok in re.findall(r'"([sv]\d+)"', stmt):
+        declared |= expand(tok)
+    assert used, "no registers parsed from the assembly"
+    assert used <= declared, sorted(used - declared)
+    # m0 is saved and restored by the block itself, never declared
+    assert "s_mov_b32 s76, m0" in code and "s_mov_b32 m0, s76" in code
+    assert "s76" in declared
